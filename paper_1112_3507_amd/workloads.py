@@ -1,0 +1,124 @@
+"""Seeded synthetic inputs for the pressure solve (host, FP64, NumPy).
+
+This module only draws coefficient fields and right-hand sides; it contains none of the solver's
+arithmetic, so both the GPU path and the CPU oracle are fed from here.
+
+The fields stand in for the paper's workloads, which are not available: the stratified,
+convectively unstable polytropic layer of Section 5 ("Physical Setting": ideal gas with
+gamma = 5/3, polytropic index alpha = 1/(gamma - 1) = 1.5, linear temperature gradient), on the
+equidistant box with horizontally periodic and vertically closed boundaries, and the Mach-number
+ladder of the Gresho-vortex test (Ma = 0.1, 0.01, 0.001). Normalisation: T = 1 + 9 z (10x
+contrast), rho = T^1.5, c2 = T (all constants 1), and dt from an advective CFL of 1 with
+|u| = Ma * c_ref, c_ref = 1: dt = h / Ma, so dt^2 c^2 / h^2 = Ma^-2 at the cool end.
+
+Layout: arrays shaped (nz, ny, nx), C order, x fastest. Axis order of n/h/bc is (x, y, z).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+PERIODIC = 0
+NEUMANN = 1
+
+
+@dataclass
+class Problem:
+    name: str
+    n: tuple          # (nx, ny, nz)
+    h: tuple          # (hx, hy, hz)
+    bc: tuple         # (bcx, bcy, bcz)
+    rho: np.ndarray   # (nz, ny, nx) float64
+    c2: np.ndarray    # (nz, ny, nx) float64
+    dt: float
+
+    @property
+    def shape(self):
+        return (self.n[2], self.n[1], self.n[0])
+
+    @property
+    def ncells(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+
+def z_centres(nz: int, hz: float) -> np.ndarray:
+    return (np.arange(nz) + 0.5) * hz
+
+
+def exp_atmosphere_2d(nx: int = 64, nz: int = 64, courant2: float = 100.0) -> Problem:
+    """2D nx x 1 x nz on the unit box: rho = exp(-z / 0.5), c2 = 1, dt^2 c^2 / h^2 = courant2."""
+    h = 1.0 / nz
+    z = z_centres(nz, h)
+    rho = np.broadcast_to(np.exp(-z / 0.5)[:, None, None], (nz, 1, nx)).copy()
+    c2 = np.ones((nz, 1, nx))
+    dt = float(np.sqrt(courant2)) * h
+    return Problem("exp2d_%dx%d" % (nx, nz), (nx, 1, nz), (h, h, h), (PERIODIC, PERIODIC, NEUMANN),
+                   rho, c2, dt)
+
+
+def polytrope(n, mach: float, seed: int = 0, noise: float = 0.01, contrast: float = 10.0,
+              index: float = 1.5, h: float | None = None, mu=None) -> Problem:
+    """Stratified polytropic box, periodic in x and y, Neumann in z.
+
+    T = 1 + (contrast - 1) z, rho = T^index * mu * (1 + noise U), c2 = (T / mu) * (1 + noise U'),
+    U, U' independent uniform(-1, 1) per cell from NumPy PCG64 seeded with `seed`
+    (rho first, then c2). h defaults to 1 / nz on every axis; dt = h / mach.
+    `mu` (optional) is a function of z giving the mean molecular weight profile.
+    """
+    nx, ny, nz = (int(v) for v in n)
+    if h is None:
+        h = 1.0 / nz
+    z = z_centres(nz, h)
+    T = 1.0 + (contrast - 1.0) * z
+    muz = np.ones(nz) if mu is None else np.asarray(mu(z), dtype=np.float64)
+    rho_z = T ** index * muz
+    c2_z = T / muz
+    rho = np.broadcast_to(rho_z[:, None, None], (nz, ny, nx)).copy()
+    c2 = np.broadcast_to(c2_z[:, None, None], (nz, ny, nx)).copy()
+    if noise:
+        rng = np.random.default_rng(seed)
+        rho *= 1.0 + noise * rng.uniform(-1.0, 1.0, size=rho.shape)
+        c2 *= 1.0 + noise * rng.uniform(-1.0, 1.0, size=c2.shape)
+    dt = h / mach
+    tag = "polytrope_%dx%dx%d_Ma%g%s" % (nx, ny, nz, mach, "" if noise else "_smooth")
+    return Problem(tag, (nx, ny, nz), (h, h, h), (PERIODIC, PERIODIC, NEUMANN), rho, c2, dt)
+
+
+def rhs_white(n, seed: int) -> np.ndarray:
+    """N(0, 1) per cell (NumPy PCG64, `seed`), minus its mean."""
+    nx, ny, nz = (int(v) for v in n)
+    b = np.random.default_rng(seed).standard_normal((nz, ny, nx))
+    return b - b.mean()
+
+
+def rhs_modes_2d(nx: int, nz: int, seed: int, modes: int = 8) -> np.ndarray:
+    """Sum of `modes` terms a_j sin(2 pi kx_j x) cos(pi kz_j z) on cell centres of the unit box.
+
+    a_j ~ N(0, 1), kx_j uniform in {1..8}, kz_j uniform in {0..8} (NumPy PCG64, `seed`).
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(modes)
+    kx = rng.integers(1, 9, size=modes)
+    kz = rng.integers(0, 9, size=modes)
+    x = (np.arange(nx) + 0.5) / nx
+    z = (np.arange(nz) + 0.5) / nz
+    b = np.zeros((nz, 1, nx))
+    for j in range(modes):
+        b[:, 0, :] += a[j] * np.cos(np.pi * kz[j] * z)[:, None] * np.sin(2 * np.pi * kx[j] * x)[None, :]
+    return b
+
+
+def config0() -> Problem:
+    """2D 64 x 64, periodic x / Neumann z, rho = exp(-z/0.5), c2 = 1, dt^2 c^2 / h^2 = 100."""
+    return exp_atmosphere_2d(64, 64, 100.0)
+
+
+def config1(mach: float = 0.01, n: int = 256, seed: int = 0, noise: float = 0.01) -> Problem:
+    """256^3 polytrope, coefficient seed 0, Ma = 0.01 (dt = 100 h)."""
+    return polytrope((n, n, n), mach, seed=seed, noise=noise)
+
+
+def semiconvection_mu(z):
+    """Mean-molecular-weight step mu(z) = 1 + 0.1 tanh((z - 0.5) / 0.02)."""
+    return 1.0 + 0.1 * np.tanh((np.asarray(z) - 0.5) / 0.02)
