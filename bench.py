@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the implicit pressure solve on one MI355X.
+
+Workload (the benchmark line's `value`): the 256^3 stratified polytropic box (T = 1 + 9z,
+rho = T^1.5, c2 = T, +-1% multiplicative noise from seed 0, periodic x/y, Neumann z), Ma = 0.01
+(dt = 100 h), white-noise zero-mean right-hand sides with seeds 100, 101, ..., solved from a
+zero initial guess to true relative residual 1e-10 with FP64 multigrid-preconditioned CG.
+One step = one solve of a fresh right-hand side; inputs are resident in HBM before timing.
+
+Also reported on the same line: the Ma = 0.001 box with FP64 MG-PCG and with the mixed-precision
+form (speedup at the same accuracy), the roofline of the dominant kernel (measured with HIP
+events on the solver's stream), and the CPU oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pressure solves/s at 256³ to 1e-10 residual; FP64 MGPCG vs mixed/learned"
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-10
+
+# Algorithmic (compulsory) FP64 bytes per fine cell for one launch of each level-0 kernel:
+# every array the kernel must touch is counted once.
+ALG_BYTES = {
+    # q = A p with <p, q>: read p, rho, m; write q
+    "apply": 32.0,
+    # one red-black half sweep: read rho (all cells), r, m and the other colour's z (half the
+    # cells each), write this colour's z (half)
+    "rbgs_half_sweep": 24.0,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_rhs(n, seeds, dev):
+    import torch
+    from paper_1112_3507_amd import workloads as wl
+    return [torch.from_numpy(wl.rhs_white(n, s)).to(dev) for s in seeds]
+
+
+def run_solves(solver, rhs, x, warmup, steps):
+    """Warm up, then time `steps` solves (each from x = 0). Returns (seconds, stats list)."""
+    import torch
+    for k in range(warmup):
+        x.zero_()
+        solver.solve(rhs[k % len(rhs)], x, tol=TOL)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        x.zero_()
+        stats.append(solver.solve(rhs[warmup + k], x, tol=TOL))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats
+
+
+def kernel_time_ms(fn, reps=50):
+    """Average duration of one launch of fn() on the current stream, timed with HIP events."""
+    import torch
+    for _ in range(5):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def roofline(solver, n_cells, dev):
+    """Per-launch duration of the level-0 kernels; roofline of the dominant one."""
+    import torch
+    x = torch.randn(n_cells, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    r = torch.randn(n_cells, dtype=torch.float64, device=dev)
+    times = {
+        "apply": kernel_time_ms(lambda: solver.apply(0, x, y)),
+        "rbgs_half_sweep": kernel_time_ms(lambda: solver.smooth(0, r, x, 1)),
+    }
+    # launches per CG iteration on level 0: 2 operator applies (CG + residual before
+    # restriction), 3 half sweeps (+1 zero-guess sweep)
+    per_iter = {"apply": 2 * times["apply"], "rbgs_half_sweep": 3 * times["rbgs_half_sweep"]}
+    dom = max(per_iter, key=per_iter.get)
+    gbs = ALG_BYTES[dom] * n_cells / (times[dom] * 1e-3) / 1e9
+    kern = {k: {"ms": round(v, 5), "alg_bytes_per_cell": ALG_BYTES[k],
+                "achieved_GBs": round(ALG_BYTES[k] * n_cells / (v * 1e-3) / 1e9, 1)}
+            for k, v in times.items()}
+    return {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "per_launch_ms": round(times[dom], 5), "kernels": kern}
+
+
+def cpu_baseline(p, b, n, mach, budget_s=15.0):
+    """The FP64 oracle (CSR Jacobi-PCG) on the host cores, on a bounded sample of iterations.
+
+    The sample is scaled to solves/s by the iteration count of the oracle's full solve of the
+    same input, recorded by oracle/full_size_iterations.py.
+    """
+    import oracle
+    path = os.path.join(ROOT, "oracle", "full_size_iterations.json")
+    rows = json.load(open(path)) if os.path.exists(path) else []
+    full = [r["iterations"] for r in rows if r["n"] == n and r["mach"] == mach]
+    if not full:
+        return None
+    full_iterations = full[0]
+    A = oracle.assemble(p.n, p.h, p.bc, p.rho, p.c2, p.dt)
+    oracle.pcg_fixed(A, b, 2)
+    t0 = time.perf_counter()
+    oracle.pcg_fixed(A, b, 5)
+    per_it = (time.perf_counter() - t0) / 5
+    k = max(5, min(400, int(budget_s / max(per_it, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.pcg_fixed(A, b, k)
+    per_it = (time.perf_counter() - t0) / k
+    return {"value": 1.0 / (per_it * full_iterations), "unit": "solves/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "%d Jacobi-PCG iterations of the CPU oracle on the same 256^3 input "
+                      "(%.3f s/iteration), scaled by the %d iterations its full solve to 1e-10 "
+                      "takes" % (k, per_it, full_iterations)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-variants", action="store_true", help="skip the Ma=0.001 forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1112_3507_amd as hp
+    from paper_1112_3507_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = (args.n, args.n, args.n)
+    K, W = args.steps, args.warmup
+    seeds = list(range(100, 100 + W + K))
+
+    log("bench: generating %s inputs" % (n,))
+    p = wl.config1(mach=0.01, n=args.n)
+    rhs = make_rhs(n, seeds, dev)
+    x = torch.zeros(p.shape, dtype=torch.float64, device=dev)
+    rho, c2 = torch.from_numpy(p.rho).to(dev), torch.from_numpy(p.c2).to(dev)
+
+    log("bench: FP64 MG-PCG, Ma=0.01, %d warmup + %d timed solves" % (W, K))
+    solver = hp.setup(p.n, p.h, p.bc, rho, c2, p.dt, hp.MODE_FP64_MGPCG)
+    secs, stats = run_solves(solver, rhs, x, W, K)
+    value = K / secs
+    its = [s["iterations"] for s in stats]
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(1e3 * secs / K, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "polytrope %dx%dx%d Ma=0.01 FP64 MG-PCG, tol 1e-10 true relative "
+                               "residual, rho/c2 noise seed 0, rhs seeds %d-%d"
+                               % (args.n, args.n, args.n, seeds[W], seeds[-1]),
+                   "grid": list(n), "mach": 0.01, "tol": TOL, "mode": "fp64_mgpcg"},
+        "iterations_mean": sum(its) / len(its),
+        "max_rel_residual": max(s["rel_residual"] for s in stats),
+        "all_converged": all(s["converged"] for s in stats),
+    }
+    log("bench: %.2f solves/s, %.1f iterations/solve" % (value, result["iterations_mean"]))
+
+    if not args.no_roofline:
+        result["roofline"] = roofline(solver, p.ncells, dev)
+        log("bench: roofline %s" % json.dumps(result["roofline"]))
+    solver.close()
+
+    if not args.no_variants:
+        p3 = wl.config1(mach=0.001, n=args.n)
+        rho3, c23 = torch.from_numpy(p3.rho).to(dev), torch.from_numpy(p3.c2).to(dev)
+        var = {}
+        base = None
+        for name, mode in (("fp64_mgpcg", hp.MODE_FP64_MGPCG), ("mixed_ir", hp.MODE_MIXED_IR)):
+            log("bench: Ma=0.001 %s" % name)
+            s3 = hp.setup(p3.n, p3.h, p3.bc, rho3, c23, p3.dt, mode)
+            secs3, st3 = run_solves(s3, rhs, x, W, K)
+            s3.close()
+            v = K / secs3
+            var[name] = {"value": round(v, 3), "unit": "solves/s",
+                         "ms_per_step": round(1e3 * secs3 / K, 4),
+                         "iterations_mean": sum(s["iterations"] for s in st3) / K,
+                         "outer_mean": sum(s["outer_iterations"] for s in st3) / K,
+                         "max_rel_residual": max(s["rel_residual"] for s in st3),
+                         "all_converged": all(s["converged"] for s in st3)}
+            if base is None:
+                base = v
+            var[name]["speedup_vs_fp64_mgpcg"] = round(v / base, 3)
+        result["ma0.001"] = var
+        del rho3, c23
+
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        from paper_1112_3507_amd import workloads as wl2
+        b0 = wl2.rhs_white(n, seeds[W])
+        result["cpu_baseline"] = cpu_baseline(p, b0, args.n, 0.01)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

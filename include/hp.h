@@ -1,0 +1,191 @@
+/*
+ * hp.h -- C ABI of the MI355X (gfx950) pressure-solve library libhp.so.
+ *
+ * The library solves the per-timestep implicit pressure equation of the semi-implicit low-Mach
+ * scheme (paper, Section 2: eq. Poiss with the coefficients of eqs. cpoiss and kappapoiss,
+ * homogeneous Neumann boundary condition eq. vonNeumannBC, periodic horizontal boundaries as in
+ * Section 5), multiplied through by dt^2:
+ *
+ *     (1 / (rho c^2)) p - dt^2 div((1/rho) grad p) = rhs            (rhs = dt^2 f)
+ *
+ * on a cell-centred equidistant box. Discretely, with m_a = 1/(rho_a c2_a) and, for every face f
+ * between adjacent cells a and b along axis d, w_f = dt^2 * (2 / (rho_a + rho_b)) / h_d^2 (the
+ * face factor of the face-velocity update, step (viii) of the fractional-step algorithm):
+ *
+ *     (A p)_a = m_a p_a + sum_{f at a} w_f (p_a - p_b).
+ *
+ * A periodic axis with n >= 2 has a wrap face between cells 0 and n-1 (two faces when n = 2);
+ * a Neumann boundary face carries no flux; an axis with n = 1 has no faces. A is symmetric
+ * positive definite when rho, c2 > 0 (the Lax-Milgram conditions of Section 2).
+ *
+ * Layout of every cell array: FP64 (or FP32 where stated), nx*ny*nz entries,
+ * index = i + nx*(j + ny*k), x fastest. Pointers named "device" are HIP device pointers on the
+ * device that was current at hp_setup; the caller owns them. All work is ordered on the
+ * handle's stream (default: the null stream; see hp_set_stream).
+ *
+ * Errors: every int-returning call returns HP_OK (0) or a negative code below; a message is kept
+ * per thread (hp_last_error). A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef HP_H
+#define HP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hp_handle hp_handle;
+
+/* Grid: cells per axis and spacings (x, y, z). ny = 1 (or nx = 1) gives a 2D problem. */
+typedef struct {
+    int nx, ny, nz;
+    double hx, hy, hz;
+} hp_grid;
+
+/* Boundary kind per axis: HP_BC_PERIODIC or HP_BC_NEUMANN (homogeneous, eq. vonNeumannBC). */
+enum { HP_BC_PERIODIC = 0, HP_BC_NEUMANN = 1 };
+typedef struct {
+    int x, y, z;
+} hp_bc;
+
+/* Return codes. */
+enum {
+    HP_OK = 0,
+    HP_EINVAL = -1,      /* null pointer, n < 1, h <= 0, dt <= 0, tol <= 0, odd periodic n > 1,
+                            bad option key or value, level out of range */
+    HP_EDOMAIN = -2,     /* rho or c2 <= 0 or not finite (Lax-Milgram conditions violated) */
+    HP_ENOMEM = -3,      /* device or host allocation failed */
+    HP_EHIP = -4,        /* HIP runtime error (message kept) */
+    HP_ENAN = -5,        /* non-finite right-hand side or iterate */
+    HP_ENOCONV = -6,     /* iteration cap reached; p holds the last iterate, stats are filled */
+    HP_EBREAKDOWN = -7   /* p^T A p <= 0 in CG (cannot happen for valid SPD input) */
+};
+
+/* Solver modes (HP_OPT_MODE). */
+enum {
+    HP_MODE_JACOBI_PCG = 0,  /* FP64 CG with diagonal preconditioner */
+    HP_MODE_FP64_MGPCG = 1,  /* FP64 CG preconditioned by one geometric-multigrid V-cycle */
+    HP_MODE_MIXED_IR = 2     /* FP64 iterative refinement around an FP32 MG-PCG inner solve */
+};
+
+/* Option keys for hp_set_option / hp_get_option. */
+enum {
+    HP_OPT_MODE = 1,          /* one of HP_MODE_*; default HP_MODE_FP64_MGPCG */
+    HP_OPT_MAX_ITER = 2,      /* CG iteration cap (total inner iterations in MIXED_IR); 1000 */
+    HP_OPT_NU_PRE = 3,        /* red-black Gauss-Seidel pre-smoothing sweeps, 1..8; default 1 */
+    HP_OPT_NU_POST = 4,       /* post-smoothing sweeps, 1..8; default 1 */
+    HP_OPT_INNER_TOL = 5,     /* MIXED_IR: relative residual reduction per inner solve; 1e-5 */
+    HP_OPT_MAX_OUTER = 6,     /* MIXED_IR: refinement-step cap; default 20 */
+    HP_OPT_COARSEST_MAX = 7   /* read-only after setup: max cells of the coarsest level (512) */
+};
+
+/* Statistics of the last hp_solve. */
+typedef struct {
+    int iterations;        /* CG iterations (all inner iterations in MIXED_IR) */
+    int outer_iterations;  /* MIXED_IR refinement steps (0 otherwise) */
+    int converged;         /* 1 if the true relative residual met tol */
+    int restarts;          /* CG restarts from the true residual */
+    double rel_residual;   /* final true ||rhs - A p||_2 / ||rhs||_2, computed in FP64 */
+    double time_ms;        /* wall time of hp_solve on the stream (HIP events) */
+    int levels;            /* multigrid levels */
+    int status;            /* return code of the solve */
+    int fallback;          /* MIXED_IR: 1 if refinement stagnated and FP64 MG-PCG finished */
+} hp_stats;
+
+/*
+ * Build a solver for the operator A on `grid` with boundary kinds `bc`.
+ *   rho, c2  device FP64 cell arrays (density and squared sound speed); copied, so the caller may
+ *            reuse them on return.
+ *   dt       time step (> 0).
+ * Validates sizes (n >= 1, h > 0, periodic n even or 1), rho, c2 > 0 and finite. Allocates all
+ * device workspace (hp_solve allocates nothing), builds the multigrid hierarchy and factorises
+ * the coarsest operator in FP64 on the host. On success *out receives the handle.
+ */
+int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt,
+             const hp_bc* bc, hp_handle** out);
+
+/*
+ * Solve A p = rhs to the true relative residual ||rhs - A p||_2 <= tol ||rhs||_2.
+ *   rhs  device FP64, read only (the scaled right-hand side dt^2 f of eq. Poiss)
+ *   p    device FP64, in: initial guess (zeros, or the previous pressure as a warm start),
+ *        out: solution. rhs == 0 gives p = 0.
+ * Synchronises the handle's stream before returning (convergence is decided on the host).
+ * Returns HP_OK, HP_ENOCONV (p holds the last iterate), HP_ENAN, HP_EBREAKDOWN or HP_EHIP.
+ */
+int hp_solve(hp_handle* h, const double* rhs, double* p, double tol);
+
+/* Release everything owned by the handle. NULL-safe. */
+void hp_free(hp_handle* h);
+
+/* Use `stream` (a hipStream_t) for all later work of this handle. */
+int hp_set_stream(hp_handle* h, void* stream);
+
+int hp_set_option(hp_handle* h, int key, double value);
+int hp_get_option(const hp_handle* h, int key, double* value);
+
+/*
+ * Replace rho, c2 and dt (same grid): re-derives every level and the coarsest factor without
+ * reallocating. Same validation as hp_setup.
+ */
+int hp_update_coefficients(hp_handle* h, const double* rho, const double* c2, double dt);
+
+int hp_get_stats(const hp_handle* h, hp_stats* out);
+
+/* Thread-local message of the last error ("" if none). */
+const char* hp_last_error(void);
+
+/* ---- Building blocks of the solve, exposed for verification and composition ------------------
+ * Levels are numbered 0 (fine) .. hp_num_levels()-1 (coarsest). Vectors of level l are device
+ * arrays of that level's cell count; FP32 variants ("_f32") act on the FP32 copies of the
+ * coefficients used by the mixed-precision inner solve.
+ */
+
+int hp_num_levels(const hp_handle* h);
+
+/* Cells per axis (n[3]) and spacings (hs[3]) of level l; either pointer may be NULL. */
+int hp_level_info(const hp_handle* h, int level, int* n, double* hs);
+
+/* y = A_l x (flux form) on level l. */
+int hp_apply(hp_handle* h, int level, const double* x, double* y);
+int hp_apply_f32(hp_handle* h, int level, const float* x, float* y);
+
+/*
+ * One red-black Gauss-Seidel half sweep of colour `colour` (0 = red: (i+j+k) even) on level l:
+ * for every cell a of that colour z_a <- (r_a + sum_f w_f z_b) / (m_a + sum_f w_f).
+ * Cells of the other colour are left unchanged.
+ */
+int hp_smooth(hp_handle* h, int level, const double* r, double* z, int colour);
+int hp_smooth_f32(hp_handle* h, int level, const float* r, float* z, int colour);
+
+/*
+ * Residual restriction to level l+1: rc = R (r - A_l z), R = P^T / 2 per coarsened axis
+ * ((1,3,3,1)/8 interior weights; Neumann ends mirrored, periodic ends wrapped).
+ */
+int hp_restrict_residual(hp_handle* h, int level, const double* r, const double* z, double* rc);
+int hp_restrict_residual_f32(hp_handle* h, int level, const float* r, const float* z, float* rc);
+
+/* Trilinear prolongation and correction from level l+1: z += P ec (weights 3/4, 1/4 per axis). */
+int hp_prolong_add(hp_handle* h, int level, const double* ec, double* z);
+int hp_prolong_add_f32(hp_handle* h, int level, const float* ec, float* z);
+
+/* Coarsest-level solve x = A_c^-1 b in FP64 (FP32 variant converts in and out). */
+int hp_coarse_solve(hp_handle* h, const double* b, double* x);
+int hp_coarse_solve_f32(hp_handle* h, const float* b, float* x);
+
+/* One multigrid V-cycle z = M r on the fine level (the preconditioner of FP64_MGPCG). */
+int hp_precond(hp_handle* h, const double* r, double* z);
+int hp_precond_f32(hp_handle* h, const float* r, float* z);
+
+/*
+ * r = rhs - A p on the fine level in FP64; if rel is not NULL it receives
+ * ||r||_2 / ||rhs||_2 (synchronises the stream).
+ */
+int hp_residual(hp_handle* h, const double* rhs, const double* p, double* r, double* rel);
+
+/* Deterministic FP64 dot product of device vectors of n entries (synchronises the stream). */
+int hp_dot(hp_handle* h, const double* x, const double* y, long long n, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HP_H */

@@ -226,8 +226,9 @@ void or_residual_mf(const or_grid* g, const double* rho, const double* c2, doubl
  *   tol      stop when the true ||b - A x||_2 <= tol ||b||_2
  *   maxiter  iteration cap
  *   stag_window  if > 0: every stag_window iterations the true residual is recomputed; the solve
- *            stops (stagnated = 1) when it has not decreased by at least 10% since the previous
- *            check. This lets tol be set below the attainable accuracy (reference solutions).
+ *            stops (stagnated = 1) once the recursive residual has drifted 100x below it, or after
+ *            5 restarts, i.e. when the true residual has reached the accuracy FP64 attains for
+ *            this system. This lets tol be set below that level (reference solutions).
  *   alpha_out/beta_out  optional (may be NULL), capacity coef_cap: CG coefficients for a Lanczos
  *            estimate of the spectrum of D^-1 A.
  * Returns 0 on convergence or stagnation, 1 when maxiter was reached, -1 on breakdown
@@ -273,7 +274,6 @@ int or_pcg(int64_t N, const int64_t* rowptr, const int64_t* colind, const double
         status = 0;
         goto done;
     }
-    double last_check = rtrue;
     int restart = 1;
     double rz = 0.0;
     int it = 0;
@@ -312,16 +312,20 @@ int or_pcg(int64_t N, const int64_t* rowptr, const int64_t* colind, const double
                 status = 0;
                 break;
             }
-            if (stag_window > 0 && it % stag_window == 0) {
-                if (rtrue > 0.9 * last_check) {
+            if (stag_window > 0 && rrec < 1e-2 * rtrue) {
+                /* the recurrence has drifted far below the true residual: the true residual is
+                   at the accuracy FP64 can attain for this system */
+                st->stagnated = 1;
+                status = 0;
+                break;
+            }
+            if (rrec <= tol) {
+                /* recursive residual drifted from the true one: restart from the true residual */
+                if (stag_window > 0 && st->restarts >= 5) {
                     st->stagnated = 1;
                     status = 0;
                     break;
                 }
-                last_check = rtrue;
-            }
-            if (rrec <= tol) {
-                /* recursive residual drifted from the true one: restart from the true residual */
                 memcpy(r, q, (size_t)N * sizeof(double));
                 restart = 1;
                 st->restarts++;

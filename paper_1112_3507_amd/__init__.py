@@ -1,0 +1,274 @@
+"""MI355X (gfx950) implicit pressure solve for the semi-implicit low-Mach scheme.
+
+Thin ctypes binding over ``libhp.so`` (declared in ``include/hp.h``): it only checks and
+marshals arguments (torch device tensors -> device pointers, the current torch stream -> the
+handle's HIP stream); every step of the solve runs in the library's HIP kernels. There is no
+CPU fallback: if the library is not built, loading fails with an error.
+
+Arrays are cell-centred, shaped (nz, ny, nx) (or flat), x fastest, on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhp.so")
+
+PERIODIC, NEUMANN = 0, 1
+MODE_JACOBI_PCG, MODE_FP64_MGPCG, MODE_MIXED_IR = 0, 1, 2
+OPT_MODE, OPT_MAX_ITER, OPT_NU_PRE, OPT_NU_POST = 1, 2, 3, 4
+OPT_INNER_TOL, OPT_MAX_OUTER, OPT_COARSEST_MAX = 5, 6, 7
+
+OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENAN, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6, -7
+_CODE_NAMES = {EINVAL: "HP_EINVAL", EDOMAIN: "HP_EDOMAIN", ENOMEM: "HP_ENOMEM", EHIP: "HP_EHIP",
+               ENAN: "HP_ENAN", ENOCONV: "HP_ENOCONV", EBREAKDOWN: "HP_EBREAKDOWN"}
+
+# every symbol include/hp.h declares
+EXPORTS = [
+    "hp_setup", "hp_solve", "hp_free", "hp_set_stream", "hp_set_option", "hp_get_option",
+    "hp_update_coefficients", "hp_get_stats", "hp_last_error", "hp_num_levels", "hp_level_info",
+    "hp_apply", "hp_apply_f32", "hp_smooth", "hp_smooth_f32", "hp_restrict_residual",
+    "hp_restrict_residual_f32", "hp_prolong_add", "hp_prolong_add_f32", "hp_coarse_solve",
+    "hp_coarse_solve_f32", "hp_precond", "hp_precond_f32", "hp_residual", "hp_dot",
+]
+
+
+class HPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_CODE_NAMES.get(code, "HP_?"), code, msg))
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double)]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_int), ("y", ctypes.c_int), ("z", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
+                ("converged", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("levels", ctypes.c_int), ("status", ctypes.c_int), ("fallback", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhp.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise ImportError("libhp.so is not built (%s); run `python -m "
+                                  "paper_1112_3507_amd.build`" % path)
+            lib = ctypes.CDLL(path)
+            vp, dp, fp, ip = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int
+            H = ctypes.c_void_p
+            sig = {
+                "hp_setup": (ip, [ctypes.POINTER(Grid), dp, dp, ctypes.c_double,
+                                  ctypes.POINTER(BC), ctypes.POINTER(ctypes.c_void_p)]),
+                "hp_solve": (ip, [H, dp, dp, ctypes.c_double]),
+                "hp_free": (None, [H]),
+                "hp_set_stream": (ip, [H, vp]),
+                "hp_set_option": (ip, [H, ip, ctypes.c_double]),
+                "hp_get_option": (ip, [H, ip, ctypes.POINTER(ctypes.c_double)]),
+                "hp_update_coefficients": (ip, [H, dp, dp, ctypes.c_double]),
+                "hp_get_stats": (ip, [H, ctypes.POINTER(Stats)]),
+                "hp_last_error": (ctypes.c_char_p, []),
+                "hp_num_levels": (ip, [H]),
+                "hp_level_info": (ip, [H, ip, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double)]),
+                "hp_apply": (ip, [H, ip, dp, dp]),
+                "hp_apply_f32": (ip, [H, ip, fp, fp]),
+                "hp_smooth": (ip, [H, ip, dp, dp, ip]),
+                "hp_smooth_f32": (ip, [H, ip, fp, fp, ip]),
+                "hp_restrict_residual": (ip, [H, ip, dp, dp, dp]),
+                "hp_restrict_residual_f32": (ip, [H, ip, fp, fp, fp]),
+                "hp_prolong_add": (ip, [H, ip, dp, dp]),
+                "hp_prolong_add_f32": (ip, [H, ip, fp, fp]),
+                "hp_coarse_solve": (ip, [H, dp, dp]),
+                "hp_coarse_solve_f32": (ip, [H, fp, fp]),
+                "hp_precond": (ip, [H, dp, dp]),
+                "hp_precond_f32": (ip, [H, fp, fp]),
+                "hp_residual": (ip, [H, dp, dp, dp, ctypes.POINTER(ctypes.c_double)]),
+                "hp_dot": (ip, [H, dp, dp, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double)]),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(lib, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = load_library().hp_last_error()
+        raise HPError(rc, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype_name: str, numel: int, device_index: int):
+    torch = _torch()
+    dt = {"f64": torch.float64, "f32": torch.float32}[dtype_name]
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda" or t.device.index != device_index:
+        raise ValueError("tensor must live on cuda:%d" % device_index)
+    if t.dtype != dt:
+        raise TypeError("expected dtype %s, got %s" % (dt, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if t.numel() != numel:
+        raise ValueError("tensor has %d entries, expected %d" % (t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Handle around hp_setup / hp_solve / hp_free (one grid, one coefficient set at a time)."""
+
+    def __init__(self, n, h, bc, rho, c2, dt: float, mode: int | None = None):
+        torch = _torch()
+        lib = load_library()
+        self._lib = lib
+        self.n = tuple(int(v) for v in n)
+        self.ncells = self.n[0] * self.n[1] * self.n[2]
+        self.device = torch.cuda.current_device()
+        g = Grid(self.n[0], self.n[1], self.n[2], float(h[0]), float(h[1]), float(h[2]))
+        b = BC(int(bc[0]), int(bc[1]), int(bc[2]))
+        handle = ctypes.c_void_p()
+        rp = _ptr(rho, "f64", self.ncells, self.device)
+        cp = _ptr(c2, "f64", self.ncells, self.device)
+        torch.cuda.current_stream().synchronize()
+        _check(lib.hp_setup(ctypes.byref(g), rp, cp, float(dt), ctypes.byref(b),
+                            ctypes.byref(handle)))
+        self._h = handle
+        self.set_stream(torch.cuda.current_stream())
+        if mode is not None:
+            self.set_option(OPT_MODE, mode)
+
+    # -- lifetime --
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- configuration --
+    def set_stream(self, stream):
+        _check(self._lib.hp_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def set_option(self, key: int, value: float):
+        _check(self._lib.hp_set_option(self._h, int(key), float(value)))
+
+    def get_option(self, key: int) -> float:
+        v = ctypes.c_double()
+        _check(self._lib.hp_get_option(self._h, int(key), ctypes.byref(v)))
+        return v.value
+
+    def update_coefficients(self, rho, c2, dt: float):
+        _check(self._lib.hp_update_coefficients(self._h, _ptr(rho, "f64", self.ncells, self.device),
+                                                _ptr(c2, "f64", self.ncells, self.device),
+                                                float(dt)))
+
+    # -- the solve --
+    def solve(self, rhs, p, tol: float = 1e-10, check: bool = True) -> dict:
+        rc = self._lib.hp_solve(self._h, _ptr(rhs, "f64", self.ncells, self.device),
+                                _ptr(p, "f64", self.ncells, self.device), float(tol))
+        st = self.stats()
+        if check:
+            _check(rc)
+        st["rc"] = rc
+        return st
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self._lib.hp_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    # -- building blocks --
+    def num_levels(self) -> int:
+        return int(self._lib.hp_num_levels(self._h))
+
+    def level_info(self, level: int):
+        n = (ctypes.c_int * 3)()
+        hs = (ctypes.c_double * 3)()
+        _check(self._lib.hp_level_info(self._h, int(level), n, hs))
+        return tuple(n), tuple(hs)
+
+    def level_cells(self, level: int) -> int:
+        n, _ = self.level_info(level)
+        return n[0] * n[1] * n[2]
+
+    def _vec(self, t, level, f32=False):
+        return _ptr(t, "f32" if f32 else "f64", self.level_cells(level), self.device)
+
+    def apply(self, level, x, y, f32=False):
+        fn = self._lib.hp_apply_f32 if f32 else self._lib.hp_apply
+        _check(fn(self._h, level, self._vec(x, level, f32), self._vec(y, level, f32)))
+
+    def smooth(self, level, r, z, colour, f32=False):
+        fn = self._lib.hp_smooth_f32 if f32 else self._lib.hp_smooth
+        _check(fn(self._h, level, self._vec(r, level, f32), self._vec(z, level, f32), int(colour)))
+
+    def restrict_residual(self, level, r, z, rc, f32=False):
+        fn = self._lib.hp_restrict_residual_f32 if f32 else self._lib.hp_restrict_residual
+        _check(fn(self._h, level, self._vec(r, level, f32), self._vec(z, level, f32),
+                  self._vec(rc, level + 1, f32)))
+
+    def prolong_add(self, level, ec, z, f32=False):
+        fn = self._lib.hp_prolong_add_f32 if f32 else self._lib.hp_prolong_add
+        _check(fn(self._h, level, self._vec(ec, level + 1, f32), self._vec(z, level, f32)))
+
+    def coarse_solve(self, b, x, f32=False):
+        last = self.num_levels() - 1
+        fn = self._lib.hp_coarse_solve_f32 if f32 else self._lib.hp_coarse_solve
+        _check(fn(self._h, self._vec(b, last, f32), self._vec(x, last, f32)))
+
+    def precond(self, r, z, f32=False):
+        fn = self._lib.hp_precond_f32 if f32 else self._lib.hp_precond
+        _check(fn(self._h, self._vec(r, 0, f32), self._vec(z, 0, f32)))
+
+    def residual(self, rhs, p, r) -> float:
+        rel = ctypes.c_double()
+        _check(self._lib.hp_residual(self._h, self._vec(rhs, 0), self._vec(p, 0), self._vec(r, 0),
+                                     ctypes.byref(rel)))
+        return rel.value
+
+    def dot(self, x, y) -> float:
+        out = ctypes.c_double()
+        n = x.numel()
+        _check(self._lib.hp_dot(self._h, _ptr(x, "f64", n, self.device),
+                                _ptr(y, "f64", n, self.device), n, ctypes.byref(out)))
+        return out.value
+
+
+def setup(n, h, bc, rho, c2, dt, mode=None) -> Solver:
+    """Python spelling of hp_setup."""
+    return Solver(n, h, bc, rho, c2, dt, mode)

@@ -1,0 +1,113 @@
+// hp_internal.h -- private declarations shared by the kernels and the solver driver of libhp.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hp {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
+
+// Device scalar slots (FP64) used by the CG drivers; kernels read alpha/beta from here so the
+// host never has to round-trip them.
+enum Slot {
+    S_RZ = 0,      // <r, z>
+    S_PQ = 1,      // <p, A p>
+    S_ALPHA = 2,
+    S_BETA = 3,
+    S_RR = 4,      // ||r||^2
+    S_BB = 5,      // ||b||^2
+    S_FLAG = 6,    // breakdown flag (1.0 when p^T A p <= 0 or not finite)
+    S_TMP = 7,     // scratch result of a plain dot
+    S_RZ_NEW = 8,
+    S_COUNT = 16
+};
+
+// What the last workgroup of a reducing kernel does with the total.
+enum RedOp {
+    OP_NONE = 0,     // no reduction at all
+    OP_STORE = 1,    // scal[slot] = total
+    OP_ALPHA = 2,    // scal[S_PQ] = total; scal[S_ALPHA] = scal[S_RZ] / total (flag if <= 0)
+    OP_BETA = 3,     // scal[S_BETA] = total / scal[S_RZ]; scal[S_RZ] = total
+    OP_RZINIT = 4    // scal[S_RZ] = total; scal[S_BETA] = 0
+};
+
+struct RedCtl {
+    double* partials;        // one entry per workgroup
+    unsigned int* counter;   // zero between launches (the last workgroup resets it)
+    double* scal;            // device scalar slots
+    int op;
+    int slot;
+};
+
+// Geometry of one level as seen by a kernel. wx/wy/wz = dt^2 / h^2 per axis.
+template <typename T>
+struct Geo {
+    int nx, ny, nz;
+    int px, py, pz;        // 1 if the axis has a periodic wrap face (periodic and n >= 2)
+    T cx, cy, cz;          // dt^2 / h_d^2
+};
+
+// Coarsening relation between level l (fine) and l+1 (coarse).
+struct Transfer {
+    int nfx, nfy, nfz;     // fine sizes
+    int ncx, ncy, ncz;     // coarse sizes
+    int fx, fy, fz;        // 1 if the axis is coarsened
+    int perx, pery, perz;  // 1 if the axis is periodic
+};
+
+// ---- launchers (hp_kernels.hip); all asynchronous on `s` ----
+void launch_setup_coef(const double* rho, const double* c2, double* rho_out, double* m,
+                       float* rho32, float* m32, int64_t n, int* bad, hipStream_t s);
+void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m_f,
+                         double* rho_c, double* m_c, float* rho32_c, float* m32_c, hipStream_t s);
+void launch_jacobi_diag(const Geo<double>& g, const double* rho, const double* m, double* dinv,
+                        hipStream_t s);
+
+// y = A x (mode 0), y = A x with <x, y> reduced (mode 1), y = b - A x (mode 2),
+// y = b - A x with <y, y> reduced (mode 3).
+template <typename T>
+void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T* b, T* y,
+                  int mode, const RedCtl& rc, hipStream_t s);
+template <typename T>
+void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
+                 hipStream_t s);
+template <typename T>
+void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z,
+                      hipStream_t s);
+template <typename T>
+void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s);
+template <typename T>
+void launch_coarse_solve(const double* ainv, int nc, const T* b, T* x, hipStream_t s);
+
+// Deterministic dot <x, y> accumulated in FP64.
+template <typename T>
+void launch_dot(const T* x, const T* y, int64_t n, const RedCtl& rc, hipStream_t s);
+// x += alpha p; r -= alpha q; ||r||^2 -> scal[S_RR]  (alpha = scal[S_ALPHA])
+template <typename T>
+void launch_axpy2_norm(T* x, const T* p, T* r, const T* q, int64_t n, const RedCtl& rc,
+                       hipStream_t s);
+// p = z + beta p (beta = scal[S_BETA])
+template <typename T>
+void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s);
+// z = dinv * r with <r, z> reduced
+void launch_jacobi_apply(const double* dinv, const double* r, double* z, int64_t n,
+                         const RedCtl& rc, hipStream_t s);
+// dst = (float)(src * scale)
+void launch_cast_scale_f32(const double* src, float* dst, double scale, int64_t n, hipStream_t s);
+// x += scale * (double)d
+void launch_axpy_from_f32(double* x, const float* d, double scale, int64_t n, hipStream_t s);
+template <typename T>
+void launch_fill(T* x, T v, int64_t n, hipStream_t s);
+template <typename T>
+void launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
+// flag nonzero if any entry is not finite
+void launch_check_finite(const double* x, int64_t n, int* bad, hipStream_t s);
+
+// Number of workgroups the reducing kernels use for these sizes (partials capacity).
+int64_t reduce_blocks_cells(int nx, int ny, int nz);
+int64_t reduce_blocks_vec(int64_t n);
+
+}  // namespace hp

@@ -1,0 +1,815 @@
+// hp_solver.hip -- handle, multigrid hierarchy and CG drivers behind the C ABI of include/hp.h.
+//
+// The solve is the preconditioned conjugate gradient method the paper uses for its generalized
+// Poisson equation (Section 2), with the paper's incomplete-Cholesky preconditioner (a sequential
+// triangular solve) replaced by one geometric-multigrid V-cycle that runs as data-parallel
+// stencil kernels. Every scalar of the CG recurrence lives on the device; the host reads one
+// squared residual norm per iteration to decide convergence.
+#include "hp.h"
+#include "hp_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace hp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess)                                                             \
+            return fail(HP_EHIP, "%s failed: %s", #x, hipGetErrorString(e_));              \
+    } while (0)
+
+#define CHK(x)                         \
+    do {                               \
+        int rc_ = (x);                 \
+        if (rc_ != HP_OK) return rc_;  \
+    } while (0)
+
+struct LevelData {
+    int n[3];
+    double h[3];
+    int coarsened[3];  // relative to the finer level
+    int64_t N;
+    double *rho = nullptr, *m = nullptr;
+    float *rho32 = nullptr, *m32 = nullptr;
+    double *r = nullptr, *z = nullptr, *t = nullptr;
+    float *r32 = nullptr, *z32 = nullptr, *t32 = nullptr;
+};
+
+bool can_coarsen(int n, int bc) {
+    if (n % 2 != 0 || n / 2 < 2) return false;
+    if (bc == HP_BC_PERIODIC && (n / 2) % 2 != 0) return false;
+    return true;
+}
+
+}  // namespace
+
+struct hp_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hp_grid grid{};
+    hp_bc bc{};
+    double dt = 0.0;
+    std::vector<LevelData> lv;
+    int nc = 0;
+    double* ainv = nullptr;
+    std::vector<double> host_ainv;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    double* scal = nullptr;
+    double* partials = nullptr;
+    unsigned int* counter = nullptr;
+    int* flag = nullptr;
+    int64_t partial_cap = 0;
+    double* host_scal = nullptr;  // pinned mirror of scal
+    int* host_flag = nullptr;     // pinned
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<void*> allocs;
+    // options
+    int mode = HP_MODE_FP64_MGPCG;
+    int max_iter = 1000;
+    int nu_pre = 1, nu_post = 1;
+    double inner_tol = 1e-5;
+    int max_outer = 20;
+    int coarsest_max = 512;
+    hp_stats stats{};
+};
+
+namespace {
+
+template <typename T>
+int dalloc(hp_handle* H, T** p, int64_t n) {
+    void* q = nullptr;
+    size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(HP_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    H->allocs.push_back(q);
+    *p = (T*)q;
+    return HP_OK;
+}
+
+template <typename T>
+Geo<T> geo(const hp_handle* H, const LevelData& L) {
+    Geo<T> g;
+    g.nx = L.n[0];
+    g.ny = L.n[1];
+    g.nz = L.n[2];
+    g.px = (H->bc.x == HP_BC_PERIODIC && L.n[0] >= 2);
+    g.py = (H->bc.y == HP_BC_PERIODIC && L.n[1] >= 2);
+    g.pz = (H->bc.z == HP_BC_PERIODIC && L.n[2] >= 2);
+    double dt2 = H->dt * H->dt;
+    g.cx = (T)(dt2 / (L.h[0] * L.h[0]));
+    g.cy = (T)(dt2 / (L.h[1] * L.h[1]));
+    g.cz = (T)(dt2 / (L.h[2] * L.h[2]));
+    return g;
+}
+
+Transfer transfer(const hp_handle* H, int l) {
+    const LevelData& F = H->lv[l];
+    const LevelData& C = H->lv[l + 1];
+    Transfer t;
+    t.nfx = F.n[0]; t.nfy = F.n[1]; t.nfz = F.n[2];
+    t.ncx = C.n[0]; t.ncy = C.n[1]; t.ncz = C.n[2];
+    t.fx = C.coarsened[0]; t.fy = C.coarsened[1]; t.fz = C.coarsened[2];
+    t.perx = H->bc.x == HP_BC_PERIODIC;
+    t.pery = H->bc.y == HP_BC_PERIODIC;
+    t.perz = H->bc.z == HP_BC_PERIODIC;
+    return t;
+}
+
+RedCtl red(const hp_handle* H, int op, int slot = 0) {
+    RedCtl rc;
+    rc.partials = H->partials;
+    rc.counter = H->counter;
+    rc.scal = H->scal;
+    rc.op = op;
+    rc.slot = slot;
+    return rc;
+}
+
+int check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HP_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return HP_OK;
+}
+
+// ---- coarsest level: dense FP64 operator, Cholesky, symmetric inverse (host) ----
+
+int build_coarse_inverse(hp_handle* H) {
+    LevelData& C = H->lv.back();
+    const int n = (int)C.N;
+    std::vector<double> rho(n), m(n);
+    HIPCHK(hipMemcpyAsync(rho.data(), C.rho, n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipMemcpyAsync(m.data(), C.m, n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    std::vector<double> A((size_t)n * n, 0.0);
+    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
+    const int per[3] = {H->bc.x == HP_BC_PERIODIC, H->bc.y == HP_BC_PERIODIC,
+                        H->bc.z == HP_BC_PERIODIC};
+    const double dt2 = H->dt * H->dt;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int a = i + nx * (j + ny * k);
+                A[(size_t)a * n + a] += m[a];
+                int c[3] = {i, j, k};
+                for (int d = 0; d < 3; ++d)
+                    for (int s = -1; s <= 1; s += 2) {
+                        int cc[3] = {c[0], c[1], c[2]};
+                        int t = cc[d] + s;
+                        if (t < 0 || t >= C.n[d]) {
+                            if (!per[d] || C.n[d] < 2) continue;
+                            t = (t + C.n[d]) % C.n[d];
+                        }
+                        cc[d] = t;
+                        int b = cc[0] + nx * (cc[1] + ny * cc[2]);
+                        double w = dt2 / (C.h[d] * C.h[d]) * (2.0 / (rho[a] + rho[b]));
+                        A[(size_t)a * n + a] += w;
+                        A[(size_t)a * n + b] -= w;
+                    }
+            }
+    // Cholesky A = L L^T (lower triangle of L stored in A)
+    for (int j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(d > 0.0)) return fail(HP_EDOMAIN, "coarsest operator is not positive definite");
+        double ljj = std::sqrt(d);
+        A[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double s = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = s / ljj;
+        }
+    }
+    // inverse: solve L L^T X = I column by column
+    std::vector<double>& X = H->host_ainv;
+    X.assign((size_t)n * n, 0.0);
+    std::vector<double> y(n);
+    for (int col = 0; col < n; ++col) {
+        for (int i = 0; i < n; ++i) {
+            double s = (i == col) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= A[(size_t)i * n + k] * y[k];
+            y[i] = s / A[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < n; ++k) s -= A[(size_t)k * n + i] * X[(size_t)k * n + col];
+            X[(size_t)i * n + col] = s / A[(size_t)i * n + i];
+        }
+    }
+    for (int i = 0; i < n; ++i)  // exact symmetry keeps the V-cycle a symmetric operator
+        for (int j = i + 1; j < n; ++j) {
+            double v = 0.5 * (X[(size_t)i * n + j] + X[(size_t)j * n + i]);
+            X[(size_t)i * n + j] = v;
+            X[(size_t)j * n + i] = v;
+        }
+    HIPCHK(hipMemcpyAsync(H->ainv, X.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice,
+                          H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    return HP_OK;
+}
+
+// ---- coefficients of every level ----
+
+int load_coefficients(hp_handle* H, const double* rho, const double* c2, double dt) {
+    if (!rho || !c2) return fail(HP_EINVAL, "rho and c2 must be non-null device pointers");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HP_EINVAL, "dt must be positive and finite");
+    H->dt = dt;
+    LevelData& F = H->lv[0];
+    *H->host_flag = 0;
+    HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
+    launch_setup_coef(rho, c2, F.rho, F.m, F.rho32, F.m32, F.N, H->flag, H->stream);
+    CHK(check_launch());
+    HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    if (*H->host_flag) return fail(HP_EDOMAIN, "rho and c2 must be positive and finite in every cell");
+    for (size_t l = 0; l + 1 < H->lv.size(); ++l) {
+        LevelData& C = H->lv[l + 1];
+        launch_coarsen_coef(transfer(H, (int)l), H->lv[l].rho, H->lv[l].m, C.rho, C.m, C.rho32,
+                            C.m32, H->stream);
+        CHK(check_launch());
+    }
+    launch_jacobi_diag(geo<double>(H, F), F.rho, F.m, H->dinv, H->stream);
+    CHK(check_launch());
+    return build_coarse_inverse(H);
+}
+
+// ---- V-cycle ----
+
+template <typename T> T* lvl_r(LevelData& L);
+template <typename T> T* lvl_z(LevelData& L);
+template <typename T> T* lvl_t(LevelData& L);
+template <typename T> const T* lvl_rho(const LevelData& L);
+template <typename T> const T* lvl_m(const LevelData& L);
+template <> double* lvl_r<double>(LevelData& L) { return L.r; }
+template <> double* lvl_z<double>(LevelData& L) { return L.z; }
+template <> double* lvl_t<double>(LevelData& L) { return L.t; }
+template <> float* lvl_r<float>(LevelData& L) { return L.r32; }
+template <> float* lvl_z<float>(LevelData& L) { return L.z32; }
+template <> float* lvl_t<float>(LevelData& L) { return L.t32; }
+template <> const double* lvl_rho<double>(const LevelData& L) { return L.rho; }
+template <> const double* lvl_m<double>(const LevelData& L) { return L.m; }
+template <> const float* lvl_rho<float>(const LevelData& L) { return L.rho32; }
+template <> const float* lvl_m<float>(const LevelData& L) { return L.m32; }
+
+template <typename T>
+void vcycle(hp_handle* H, int l, const T* r, T* z) {
+    LevelData& L = H->lv[l];
+    hipStream_t s = H->stream;
+    if (l == (int)H->lv.size() - 1) {
+        launch_coarse_solve<T>(H->ainv, H->nc, r, z, s);
+        return;
+    }
+    Geo<T> g = geo<T>(H, L);
+    const T* rho = lvl_rho<T>(L);
+    const T* m = lvl_m<T>(L);
+    launch_rbgs_zero<T>(g, rho, m, r, z, s);
+    launch_rbgs<T>(g, rho, m, r, z, 1, s);
+    for (int it = 1; it < H->nu_pre; ++it) {
+        launch_rbgs<T>(g, rho, m, r, z, 0, s);
+        launch_rbgs<T>(g, rho, m, r, z, 1, s);
+    }
+    T* t = lvl_t<T>(L);
+    launch_apply<T>(g, rho, m, z, r, t, 2, red(H, OP_NONE), s);
+    LevelData& C = H->lv[l + 1];
+    Transfer tr = transfer(H, l);
+    launch_restrict<T>(tr, t, lvl_r<T>(C), s);
+    vcycle<T>(H, l + 1, lvl_r<T>(C), lvl_z<T>(C));
+    launch_prolong_add<T>(tr, lvl_z<T>(C), z, s);
+    for (int it = 0; it < H->nu_post; ++it) {
+        launch_rbgs<T>(g, rho, m, r, z, 1, s);
+        launch_rbgs<T>(g, rho, m, r, z, 0, s);
+    }
+}
+
+int read_scalars(hp_handle* H) {
+    HIPCHK(hipMemcpyAsync(H->host_scal, H->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                          H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    return HP_OK;
+}
+
+// Preconditioner z = M r with <r, z> reduced under `op` (OP_RZINIT or OP_BETA).
+void precond64(hp_handle* H, const double* r, double* z, int op) {
+    int64_t N = H->lv[0].N;
+    if (H->mode == HP_MODE_JACOBI_PCG) {
+        launch_jacobi_apply(H->dinv, r, z, N, red(H, op), H->stream);
+    } else {
+        vcycle<double>(H, 0, r, z);
+        launch_dot<double>(r, z, N, red(H, op), H->stream);
+    }
+}
+
+// True relative residual of x into H->z (scratch); returns HP_OK and sets *rel.
+int true_residual(hp_handle* H, const double* b, const double* x, double* out, double bnorm,
+                  double* rel) {
+    LevelData& F = H->lv[0];
+    launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, out, 3, red(H, OP_STORE, S_TMP),
+                         H->stream);
+    CHK(check_launch());
+    CHK(read_scalars(H));
+    *rel = std::sqrt(H->host_scal[S_TMP]) / bnorm;
+    return HP_OK;
+}
+
+// FP64 PCG (Jacobi or MG preconditioner) from the current x; r holds b - A x and
+// host_scal[S_RR] its squared norm on entry.
+int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
+    LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    Geo<double> g = geo<double>(H, F);
+    hipStream_t s = H->stream;
+    hp_stats& st = H->stats;
+    bool restart = true;
+    while (true) {
+        if (restart) {
+            precond64(H, H->r, H->z, OP_RZINIT);
+            launch_copy<double>(H->z, H->p, N, s);
+            restart = false;
+        }
+        launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
+        launch_axpy2_norm<double>(x, H->p, H->r, H->q, N, red(H, OP_STORE, S_RR), s);
+        CHK(check_launch());
+        CHK(read_scalars(H));
+        st.iterations++;
+        if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
+        double rr = H->host_scal[S_RR];
+        if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite residual in iteration %d", st.iterations);
+        if (std::sqrt(rr) <= tol * bnorm) {
+            double rel;
+            CHK(true_residual(H, b, x, H->z, bnorm, &rel));
+            st.rel_residual = rel;
+            if (rel <= tol) {
+                st.converged = 1;
+                return HP_OK;
+            }
+            launch_copy<double>(H->z, H->r, N, s);   // continue from the true residual
+            st.restarts++;
+            restart = true;
+            if (st.iterations >= H->max_iter) break;
+            continue;
+        }
+        if (st.iterations >= H->max_iter) break;
+        precond64(H, H->r, H->z, OP_BETA);
+        launch_xpby<double>(H->z, H->p, N, H->scal, s);
+    }
+    double rel;
+    CHK(true_residual(H, b, x, H->z, bnorm, &rel));
+    st.rel_residual = rel;
+    return fail(HP_ENOCONV, "no convergence in %d iterations (relative residual %.3e)",
+                st.iterations, rel);
+}
+
+// FP32 MG-PCG on A32 d = r32 (unit-norm r32), d = x32 starts at 0; returns inner iterations.
+int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
+    LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    Geo<float> g = geo<float>(H, F);
+    hipStream_t s = H->stream;
+    launch_fill<float>(H->x32, 0.0f, N, s);
+    vcycle<float>(H, 0, H->r32, H->z32);
+    launch_dot<float>(H->r32, H->z32, N, red(H, OP_RZINIT), s);
+    launch_copy<float>(H->z32, H->p32, N, s);
+    *its = 0;
+    while (*its < budget) {
+        launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
+        launch_axpy2_norm<float>(H->x32, H->p32, H->r32, H->q32, N, red(H, OP_STORE, S_RR), s);
+        CHK(check_launch());
+        CHK(read_scalars(H));
+        (*its)++;
+        if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "inner CG breakdown");
+        double rr = H->host_scal[S_RR];
+        if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite inner residual");
+        if (std::sqrt(rr) <= eta) break;
+        vcycle<float>(H, 0, H->r32, H->z32);
+        launch_dot<float>(H->r32, H->z32, N, red(H, OP_BETA), s);
+        launch_xpby<float>(H->z32, H->p32, N, H->scal, s);
+    }
+    return HP_OK;
+}
+
+// Mixed precision: FP64 residual and update, FP32 MG-PCG correction.
+int mixed_ir(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
+    LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    hp_stats& st = H->stats;
+    double rnorm = std::sqrt(H->host_scal[S_RR]);
+    while (true) {
+        if (rnorm <= tol * bnorm) {
+            st.converged = 1;
+            st.rel_residual = rnorm / bnorm;
+            return HP_OK;
+        }
+        if (st.outer_iterations >= H->max_outer || st.iterations >= H->max_iter) break;
+        launch_cast_scale_f32(H->r, H->r32, 1.0 / rnorm, N, H->stream);
+        // the inner solve need not go below what the outer tolerance still requires
+        double eta = std::max(H->inner_tol, 0.5 * tol * bnorm / rnorm);
+        int its = 0;
+        CHK(inner_pcg32(H, eta, H->max_iter - st.iterations, &its));
+        st.iterations += its;
+        launch_axpy_from_f32(x, H->x32, rnorm, N, H->stream);
+        launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR),
+                             H->stream);
+        CHK(check_launch());
+        CHK(read_scalars(H));
+        st.outer_iterations++;
+        double rn = std::sqrt(H->host_scal[S_RR]);
+        if (!std::isfinite(rn)) return fail(HP_ENAN, "non-finite residual in refinement");
+        if (rn > 0.5 * rnorm) {
+            // refinement stagnates (FP32 inner solve cannot reduce the FP64 residual): finish
+            // with FP64 MG-PCG from the current iterate
+            st.fallback = 1;
+            int saved = H->mode;
+            H->mode = HP_MODE_FP64_MGPCG;
+            int rc = pcg64(H, b, x, tol, bnorm);
+            H->mode = saved;
+            return rc;
+        }
+        rnorm = rn;
+    }
+    st.rel_residual = rnorm / bnorm;
+    return fail(HP_ENOCONV, "mixed refinement did not converge (relative residual %.3e)",
+                st.rel_residual);
+}
+
+int level_ok(const hp_handle* H, int level) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    if (level < 0 || level >= (int)H->lv.size()) return fail(HP_EINVAL, "level %d out of range", level);
+    return HP_OK;
+}
+
+template <typename T>
+int apply_t(hp_handle* H, int level, const T* x, T* y) {
+    CHK(level_ok(H, level));
+    if (!x || !y) return fail(HP_EINVAL, "null vector");
+    LevelData& L = H->lv[level];
+    launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), x, nullptr, y, 0, red(H, OP_NONE),
+                    H->stream);
+    return check_launch();
+}
+
+template <typename T>
+int smooth_t(hp_handle* H, int level, const T* r, T* z, int colour) {
+    CHK(level_ok(H, level));
+    if (!r || !z) return fail(HP_EINVAL, "null vector");
+    if (colour != 0 && colour != 1) return fail(HP_EINVAL, "colour must be 0 or 1");
+    LevelData& L = H->lv[level];
+    launch_rbgs<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), r, z, colour, H->stream);
+    return check_launch();
+}
+
+template <typename T>
+int restrict_t(hp_handle* H, int level, const T* r, const T* z, T* rc) {
+    CHK(level_ok(H, level));
+    if (level + 1 >= (int)H->lv.size()) return fail(HP_EINVAL, "no coarser level below %d", level);
+    if (!r || !z || !rc) return fail(HP_EINVAL, "null vector");
+    LevelData& L = H->lv[level];
+    launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), z, r, lvl_t<T>(L), 2, red(H, OP_NONE),
+                    H->stream);
+    launch_restrict<T>(transfer(H, level), lvl_t<T>(L), rc, H->stream);
+    return check_launch();
+}
+
+template <typename T>
+int prolong_t(hp_handle* H, int level, const T* ec, T* z) {
+    CHK(level_ok(H, level));
+    if (level + 1 >= (int)H->lv.size()) return fail(HP_EINVAL, "no coarser level below %d", level);
+    if (!ec || !z) return fail(HP_EINVAL, "null vector");
+    launch_prolong_add<T>(transfer(H, level), ec, z, H->stream);
+    return check_launch();
+}
+
+template <typename T>
+int coarse_t(hp_handle* H, const T* b, T* x) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    if (!b || !x) return fail(HP_EINVAL, "null vector");
+    launch_coarse_solve<T>(H->ainv, H->nc, b, x, H->stream);
+    return check_launch();
+}
+
+template <typename T>
+int precond_t(hp_handle* H, const T* r, T* z) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    if (!r || !z) return fail(HP_EINVAL, "null vector");
+    vcycle<T>(H, 0, r, z);
+    return check_launch();
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+
+extern "C" {
+
+const char* hp_last_error(void) { return g_err.c_str(); }
+
+int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt, const hp_bc* bc,
+             hp_handle** out) {
+    g_err.clear();
+    if (!grid || !bc || !out) return fail(HP_EINVAL, "grid, bc and out must be non-null");
+    *out = nullptr;
+    const int n[3] = {grid->nx, grid->ny, grid->nz};
+    const double hs[3] = {grid->hx, grid->hy, grid->hz};
+    const int bcs[3] = {bc->x, bc->y, bc->z};
+    int64_t N = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 1) return fail(HP_EINVAL, "grid size must be >= 1 on every axis");
+        if (!(hs[d] > 0.0) || !std::isfinite(hs[d])) return fail(HP_EINVAL, "spacings must be positive");
+        if (bcs[d] != HP_BC_PERIODIC && bcs[d] != HP_BC_NEUMANN) return fail(HP_EINVAL, "unknown boundary kind");
+        if (bcs[d] == HP_BC_PERIODIC && n[d] > 1 && n[d] % 2 != 0)
+            return fail(HP_EINVAL, "periodic axes need an even number of cells (red-black colouring)");
+        N *= n[d];
+    }
+    if (N >= (int64_t)1 << 31) return fail(HP_EINVAL, "grid has too many cells (limit 2^31 - 1)");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HP_EINVAL, "dt must be positive and finite");
+    if (!rho || !c2) return fail(HP_EINVAL, "rho and c2 must be non-null");
+
+    hp_handle* H = new hp_handle();
+    H->grid = *grid;
+    H->bc = *bc;
+    H->dt = dt;
+    int rc = HP_OK;
+    auto bail = [&](int code) {
+        hp_free(H);
+        return code;
+    };
+    if (hipGetDevice(&H->device) != hipSuccess) return bail(fail(HP_EHIP, "no HIP device"));
+
+    // hierarchy dimensions
+    LevelData L0;
+    for (int d = 0; d < 3; ++d) {
+        L0.n[d] = n[d];
+        L0.h[d] = hs[d];
+        L0.coarsened[d] = 0;
+    }
+    L0.N = N;
+    H->lv.push_back(L0);
+    while (true) {
+        const LevelData& L = H->lv.back();
+        int fl[3];
+        bool any = false;
+        for (int d = 0; d < 3; ++d) {
+            fl[d] = can_coarsen(L.n[d], bcs[d]);
+            any = any || fl[d];
+        }
+        if (L.N <= H->coarsest_max || !any) break;
+        LevelData C;
+        C.N = 1;
+        for (int d = 0; d < 3; ++d) {
+            C.n[d] = fl[d] ? L.n[d] / 2 : L.n[d];
+            C.h[d] = fl[d] ? 2.0 * L.h[d] : L.h[d];
+            C.coarsened[d] = fl[d];
+            C.N *= C.n[d];
+        }
+        H->lv.push_back(C);
+    }
+    H->nc = (int)H->lv.back().N;
+    if (H->nc > 4096)
+        return bail(fail(HP_EINVAL, "grid cannot be coarsened below 4096 cells (coarsest %d); use sizes with more factors of 2", H->nc));
+
+    // allocations
+    for (size_t l = 0; l < H->lv.size(); ++l) {
+        LevelData& L = H->lv[l];
+        if ((rc = dalloc(H, &L.rho, L.N)) || (rc = dalloc(H, &L.m, L.N)) ||
+            (rc = dalloc(H, &L.rho32, L.N)) || (rc = dalloc(H, &L.m32, L.N)))
+            return bail(rc);
+        if (l > 0) {
+            if ((rc = dalloc(H, &L.r, L.N)) || (rc = dalloc(H, &L.z, L.N)) ||
+                (rc = dalloc(H, &L.r32, L.N)) || (rc = dalloc(H, &L.z32, L.N)))
+                return bail(rc);
+        }
+        if (l + 1 < H->lv.size()) {
+            if ((rc = dalloc(H, &L.t, L.N)) || (rc = dalloc(H, &L.t32, L.N))) return bail(rc);
+        }
+    }
+    if ((rc = dalloc(H, &H->ainv, (int64_t)H->nc * H->nc))) return bail(rc);
+    if ((rc = dalloc(H, &H->r, N)) || (rc = dalloc(H, &H->z, N)) || (rc = dalloc(H, &H->p, N)) ||
+        (rc = dalloc(H, &H->q, N)) || (rc = dalloc(H, &H->dinv, N)))
+        return bail(rc);
+    if ((rc = dalloc(H, &H->x32, N)) || (rc = dalloc(H, &H->r32, N)) ||
+        (rc = dalloc(H, &H->z32, N)) || (rc = dalloc(H, &H->p32, N)) || (rc = dalloc(H, &H->q32, N)))
+        return bail(rc);
+    int64_t cap = std::max<int64_t>(reduce_blocks_vec(N), 1);
+    for (auto& L : H->lv)
+        cap = std::max(cap, reduce_blocks_cells(L.n[0], L.n[1], L.n[2]));
+    H->partial_cap = cap;
+    if ((rc = dalloc(H, &H->partials, cap)) || (rc = dalloc(H, &H->scal, S_COUNT)) ||
+        (rc = dalloc(H, &H->counter, 1)) || (rc = dalloc(H, &H->flag, 1)))
+        return bail(rc);
+    if (hipHostMalloc((void**)&H->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&H->host_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(HP_ENOMEM, "pinned host allocation failed"));
+    if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess)
+        return bail(fail(HP_EHIP, "hipEventCreate failed"));
+    if (hipMemsetAsync(H->counter, 0, sizeof(unsigned), H->stream) != hipSuccess ||
+        hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), H->stream) != hipSuccess)
+        return bail(fail(HP_EHIP, "hipMemsetAsync failed"));
+    if ((rc = load_coefficients(H, rho, c2, dt))) return bail(rc);
+    H->stats.levels = (int)H->lv.size();
+    *out = H;
+    return HP_OK;
+}
+
+void hp_free(hp_handle* H) {
+    if (!H) return;
+    if (H->stream) (void)hipStreamSynchronize(H->stream);
+    else (void)hipDeviceSynchronize();
+    for (void* p : H->allocs) (void)hipFree(p);
+    if (H->host_scal) (void)hipHostFree(H->host_scal);
+    if (H->host_flag) (void)hipHostFree(H->host_flag);
+    if (H->ev0) (void)hipEventDestroy(H->ev0);
+    if (H->ev1) (void)hipEventDestroy(H->ev1);
+    delete H;
+}
+
+int hp_set_stream(hp_handle* H, void* stream) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    H->stream = (hipStream_t)stream;
+    return HP_OK;
+}
+
+int hp_set_option(hp_handle* H, int key, double v) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    switch (key) {
+        case HP_OPT_MODE:
+            if (v != HP_MODE_JACOBI_PCG && v != HP_MODE_FP64_MGPCG && v != HP_MODE_MIXED_IR)
+                return fail(HP_EINVAL, "unknown mode");
+            H->mode = (int)v;
+            return HP_OK;
+        case HP_OPT_MAX_ITER:
+            if (!(v >= 1)) return fail(HP_EINVAL, "max_iter must be >= 1");
+            H->max_iter = (int)v;
+            return HP_OK;
+        case HP_OPT_NU_PRE:
+        case HP_OPT_NU_POST:
+            if (!(v >= 1 && v <= 8)) return fail(HP_EINVAL, "smoothing sweeps must be in 1..8");
+            (key == HP_OPT_NU_PRE ? H->nu_pre : H->nu_post) = (int)v;
+            return HP_OK;
+        case HP_OPT_INNER_TOL:
+            if (!(v > 0.0 && v < 1.0)) return fail(HP_EINVAL, "inner tolerance must be in (0, 1)");
+            H->inner_tol = v;
+            return HP_OK;
+        case HP_OPT_MAX_OUTER:
+            if (!(v >= 1)) return fail(HP_EINVAL, "max_outer must be >= 1");
+            H->max_outer = (int)v;
+            return HP_OK;
+        default:
+            return fail(HP_EINVAL, "unknown or read-only option %d", key);
+    }
+}
+
+int hp_get_option(const hp_handle* H, int key, double* v) {
+    if (!H || !v) return fail(HP_EINVAL, "null argument");
+    switch (key) {
+        case HP_OPT_MODE: *v = H->mode; return HP_OK;
+        case HP_OPT_MAX_ITER: *v = H->max_iter; return HP_OK;
+        case HP_OPT_NU_PRE: *v = H->nu_pre; return HP_OK;
+        case HP_OPT_NU_POST: *v = H->nu_post; return HP_OK;
+        case HP_OPT_INNER_TOL: *v = H->inner_tol; return HP_OK;
+        case HP_OPT_MAX_OUTER: *v = H->max_outer; return HP_OK;
+        case HP_OPT_COARSEST_MAX: *v = H->coarsest_max; return HP_OK;
+        default: return fail(HP_EINVAL, "unknown option %d", key);
+    }
+}
+
+int hp_update_coefficients(hp_handle* H, const double* rho, const double* c2, double dt) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    return load_coefficients(H, rho, c2, dt);
+}
+
+int hp_get_stats(const hp_handle* H, hp_stats* out) {
+    if (!H || !out) return fail(HP_EINVAL, "null argument");
+    *out = H->stats;
+    return HP_OK;
+}
+
+int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (!b || !x) return fail(HP_EINVAL, "rhs and p must be non-null");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HP_EINVAL, "tol must be positive");
+    hp_stats& st = H->stats;
+    int levels = st.levels;
+    st = hp_stats{};
+    st.levels = levels;
+    LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    hipStream_t s = H->stream;
+    HIPCHK(hipEventRecord(H->ev0, s));
+    HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), s));
+    launch_check_finite(b, N, H->flag, s);
+    launch_check_finite(x, N, H->flag, s);
+    launch_dot<double>(b, b, N, red(H, OP_STORE, S_BB), s);
+    launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
+    int rc = check_launch();
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    if ((rc = read_scalars(H))) return rc;
+    if (*H->host_flag) {
+        st.status = HP_ENAN;
+        return fail(HP_ENAN, "rhs or initial guess contains non-finite values");
+    }
+    double bnorm = std::sqrt(H->host_scal[S_BB]);
+    if (bnorm == 0.0) {
+        launch_fill<double>(x, 0.0, N, s);
+        st.converged = 1;
+        st.rel_residual = 0.0;
+        rc = HP_OK;
+    } else if (std::sqrt(H->host_scal[S_RR]) <= tol * bnorm) {
+        st.converged = 1;
+        st.rel_residual = std::sqrt(H->host_scal[S_RR]) / bnorm;
+        rc = HP_OK;
+    } else if (H->mode == HP_MODE_MIXED_IR) {
+        rc = mixed_ir(H, b, x, tol, bnorm);
+    } else {
+        rc = pcg64(H, b, x, tol, bnorm);
+    }
+    HIPCHK(hipEventRecord(H->ev1, s));
+    HIPCHK(hipEventSynchronize(H->ev1));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, H->ev0, H->ev1);
+    st.time_ms = ms;
+    st.status = rc;
+    return rc;
+}
+
+// ---- building blocks ----
+
+int hp_num_levels(const hp_handle* H) { return H ? (int)H->lv.size() : 0; }
+
+int hp_level_info(const hp_handle* H, int level, int* n, double* hs) {
+    CHK(level_ok(H, level));
+    const LevelData& L = H->lv[level];
+    for (int d = 0; d < 3; ++d) {
+        if (n) n[d] = L.n[d];
+        if (hs) hs[d] = L.h[d];
+    }
+    return HP_OK;
+}
+
+int hp_apply(hp_handle* H, int level, const double* x, double* y) { return apply_t(H, level, x, y); }
+int hp_apply_f32(hp_handle* H, int level, const float* x, float* y) { return apply_t(H, level, x, y); }
+
+int hp_smooth(hp_handle* H, int level, const double* r, double* z, int colour) { return smooth_t(H, level, r, z, colour); }
+int hp_smooth_f32(hp_handle* H, int level, const float* r, float* z, int colour) { return smooth_t(H, level, r, z, colour); }
+
+int hp_restrict_residual(hp_handle* H, int level, const double* r, const double* z, double* rc) { return restrict_t(H, level, r, z, rc); }
+int hp_restrict_residual_f32(hp_handle* H, int level, const float* r, const float* z, float* rc) { return restrict_t(H, level, r, z, rc); }
+
+int hp_prolong_add(hp_handle* H, int level, const double* ec, double* z) { return prolong_t(H, level, ec, z); }
+int hp_prolong_add_f32(hp_handle* H, int level, const float* ec, float* z) { return prolong_t(H, level, ec, z); }
+
+int hp_coarse_solve(hp_handle* H, const double* b, double* x) { return coarse_t(H, b, x); }
+int hp_coarse_solve_f32(hp_handle* H, const float* b, float* x) { return coarse_t(H, b, x); }
+
+int hp_precond(hp_handle* H, const double* r, double* z) { return precond_t(H, r, z); }
+int hp_precond_f32(hp_handle* H, const float* r, float* z) { return precond_t(H, r, z); }
+
+int hp_residual(hp_handle* H, const double* b, const double* x, double* r, double* rel) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    if (!b || !x || !r) return fail(HP_EINVAL, "null vector");
+    LevelData& F = H->lv[0];
+    launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, r, 3, red(H, OP_STORE, S_RR), H->stream);
+    launch_dot<double>(b, b, F.N, red(H, OP_STORE, S_BB), H->stream);
+    CHK(check_launch());
+    if (rel) {
+        CHK(read_scalars(H));
+        double bb = H->host_scal[S_BB];
+        *rel = bb > 0.0 ? std::sqrt(H->host_scal[S_RR] / bb) : std::sqrt(H->host_scal[S_RR]);
+    }
+    return HP_OK;
+}
+
+int hp_dot(hp_handle* H, const double* x, const double* y, long long n, double* out) {
+    if (!H || !x || !y || !out) return fail(HP_EINVAL, "null argument");
+    if (n < 0 || reduce_blocks_vec(n) > H->partial_cap) return fail(HP_EINVAL, "bad length");
+    launch_dot<double>(x, y, n, red(H, OP_STORE, S_TMP), H->stream);
+    CHK(check_launch());
+    CHK(read_scalars(H));
+    *out = H->host_scal[S_TMP];
+    return HP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,323 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle, element by element.
+
+Sizes span several workgroup tiles with ragged tails (80 x 24 x 40: x tiles of 64 with a tail of
+16, odd coarse sizes) and finish in seconds on the oracle; the full-size cases (256^3, the
+benchmark's launch configuration) are checked against the separable FFT + tridiagonal reduction
+(noise off) and by the oracle's matrix-free residual certificate (noise on).
+
+Tolerances: building blocks in FP64 are compared to 1e-12 relative (only the summation order
+of at most 64 products differs, each rounding contributes ~1e-16, amplified by the cancellation
+between the m and w terms of at most |terms| / |result|); the V-cycle to 1e-9 (its coarsest solve
+goes through an explicit inverse of an operator with condition number ~1e5); full solves to the
+bar of 1e-9 relative L2 at true residual 1e-10. FP32 blocks are compared with 2e-5 (a few FP32
+ulps through the same cancellations).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mg, separable
+from paper_1112_3507_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP GPU")]
+
+import paper_1112_3507_amd as hp  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a).ravel() - np.asarray(b).ravel())
+                 / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300))
+
+
+def make(p, mode=None):
+    return hp.setup(p.n, p.h, p.bc, dev(p.rho), dev(p.c2), p.dt, mode)
+
+
+@functools.lru_cache(maxsize=None)
+def problem(n, mach, seed=1, noise=0.01):
+    return wl.polytrope(n, mach, seed=seed, noise=noise)
+
+
+@functools.lru_cache(maxsize=None)
+def reference(n, mach, seed, rhs_seed):
+    p = problem(n, mach, seed)
+    b = wl.rhs_white(p.n, rhs_seed)
+    x, st = oracle.reference_solve(p.n, p.h, p.bc, p.rho, p.c2, p.dt, b)
+    assert st["converged"] or st["stagnated"]
+    return b, x
+
+
+RAGGED = (80, 24, 40)
+
+
+# ------------------------------------------------------------------ building blocks (FP64/FP32)
+
+def _hier(p):
+    return mg.build_hierarchy(p.n, p.h, p.bc, p.rho, p.c2, p.dt, coarsest_max=512)
+
+
+def test_hierarchy_matches_oracle_levels():
+    p = problem(RAGGED, 0.001)
+    lv = _hier(p)
+    with make(p) as s:
+        assert s.num_levels() == len(lv)
+        for l, L in enumerate(lv):
+            n, h = s.level_info(l)
+            assert n == L.n
+            assert np.allclose(h, L.h, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_apply_parity_every_level(f32):
+    p = problem(RAGGED, 0.001)
+    lv = _hier(p)
+    rng = np.random.default_rng(0)
+    dt = torch.float32 if f32 else torch.float64
+    with make(p) as s:
+        for l, L in enumerate(lv):
+            x = rng.standard_normal(L.shape)
+            y = torch.empty(L.shape, dtype=dt, device=DEV)
+            s.apply(l, dev(x, dt), y, f32=f32)
+            ref = mg.apply(L, x if not f32 else x.astype(np.float32).astype(np.float64))
+            assert relerr(host(y), ref) <= (2e-5 if f32 else 1e-13), (l, f32)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_smoother_half_sweeps_parity(f32):
+    p = problem(RAGGED, 0.001)
+    lv = _hier(p)
+    rng = np.random.default_rng(1)
+    dt = torch.float32 if f32 else torch.float64
+    with make(p) as s:
+        for l, L in enumerate(lv[:-1]):
+            r = rng.standard_normal(L.shape)
+            z0 = rng.standard_normal(L.shape)
+            if f32:
+                r = r.astype(np.float32).astype(np.float64)
+                z0 = z0.astype(np.float32).astype(np.float64)
+            zt = dev(z0, dt)
+            rt = dev(r, dt)
+            ref = z0
+            for c in (0, 1, 1, 0):
+                s.smooth(l, rt, zt, c, f32=f32)
+                ref = mg.half_sweep(L, r, ref, c)
+                assert relerr(host(zt), ref) <= (2e-5 if f32 else 1e-12), (l, c)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_restrict_and_prolong_parity(f32):
+    p = problem(RAGGED, 0.001)
+    lv = _hier(p)
+    rng = np.random.default_rng(2)
+    dt = torch.float32 if f32 else torch.float64
+    with make(p) as s:
+        for l in range(len(lv) - 1):
+            Lf, Lc = lv[l], lv[l + 1]
+            r = rng.standard_normal(Lf.shape)
+            z = rng.standard_normal(Lf.shape) * 1e-3
+            if f32:
+                r = r.astype(np.float32).astype(np.float64)
+                z = z.astype(np.float32).astype(np.float64)
+            rc = torch.empty(Lc.shape, dtype=dt, device=DEV)
+            s.restrict_residual(l, dev(r, dt), dev(z, dt), rc, f32=f32)
+            ref = mg.restrict(Lf, Lc, r - mg.apply(Lf, z))
+            assert relerr(host(rc), ref) <= (2e-4 if f32 else 1e-12), l
+            ec = rng.standard_normal(Lc.shape)
+            zf = rng.standard_normal(Lf.shape)
+            if f32:
+                ec = ec.astype(np.float32).astype(np.float64)
+                zf = zf.astype(np.float32).astype(np.float64)
+            zt = dev(zf, dt)
+            s.prolong_add(l, dev(ec, dt), zt, f32=f32)
+            assert relerr(host(zt), zf + mg.prolong(Lf, Lc, ec)) <= (1e-6 if f32 else 1e-15), l
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_coarse_solve_and_vcycle_parity(f32):
+    p = problem(RAGGED, 0.001)
+    lv = _hier(p)
+    rng = np.random.default_rng(3)
+    dt = torch.float32 if f32 else torch.float64
+    with make(p) as s:
+        Lc = lv[-1]
+        b = rng.standard_normal(Lc.shape)
+        if f32:
+            b = b.astype(np.float32).astype(np.float64)
+        x = torch.empty(Lc.shape, dtype=dt, device=DEV)
+        s.coarse_solve(dev(b, dt), x, f32=f32)
+        assert relerr(host(x), mg.coarse_solve(Lc, b)) <= (1e-6 if f32 else 1e-10)
+        r = rng.standard_normal(lv[0].shape)
+        if f32:
+            r = r.astype(np.float32).astype(np.float64)
+        z = torch.empty(lv[0].shape, dtype=dt, device=DEV)
+        s.precond(dev(r, dt), z, f32=f32)
+        assert relerr(host(z), mg.vcycle(lv, r)) <= (1e-4 if f32 else 1e-9)
+
+
+# ------------------------------------------------------------------ full solves
+
+@pytest.mark.parametrize("mach,rhs_seed", [(0.001, 2), (0.01, 3)])
+def test_fp64_mgpcg_matches_oracle(mach, rhs_seed):
+    p = problem(RAGGED, mach)
+    b, xref = reference(RAGGED, mach, 1, rhs_seed)
+    x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+    with make(p) as s:
+        st = s.solve(dev(b), x, tol=1e-10)
+    xg = host(x)
+    assert st["converged"] and st["rel_residual"] <= 1e-10
+    assert relerr(xg, xref) <= 1e-9
+    assert np.max(np.abs(xg - xref)) <= 1e-8 * np.max(np.abs(xref))
+    # the oracle's own residual of the GPU result
+    r = oracle.residual(p.n, p.h, p.bc, p.rho, p.c2, p.dt, xg, b)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+
+
+def test_mixed_ir_matches_oracle():
+    p = problem(RAGGED, 0.001)
+    b, xref = reference(RAGGED, 0.001, 1, 2)
+    x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+    with make(p, hp.MODE_MIXED_IR) as s:
+        st = s.solve(dev(b), x, tol=1e-10)
+    assert st["converged"] and st["rel_residual"] <= 1e-10 and st["outer_iterations"] >= 1
+    assert relerr(host(x), xref) <= 1e-9
+
+
+def test_jacobi_pcg_config0():
+    p = wl.config0()
+    b = wl.rhs_modes_2d(64, 64, seed=0)
+    xref, _ = oracle.reference_solve(p.n, p.h, p.bc, p.rho, p.c2, p.dt, b)
+    xs = separable.solve_stratified(p.n, p.h, p.bc, p.rho[:, 0, 0], p.c2[:, 0, 0], p.dt, b)
+    for mode in (hp.MODE_JACOBI_PCG, hp.MODE_FP64_MGPCG, hp.MODE_MIXED_IR):
+        x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        with make(p, mode) as s:
+            st = s.solve(dev(b), x, tol=1e-10)
+        assert st["converged"] and st["rel_residual"] <= 1e-10
+        # Jacobi-PCG leaves its residual in low modes: its error bound is kappa * tol
+        assert relerr(host(x), xref) <= (1e-8 if mode == hp.MODE_JACOBI_PCG else 1e-9), mode
+        assert relerr(xref, xs) <= 1e-11
+
+
+@pytest.mark.parametrize("n,bc", [((2, 1, 6), (0, 0, 1)), ((4, 4, 4), (0, 0, 1)),
+                                  ((16, 16, 16), (1, 1, 1)), ((8, 8, 8), (0, 0, 0)),
+                                  ((12, 8, 15), (1, 0, 1)), ((64, 1, 64), (0, 0, 1)),
+                                  ((1, 1, 40), (0, 0, 1)), ((36, 20, 7), (0, 0, 1))])
+def test_solve_edge_shapes(n, bc):
+    p = wl.polytrope(n, 0.01, seed=4)
+    p.bc = bc
+    b = wl.rhs_white(n, 5)
+    xref, _ = oracle.reference_solve(p.n, p.h, p.bc, p.rho, p.c2, p.dt, b)
+    for mode in (hp.MODE_FP64_MGPCG, hp.MODE_MIXED_IR):
+        x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        with make(p, mode) as s:
+            st = s.solve(dev(b), x, tol=1e-10)
+        assert st["converged"], (n, bc, mode, st)
+        assert relerr(host(x), xref) <= 1e-9, (n, bc, mode)
+
+
+def test_warm_start_zero_rhs_and_errors():
+    p = problem(RAGGED, 0.001)
+    b, xref = reference(RAGGED, 0.001, 1, 2)
+    with make(p) as s:
+        # rhs = 0 gives p = 0 and no iterations
+        x = torch.ones(p.shape, dtype=torch.float64, device=DEV)
+        st = s.solve(torch.zeros_like(x), x, tol=1e-10)
+        assert st["iterations"] == 0 and float(x.abs().max()) == 0.0
+        # the converged solution as a warm start needs no iterations
+        x = dev(xref)
+        st = s.solve(dev(b), x, tol=1e-10)
+        assert st["iterations"] == 0 and st["converged"]
+        # iteration cap: HP_ENOCONV with the last iterate and stats filled
+        s.set_option(hp.OPT_MAX_ITER, 1)
+        x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        st = s.solve(dev(b), x, tol=1e-10, check=False)
+        assert st["rc"] == hp.ENOCONV and st["iterations"] == 1 and st["rel_residual"] < 1.0
+        s.set_option(hp.OPT_MAX_ITER, 1000)
+        # non-finite right-hand side
+        bn = dev(b)
+        bn[3, 2, 1] = float("nan")
+        with pytest.raises(hp.HPError) as e:
+            s.solve(bn, x, tol=1e-10)
+        assert e.value.code == hp.ENAN
+        with pytest.raises(hp.HPError):
+            s.set_option(hp.OPT_MODE, 7)
+    rho = p.rho.copy()
+    rho[5, 5, 5] = -1.0
+    with pytest.raises(hp.HPError) as e:
+        hp.setup(p.n, p.h, p.bc, dev(rho), dev(p.c2), p.dt)
+    assert e.value.code == hp.EDOMAIN
+
+
+def test_update_coefficients_matches_fresh_setup():
+    p1 = problem(RAGGED, 0.001, seed=1)
+    p2 = problem(RAGGED, 0.01, seed=2)
+    b, xref = reference(RAGGED, 0.01, 2, 7)
+    x = torch.zeros(p1.shape, dtype=torch.float64, device=DEV)
+    with make(p1) as s:
+        s.update_coefficients(dev(p2.rho), dev(p2.c2), p2.dt)
+        st = s.solve(dev(b), x, tol=1e-10)
+    assert st["converged"] and relerr(host(x), xref) <= 1e-9
+
+
+def test_solve_is_deterministic():
+    p = problem(RAGGED, 0.001)
+    b, _ = reference(RAGGED, 0.001, 1, 2)
+    outs = []
+    with make(p) as s:
+        for _ in range(2):
+            x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+            s.solve(dev(b), x, tol=1e-10)
+            outs.append(host(x))
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------------ full size (256^3)
+
+@pytest.mark.parametrize("mach", [0.01, 0.001])
+def test_full_size_separable_pin(mach):
+    n = (256, 256, 256)
+    p = wl.polytrope(n, mach, noise=0.0)
+    b = wl.rhs_white(n, 100)
+    xs = separable.solve_stratified(p.n, p.h, p.bc, p.rho[:, 0, 0], p.c2[:, 0, 0], p.dt, b)
+    for mode in (hp.MODE_FP64_MGPCG, hp.MODE_MIXED_IR):
+        x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        with make(p, mode) as s:
+            st = s.solve(dev(b), x, tol=1e-10)
+        assert st["converged"] and st["rel_residual"] <= 1e-10
+        err = relerr(host(x), xs)
+        print("256^3 separable Ma=%g mode=%d iterations=%d err=%.2e" % (mach, mode,
+              st["iterations"], err), flush=True)
+        assert err <= 1e-9
+
+
+@pytest.mark.parametrize("mach", [0.01, 0.001])
+def test_full_size_noisy_residual_certificate(mach):
+    n = (256, 256, 256)
+    p = wl.polytrope(n, mach, seed=0)
+    b = wl.rhs_white(n, 101)
+    sols = []
+    for mode in (hp.MODE_FP64_MGPCG, hp.MODE_MIXED_IR):
+        x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        with make(p, mode) as s:
+            st = s.solve(dev(b), x, tol=1e-10)
+        assert st["converged"]
+        xg = host(x)
+        r = oracle.residual(p.n, p.h, p.bc, p.rho, p.c2, p.dt, xg, b)
+        assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+        sols.append(xg)
+    # both forms solve the same system: they agree to the parity bar
+    assert relerr(sols[1], sols[0]) <= 1e-9
