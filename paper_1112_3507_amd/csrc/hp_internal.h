@@ -23,7 +23,7 @@ enum Slot {
     S_COUNT = 16
 };
 
-// What the last workgroup of a reducing kernel does with the total.
+// What the second reduction stage (one workgroup) does with the total.
 enum RedOp {
     OP_NONE = 0,     // no reduction at all
     OP_STORE = 1,    // scal[slot] = total
@@ -33,8 +33,7 @@ enum RedOp {
 };
 
 struct RedCtl {
-    double* partials;        // one entry per workgroup
-    unsigned int* counter;   // zero between launches (the last workgroup resets it)
+    double* partials;        // one entry per workgroup (first stage)
     double* scal;            // device scalar slots
     int op;
     int slot;

@@ -6,8 +6,15 @@
 // exactly and the two cells of a face see bit-identical weights (rho_a + rho_b is commutative).
 //
 // Reductions are deterministic: each workgroup reduces in a fixed butterfly/tree order and
-// writes one partial; the last workgroup to finish (atomic ticket) sums the partials in index
-// order and applies the scalar update of the CG recurrence on the device.
+// writes one partial; a one-workgroup kernel then sums the partials in index order and applies
+// the scalar update of the CG recurrence on the device (no atomics, so no serialisation of
+// thousands of workgroups on one address).
+//
+// Large levels use z-marching kernels: a workgroup owns a 64-wide (apply) or 128-wide
+// (red-black, two cells per thread) by 4-row column tile and walks a chunk of z planes, keeping
+// the z neighbours of the current plane in registers so every array is streamed once. Tiles are
+// numbered so that each of the 8 XCDs (which receive workgroups round-robin) works on one
+// contiguous range of z chunks, keeping y halos in its own L2.
 #include "hp_internal.h"
 
 #include <algorithm>
@@ -63,50 +70,47 @@ __device__ double block_sum(double v) {
     return s;
 }
 
-// Two-stage deterministic reduction with the last-workgroup epilogue. Every thread must call.
-__device__ void red_finish(double v, const RedCtl& rc) {
-    __shared__ int is_last;
-    const int tid = flat_tid();
-    const int nb = num_blocks();
+// First stage of a deterministic reduction: the workgroup total goes to partials[workgroup].
+// Every thread must call. The second stage is k_finalize (one workgroup, fixed order).
+__device__ void block_partial(double v, double* partials) {
     double s = block_sum(v);
-    if (tid == 0) {
-        rc.partials[flat_bid()] = s;
-        __threadfence();
-        unsigned t = atomicAdd(rc.counter, 1u);
-        is_last = (t == (unsigned)(nb - 1));
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+    if (flat_tid() == 0) partials[flat_bid()] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int nb,
+                                                     double* __restrict__ sc, int op, int slot) {
+    const int tid = threadIdx.x;
     double acc = 0.0;
-    for (int b = tid; b < nb; b += kBlock)
-        acc += __hip_atomic_load(&rc.partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int b = tid; b < nb; b += kBlock) acc += partials[b];
     double tot = block_sum(acc);
-    if (tid == 0) {
-        double* sc = rc.scal;
-        switch (rc.op) {
-            case OP_STORE: sc[rc.slot] = tot; break;
-            case OP_ALPHA:
-                sc[S_PQ] = tot;
-                if (!(tot > 0.0) || !isfinite(tot)) {
-                    sc[S_FLAG] = 1.0;
-                    sc[S_ALPHA] = 0.0;
-                } else {
-                    sc[S_ALPHA] = sc[S_RZ] / tot;
-                }
-                break;
-            case OP_BETA:
-                sc[S_BETA] = tot / sc[S_RZ];
-                sc[S_RZ] = tot;
-                break;
-            case OP_RZINIT:
-                sc[S_RZ] = tot;
-                sc[S_BETA] = 0.0;
-                break;
-            default: break;
-        }
-        __hip_atomic_store(rc.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid != 0) return;
+    switch (op) {
+        case OP_STORE: sc[slot] = tot; break;
+        case OP_ALPHA:
+            sc[S_PQ] = tot;
+            if (!(tot > 0.0) || !isfinite(tot)) {
+                sc[S_FLAG] = 1.0;
+                sc[S_ALPHA] = 0.0;
+            } else {
+                sc[S_ALPHA] = sc[S_RZ] / tot;
+            }
+            break;
+        case OP_BETA:
+            sc[S_BETA] = tot / sc[S_RZ];
+            sc[S_RZ] = tot;
+            break;
+        case OP_RZINIT:
+            sc[S_RZ] = tot;
+            sc[S_BETA] = 0.0;
+            break;
+        default: break;
     }
+}
+
+static void finalize(const RedCtl& rc, int nb, hipStream_t s) {
+    if (rc.op == OP_NONE) return;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, rc.partials, nb, rc.scal, rc.op,
+                       rc.slot);
 }
 
 // Launch shape over cells: 256-thread 3D workgroups sized to the level.
@@ -127,9 +131,11 @@ static Shape3 cells_shape(int nx, int ny, int nz) {
     s.grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, (nz + bz - 1) / bz);
     return s;
 }
+struct ZTiles;
+static int64_t zm_blocks(int nx, int ny, int nz);
 int64_t reduce_blocks_cells(int nx, int ny, int nz) {
     Shape3 s = cells_shape(nx, ny, nz);
-    return (int64_t)s.grid.x * s.grid.y * s.grid.z;
+    return std::max<int64_t>((int64_t)s.grid.x * s.grid.y * s.grid.z, zm_blocks(nx, ny, nz));
 }
 static inline int vec_blocks(int64_t n) {
     int64_t b = (n + 4 * kBlock - 1) / (4 * kBlock);
@@ -268,19 +274,163 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo<T> g, const T* __restrict_
         if (MODE == 1) part = (double)xa * (double)acc;
         if (MODE == 3) part = (double)acc * (double)acc;
     }
-    if (MODE == 1 || MODE == 3) red_finish(part, rc);
+    if (MODE == 1 || MODE == 3) block_partial(part, rc.partials);
+}
+
+// ---- z-marching operator apply (large levels) ----
+
+struct ZTiles {
+    int tx, ty, tz;  // tiles along x, y and z chunks
+    int kz;          // planes per z chunk
+};
+
+// Tile of this workgroup, XCD-contiguous: hardware dispatches workgroup L to XCD L % 8.
+__device__ __forceinline__ void ztile(const ZTiles& t, int& bx, int& by, int& bz) {
+    unsigned total = (unsigned)t.tx * t.ty * t.tz;
+    unsigned L = blockIdx.x;
+    if ((total & 7u) == 0) L = (L & 7u) * (total >> 3) + (L >> 3);
+    bx = (int)(L % (unsigned)t.tx);
+    by = (int)((L / (unsigned)t.tx) % (unsigned)t.ty);
+    bz = (int)(L / ((unsigned)t.tx * t.ty));
+}
+
+static ZTiles ztiles(int nx, int ny, int nz, int xw) {
+    ZTiles t;
+    t.tx = (nx + xw - 1) / xw;
+    t.ty = (ny + 3) / 4;
+    int cols = t.tx * t.ty;
+    t.kz = nz;
+    // aim for >= 2048 workgroups (8 per CU) with chunks of at least 8 planes
+    while (t.kz > 8 && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < 2048) t.kz = (t.kz + 1) / 2;
+    t.tz = (nz + t.kz - 1) / t.kz;
+    return t;
+}
+
+// In-plane neighbour offsets of column (i, j): offset and presence of the x-, x+, y-, y+ faces.
+template <typename T>
+struct PlaneNb {
+    int oxm, oxp, oym, oyp;
+    bool hxm, hxp, hym, hyp;
+    __device__ __forceinline__ PlaneNb(const Geo<T>& g, int i, int j) {
+        hxm = (i > 0) || g.px;
+        oxm = (i > 0) ? -1 : (g.nx - 1);
+        hxp = (i < g.nx - 1) || g.px;
+        oxp = (i < g.nx - 1) ? 1 : -(g.nx - 1);
+        hym = (j > 0) || g.py;
+        oym = (j > 0) ? -g.nx : (g.ny - 1) * g.nx;
+        hyp = (j < g.ny - 1) || g.py;
+        oyp = (j < g.ny - 1) ? g.nx : -(g.ny - 1) * g.nx;
+    }
+};
+
+// plane index of the z neighbour of plane k in direction s; -1 if there is no face
+__device__ __forceinline__ int zplane(int k, int s, int nz, int pz) {
+    int t = k + s;
+    if (t >= 0 && t < nz) return t;
+    if (!pz) return -1;
+    return t < 0 ? t + nz : t - nz;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
+                                                     const T* __restrict__ rho,
+                                                     const T* __restrict__ m,
+                                                     const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y,
+                                                     double* __restrict__ partials) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int i = bx * 64 + (threadIdx.x & 63);
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
+    const int64_t sz = (int64_t)g.nx * g.ny;
+    double part = 0.0;
+    if (i < g.nx && j < g.ny) {
+        const PlaneNb<T> nb(g, i, j);
+        const int64_t col = i + (int64_t)g.nx * j;
+        const T* xc_p = x + col;
+        const T* rc_p = rho + col;
+        T xc = xc_p[k0 * sz], rc = rc_p[k0 * sz];
+        // face below plane k0
+        int km = zplane(k0, -1, g.nz, g.pz);
+        T wzm = T(0), xm = T(0);
+        if (km >= 0) {
+            xm = xc_p[km * sz];
+            wzm = g.cz * face_kappa(rc, rc_p[km * sz]);
+        }
+        int kp = zplane(k0, 1, g.nz, g.pz);
+        T xn = T(0), rn = T(0);
+        if (kp >= 0) {
+            xn = xc_p[kp * sz];
+            rn = rc_p[kp * sz];
+        }
+        for (int k = k0; k < k1; ++k) {
+            const int64_t a = col + k * sz;
+            T acc = m[a] * xc;
+            if (nb.hxm) acc += g.cx * face_kappa(rc, rho[a + nb.oxm]) * (xc - x[a + nb.oxm]);
+            if (nb.hxp) acc += g.cx * face_kappa(rc, rho[a + nb.oxp]) * (xc - x[a + nb.oxp]);
+            if (nb.hym) acc += g.cy * face_kappa(rc, rho[a + nb.oym]) * (xc - x[a + nb.oym]);
+            if (nb.hyp) acc += g.cy * face_kappa(rc, rho[a + nb.oyp]) * (xc - x[a + nb.oyp]);
+            if (km >= 0) acc += wzm * (xc - xm);
+            T wzp = T(0);
+            if (kp >= 0) {
+                wzp = g.cz * face_kappa(rc, rn);
+                acc += wzp * (xc - xn);
+            }
+            if (MODE >= 2) acc = b[a] - acc;
+            y[a] = acc;
+            if (MODE == 1) part += (double)xc * (double)acc;
+            if (MODE == 3) part += (double)acc * (double)acc;
+            // advance one plane: the z+ face of plane k is the z- face of plane k+1
+            km = (kp >= 0) ? k : -1;
+            wzm = wzp;
+            xm = xc;
+            xc = xn;
+            rc = rn;
+            if (k + 1 < k1) {
+                kp = zplane(k + 1, 1, g.nz, g.pz);
+                if (kp >= 0) {
+                    xn = xc_p[kp * sz];
+                    rn = rc_p[kp * sz];
+                }
+            }
+        }
+    }
+    if (MODE == 1 || MODE == 3) block_partial(part, partials);
+}
+
+static bool use_zm(int nx, int ny, int nz) { return nx >= 64 && ny >= 4 && nz >= 8; }
+static int64_t zm_blocks(int nx, int ny, int nz) {
+    ZTiles t = ztiles(nx, ny, nz, 64);
+    return (int64_t)t.tx * t.ty * t.tz;
 }
 
 template <typename T>
 void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T* b, T* y,
                   int mode, const RedCtl& rc, hipStream_t s) {
-    Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
-    switch (mode) {
-        case 0: hipLaunchKernelGGL((k_apply<T, 0>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
-        case 1: hipLaunchKernelGGL((k_apply<T, 1>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
-        case 2: hipLaunchKernelGGL((k_apply<T, 2>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
-        default: hipLaunchKernelGGL((k_apply<T, 3>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+    int nb;
+    if (use_zm(g.nx, g.ny, g.nz)) {
+        ZTiles zt = ztiles(g.nx, g.ny, g.nz, 64);
+        nb = zt.tx * zt.ty * zt.tz;
+        dim3 grid(nb), block(kBlock);
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((k_apply_zm<T, 0>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 1: hipLaunchKernelGGL((k_apply_zm<T, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 2: hipLaunchKernelGGL((k_apply_zm<T, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            default: hipLaunchKernelGGL((k_apply_zm<T, 3>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+        }
+    } else {
+        Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
+        nb = sh.grid.x * sh.grid.y * sh.grid.z;
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((k_apply<T, 0>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+            case 1: hipLaunchKernelGGL((k_apply<T, 1>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+            case 2: hipLaunchKernelGGL((k_apply<T, 2>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+            default: hipLaunchKernelGGL((k_apply<T, 3>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+        }
     }
+    if (mode == 1 || mode == 3) finalize(rc, nb, s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -329,9 +479,129 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zero(Geo<T> g, const T* __restr
     z[a] = r[a] / (m[a] + sw);
 }
 
+// Z-marching red-black half sweep: each thread owns the cell pair (i0, i0+1) of one row and
+// updates, plane by plane, the member of colour `colour` (the colour alternates with k). The
+// z neighbours of the updated cell are the other-colour cells of the pairs one plane up and
+// down, which this sweep never writes, so they are kept in registers. ZERO: first red sweep from
+// z = 0 (red cells r / D, black cells 0; no z loads).
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
+                                                    const T* __restrict__ rho,
+                                                    const T* __restrict__ m,
+                                                    const T* __restrict__ r, T* __restrict__ z,
+                                                    int colour) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int i0 = (bx * 64 + (threadIdx.x & 63)) * 2;
+    const int j = by * 4 + (threadIdx.x >> 6);
+    if (i0 >= g.nx || j >= g.ny) return;
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
+    const int64_t sz = (int64_t)g.nx * g.ny;
+    const bool has1 = i0 + 1 < g.nx;
+    const PlaneNb<T> nb0(g, i0, j), nb1(g, has1 ? i0 + 1 : i0, j);
+    const int64_t col = i0 + (int64_t)g.nx * j;
+    // pair values at planes k-1 (m), k (c), k+1 (n)
+    T rm0 = T(0), rm1 = T(0), rc0, rc1 = T(0), rn0 = T(0), rn1 = T(0);
+    T zm0 = T(0), zm1 = T(0), zc0 = T(0), zc1 = T(0), zn0 = T(0), zn1 = T(0);
+    int km = zplane(k0, -1, g.nz, g.pz);
+    int kp = zplane(k0, 1, g.nz, g.pz);
+    rc0 = rho[col + k0 * sz];
+    if (has1) rc1 = rho[col + 1 + k0 * sz];
+    if (!ZERO) {
+        zc0 = z[col + k0 * sz];
+        if (has1) zc1 = z[col + 1 + k0 * sz];
+    }
+    if (km >= 0) {
+        rm0 = rho[col + km * sz];
+        if (has1) rm1 = rho[col + 1 + km * sz];
+        if (!ZERO) {
+            zm0 = z[col + km * sz];
+            if (has1) zm1 = z[col + 1 + km * sz];
+        }
+    }
+    if (kp >= 0) {
+        rn0 = rho[col + kp * sz];
+        if (has1) rn1 = rho[col + 1 + kp * sz];
+        if (!ZERO) {
+            zn0 = z[col + kp * sz];
+            if (has1) zn1 = z[col + 1 + kp * sz];
+        }
+    }
+    for (int k = k0; k < k1; ++k) {
+        const int sel = (colour + j + k) & 1;  // i0 is even
+        if (sel == 0 || has1) {
+            const PlaneNb<T>& nb = sel ? nb1 : nb0;
+            const int64_t a = col + sel + k * sz;
+            const T ra = sel ? rc1 : rc0;
+            T sw = T(0), swz = T(0);
+            if (nb.hxm) {
+                T w = g.cx * face_kappa(ra, rho[a + nb.oxm]);
+                sw += w;
+                if (!ZERO) swz += w * z[a + nb.oxm];
+            }
+            if (nb.hxp) {
+                T w = g.cx * face_kappa(ra, rho[a + nb.oxp]);
+                sw += w;
+                if (!ZERO) swz += w * z[a + nb.oxp];
+            }
+            if (nb.hym) {
+                T w = g.cy * face_kappa(ra, rho[a + nb.oym]);
+                sw += w;
+                if (!ZERO) swz += w * z[a + nb.oym];
+            }
+            if (nb.hyp) {
+                T w = g.cy * face_kappa(ra, rho[a + nb.oyp]);
+                sw += w;
+                if (!ZERO) swz += w * z[a + nb.oyp];
+            }
+            if (km >= 0) {
+                T w = g.cz * face_kappa(ra, sel ? rm1 : rm0);
+                sw += w;
+                if (!ZERO) swz += w * (sel ? zm1 : zm0);
+            }
+            if (kp >= 0) {
+                T w = g.cz * face_kappa(ra, sel ? rn1 : rn0);
+                sw += w;
+                if (!ZERO) swz += w * (sel ? zn1 : zn0);
+            }
+            z[a] = (r[a] + swz) / (m[a] + sw);
+            if (ZERO) {
+                const int other = 1 - sel;
+                if (other == 0 || has1) z[col + other + k * sz] = T(0);
+            }
+        }
+        // advance one plane. At plane k+1 the other pair member is updated; its z neighbours
+        // are the members of planes k and k+2 that this sweep does not write, so the register
+        // copies stay valid (the updated member's stale copy is never read again).
+        km = (kp >= 0) ? k : -1;
+        rm0 = rc0; rm1 = rc1;
+        rc0 = rn0; rc1 = rn1;
+        zm0 = zc0; zm1 = zc1;
+        zc0 = zn0; zc1 = zn1;
+        if (k + 1 < k1) {
+            kp = zplane(k + 1, 1, g.nz, g.pz);
+            if (kp >= 0) {
+                rn0 = rho[col + kp * sz];
+                if (has1) rn1 = rho[col + 1 + kp * sz];
+                if (!ZERO) {
+                    zn0 = z[col + kp * sz];
+                    if (has1) zn1 = z[col + 1 + kp * sz];
+                }
+            }
+        }
+    }
+}
+
 template <typename T>
 void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                  hipStream_t s) {
+    if (use_zm(g.nx, g.ny, g.nz)) {
+        ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+        hipLaunchKernelGGL((k_rbgs_zm<T, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
+                           g, zt, rho, m, r, z, colour);
+        return;
+    }
     Shape3 sh = cells_shape((g.nx + 1) / 2, g.ny, g.nz);
     hipLaunchKernelGGL((k_rbgs<T>), sh.grid, sh.block, 0, s, g, rho, m, r, z, colour);
 }
@@ -339,6 +609,12 @@ void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, in
 template <typename T>
 void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z,
                       hipStream_t s) {
+    if (use_zm(g.nx, g.ny, g.nz)) {
+        ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+        hipLaunchKernelGGL((k_rbgs_zm<T, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
+                           g, zt, rho, m, r, z, 0);
+        return;
+    }
     Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
     hipLaunchKernelGGL((k_rbgs_zero<T>), sh.grid, sh.block, 0, s, g, rho, m, r, z);
 }
@@ -491,12 +767,13 @@ __global__ __launch_bounds__(kBlock) void k_dot(const T* __restrict__ x, const T
     int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x; a < n; a += stride)
         acc += (double)x[a] * (double)y[a];
-    red_finish(acc, rc);
+    block_partial(acc, rc.partials);
 }
 
 template <typename T>
 void launch_dot(const T* x, const T* y, int64_t n, const RedCtl& rc, hipStream_t s) {
     hipLaunchKernelGGL((k_dot<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, y, n, rc);
+    finalize(rc, vec_blocks(n), s);
 }
 
 template <typename T>
@@ -513,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy2_norm(T* __restrict__ x, const 
         r[a] = ra;
         acc += (double)ra * (double)ra;
     }
-    red_finish(acc, rc);
+    block_partial(acc, rc.partials);
 }
 
 template <typename T>
@@ -521,6 +798,7 @@ void launch_axpy2_norm(T* x, const T* p, T* r, const T* q, int64_t n, const RedC
                        hipStream_t s) {
     hipLaunchKernelGGL((k_axpy2_norm<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, p, r, q, n,
                        rc);
+    finalize(rc, vec_blocks(n), s);
 }
 
 template <typename T>
@@ -548,12 +826,13 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_apply(const double* __restric
         z[a] = za;
         acc += r[a] * za;
     }
-    red_finish(acc, rc);
+    block_partial(acc, rc.partials);
 }
 
 void launch_jacobi_apply(const double* dinv, const double* r, double* z, int64_t n,
                          const RedCtl& rc, hipStream_t s) {
     hipLaunchKernelGGL(k_jacobi_apply, dim3(vec_blocks(n)), dim3(kBlock), 0, s, dinv, r, z, n, rc);
+    finalize(rc, vec_blocks(n), s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cast_scale_f32(const double* __restrict__ src,

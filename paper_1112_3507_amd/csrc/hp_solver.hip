@@ -77,7 +77,6 @@ struct hp_handle {
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     double* scal = nullptr;
     double* partials = nullptr;
-    unsigned int* counter = nullptr;
     int* flag = nullptr;
     int64_t partial_cap = 0;
     double* host_scal = nullptr;  // pinned mirror of scal
@@ -139,7 +138,6 @@ Transfer transfer(const hp_handle* H, int l) {
 RedCtl red(const hp_handle* H, int op, int slot = 0) {
     RedCtl rc;
     rc.partials = H->partials;
-    rc.counter = H->counter;
     rc.scal = H->scal;
     rc.op = op;
     rc.slot = slot;
@@ -614,15 +612,14 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
         cap = std::max(cap, reduce_blocks_cells(L.n[0], L.n[1], L.n[2]));
     H->partial_cap = cap;
     if ((rc = dalloc(H, &H->partials, cap)) || (rc = dalloc(H, &H->scal, S_COUNT)) ||
-        (rc = dalloc(H, &H->counter, 1)) || (rc = dalloc(H, &H->flag, 1)))
+        (rc = dalloc(H, &H->flag, 1)))
         return bail(rc);
     if (hipHostMalloc((void**)&H->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&H->host_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(HP_ENOMEM, "pinned host allocation failed"));
     if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess)
         return bail(fail(HP_EHIP, "hipEventCreate failed"));
-    if (hipMemsetAsync(H->counter, 0, sizeof(unsigned), H->stream) != hipSuccess ||
-        hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), H->stream) != hipSuccess)
+    if (hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), H->stream) != hipSuccess)
         return bail(fail(HP_EHIP, "hipMemsetAsync failed"));
     if ((rc = load_coefficients(H, rho, c2, dt))) return bail(rc);
     H->stats.levels = (int)H->lv.size();
