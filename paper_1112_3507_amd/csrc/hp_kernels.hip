@@ -331,6 +331,36 @@ __device__ __forceinline__ int zplane(int k, int s, int nz, int pz) {
     return t < 0 ? t + nz : t - nz;
 }
 
+// Branch-free face table of one column: offsets of the four in-plane neighbours (0, i.e. the
+// cell itself, where the face is absent) and their dt^2/h^2 factors (0 where absent). An absent
+// face then contributes c * kappa * (x_a - x_a) = 0 exactly and nothing to the diagonal.
+template <typename T>
+struct FaceTab {
+    int o[4];
+    T c[4];
+    __device__ __forceinline__ FaceTab(const Geo<T>& g, int i, int j) {
+        const PlaneNb<T> nb(g, i, j);
+        o[0] = nb.hxm ? nb.oxm : 0; c[0] = nb.hxm ? g.cx : T(0);
+        o[1] = nb.hxp ? nb.oxp : 0; c[1] = nb.hxp ? g.cx : T(0);
+        o[2] = nb.hym ? nb.oym : 0; c[2] = nb.hym ? g.cy : T(0);
+        o[3] = nb.hyp ? nb.oyp : 0; c[3] = nb.hyp ? g.cy : T(0);
+    }
+};
+
+// offset (in cells) from plane k to its z neighbour in direction s, and whether the face exists
+__device__ __forceinline__ int zoff(int k, int s, int nz, int pz, int sz, bool& has) {
+    int t = k + s;
+    has = true;
+    if (t >= 0 && t < nz) return s * sz;
+    if (!pz) {
+        has = false;
+        return 0;
+    }
+    return (t < 0 ? t + nz : t - nz) * sz - k * sz;
+}
+
+// Software-pipelined z march: all loads of plane k+1 are issued before plane k is computed
+// (unconditionally, with clamped addresses), so each wave keeps two planes of loads in flight.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
@@ -344,57 +374,71 @@ __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
     const int j = by * 4 + (threadIdx.x >> 6);
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
-    const int64_t sz = (int64_t)g.nx * g.ny;
+    const int sz = g.nx * g.ny;
     double part = 0.0;
     if (i < g.nx && j < g.ny) {
-        const PlaneNb<T> nb(g, i, j);
-        const int64_t col = i + (int64_t)g.nx * j;
-        const T* xc_p = x + col;
-        const T* rc_p = rho + col;
-        T xc = xc_p[k0 * sz], rc = rc_p[k0 * sz];
-        // face below plane k0
-        int km = zplane(k0, -1, g.nz, g.pz);
-        T wzm = T(0), xm = T(0);
-        if (km >= 0) {
-            xm = xc_p[km * sz];
-            wzm = g.cz * face_kappa(rc, rc_p[km * sz]);
+        const FaceTab<T> ft(g, i, j);
+        const int col = i + g.nx * j;
+        // plane k0: centre, below, above
+        int a = col + k0 * sz;
+        bool hm, hp;
+        int om = zoff(k0, -1, g.nz, g.pz, sz, hm);
+        int op = zoff(k0, 1, g.nz, g.pz, sz, hp);
+        T xc = x[a], rc = rho[a];
+        T xm = x[a + om];
+        T wzm = hm ? g.cz * face_kappa(rc, rho[a + om]) : T(0);
+        T xn = x[a + op], rn = rho[a + op];
+        T czp = hp ? g.cz : T(0);
+        T xv[4], rv[4], mv, bv = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xv[q] = x[a + ft.o[q]];
+            rv[q] = rho[a + ft.o[q]];
         }
-        int kp = zplane(k0, 1, g.nz, g.pz);
-        T xn = T(0), rn = T(0);
-        if (kp >= 0) {
-            xn = xc_p[kp * sz];
-            rn = rc_p[kp * sz];
-        }
+        mv = m[a];
+        if (MODE >= 2) bv = b[a];
         for (int k = k0; k < k1; ++k) {
-            const int64_t a = col + k * sz;
-            T acc = m[a] * xc;
-            if (nb.hxm) acc += g.cx * face_kappa(rc, rho[a + nb.oxm]) * (xc - x[a + nb.oxm]);
-            if (nb.hxp) acc += g.cx * face_kappa(rc, rho[a + nb.oxp]) * (xc - x[a + nb.oxp]);
-            if (nb.hym) acc += g.cy * face_kappa(rc, rho[a + nb.oym]) * (xc - x[a + nb.oym]);
-            if (nb.hyp) acc += g.cy * face_kappa(rc, rho[a + nb.oyp]) * (xc - x[a + nb.oyp]);
-            if (km >= 0) acc += wzm * (xc - xm);
-            T wzp = T(0);
-            if (kp >= 0) {
-                wzp = g.cz * face_kappa(rc, rn);
-                acc += wzp * (xc - xn);
+            // prefetch plane k+1 (clamped to the chunk) and the column two planes up
+            const int kn = min(k + 1, k1 - 1);
+            const int an = col + kn * sz;
+            bool hpn;
+            const int opn = zoff(kn, 1, g.nz, g.pz, sz, hpn);
+            T xvn[4], rvn[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                xvn[q] = x[an + ft.o[q]];
+                rvn[q] = rho[an + ft.o[q]];
             }
-            if (MODE >= 2) acc = b[a] - acc;
+            const T mvn = m[an];
+            const T bvn = (MODE >= 2) ? b[an] : T(0);
+            const T xnn = x[an + opn], rnn = rho[an + opn];
+            // plane k
+            T acc = mv * xc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc += ft.c[q] * face_kappa(rc, rv[q]) * (xc - xv[q]);
+            acc += wzm * (xc - xm);
+            const T wzp = czp * face_kappa(rc, rn);
+            acc += wzp * (xc - xn);
+            if (MODE >= 2) acc = bv - acc;
             y[a] = acc;
             if (MODE == 1) part += (double)xc * (double)acc;
             if (MODE == 3) part += (double)acc * (double)acc;
-            // advance one plane: the z+ face of plane k is the z- face of plane k+1
-            km = (kp >= 0) ? k : -1;
+            // advance: the z+ face of plane k is the z- face of plane k+1
             wzm = wzp;
             xm = xc;
             xc = xn;
             rc = rn;
-            if (k + 1 < k1) {
-                kp = zplane(k + 1, 1, g.nz, g.pz);
-                if (kp >= 0) {
-                    xn = xc_p[kp * sz];
-                    rn = rc_p[kp * sz];
-                }
+            xn = xnn;
+            rn = rnn;
+            czp = hpn ? g.cz : T(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                xv[q] = xvn[q];
+                rv[q] = rvn[q];
             }
+            mv = mvn;
+            bv = bvn;
+            a = an;
         }
     }
     if (MODE == 1 || MODE == 3) block_partial(part, partials);
@@ -482,8 +526,10 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zero(Geo<T> g, const T* __restr
 // Z-marching red-black half sweep: each thread owns the cell pair (i0, i0+1) of one row and
 // updates, plane by plane, the member of colour `colour` (the colour alternates with k). The
 // z neighbours of the updated cell are the other-colour cells of the pairs one plane up and
-// down, which this sweep never writes, so they are kept in registers. ZERO: first red sweep from
-// z = 0 (red cells r / D, black cells 0; no z loads).
+// down, which this sweep never writes, so they are kept in registers. The loads of plane k+1
+// (the in-plane neighbours of its active member, its r and m, the pair two planes up) are
+// issued before plane k is computed. ZERO: first red sweep from z = 0 (red cells r / D, black
+// cells 0; no z loads).
 template <typename T, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
@@ -497,99 +543,102 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
     if (i0 >= g.nx || j >= g.ny) return;
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
-    const int64_t sz = (int64_t)g.nx * g.ny;
-    const bool has1 = i0 + 1 < g.nx;
-    const PlaneNb<T> nb0(g, i0, j), nb1(g, has1 ? i0 + 1 : i0, j);
-    const int64_t col = i0 + (int64_t)g.nx * j;
-    // pair values at planes k-1 (m), k (c), k+1 (n)
-    T rm0 = T(0), rm1 = T(0), rc0, rc1 = T(0), rn0 = T(0), rn1 = T(0);
-    T zm0 = T(0), zm1 = T(0), zc0 = T(0), zc1 = T(0), zn0 = T(0), zn1 = T(0);
-    int km = zplane(k0, -1, g.nz, g.pz);
-    int kp = zplane(k0, 1, g.nz, g.pz);
-    rc0 = rho[col + k0 * sz];
-    if (has1) rc1 = rho[col + 1 + k0 * sz];
+    const int sz = g.nx * g.ny;
+    const int d1 = (i0 + 1 < g.nx) ? 1 : 0;  // 0: the pair has one cell only
+    const FaceTab<T> f0(g, i0, j), f1(g, i0 + d1, j);
+    const int col = i0 + g.nx * j;
+    int a = col + k0 * sz;
+    bool hm, hp;
+    const int om = zoff(k0, -1, g.nz, g.pz, sz, hm);
+    const int op = zoff(k0, 1, g.nz, g.pz, sz, hp);
+    T czm = hm ? g.cz : T(0), czp = hp ? g.cz : T(0);
+    // the pair at planes k-1 (m), k (c), k+1 (n)
+    T rc0 = rho[a], rc1 = rho[a + d1];
+    T rm0 = rho[a + om], rm1 = rho[a + om + d1];
+    T rn0 = rho[a + op], rn1 = rho[a + op + d1];
+    T zc0 = T(0), zc1 = T(0), zm0 = T(0), zm1 = T(0), zn0 = T(0), zn1 = T(0);
     if (!ZERO) {
-        zc0 = z[col + k0 * sz];
-        if (has1) zc1 = z[col + 1 + k0 * sz];
+        zc0 = z[a]; zc1 = z[a + d1];
+        zm0 = z[a + om]; zm1 = z[a + om + d1];
+        zn0 = z[a + op]; zn1 = z[a + op + d1];
     }
-    if (km >= 0) {
-        rm0 = rho[col + km * sz];
-        if (has1) rm1 = rho[col + 1 + km * sz];
-        if (!ZERO) {
-            zm0 = z[col + km * sz];
-            if (has1) zm1 = z[col + 1 + km * sz];
+    int sel = (colour + j + k0) & 1;  // i0 is even: the active member of plane k0
+    int o[4];
+    T cf[4], rv[4], zv[4], rr, mm;
+    {
+        const int act = a + (sel & d1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[q] = sel ? f1.o[q] : f0.o[q];
+            cf[q] = sel ? f1.c[q] : f0.c[q];
+            rv[q] = rho[act + o[q]];
+            zv[q] = ZERO ? T(0) : z[act + o[q]];
         }
-    }
-    if (kp >= 0) {
-        rn0 = rho[col + kp * sz];
-        if (has1) rn1 = rho[col + 1 + kp * sz];
-        if (!ZERO) {
-            zn0 = z[col + kp * sz];
-            if (has1) zn1 = z[col + 1 + kp * sz];
-        }
+        rr = r[act];
+        mm = m[act];
     }
     for (int k = k0; k < k1; ++k) {
-        const int sel = (colour + j + k) & 1;  // i0 is even
-        if (sel == 0 || has1) {
-            const PlaneNb<T>& nb = sel ? nb1 : nb0;
-            const int64_t a = col + sel + k * sz;
-            const T ra = sel ? rc1 : rc0;
-            T sw = T(0), swz = T(0);
-            if (nb.hxm) {
-                T w = g.cx * face_kappa(ra, rho[a + nb.oxm]);
-                sw += w;
-                if (!ZERO) swz += w * z[a + nb.oxm];
-            }
-            if (nb.hxp) {
-                T w = g.cx * face_kappa(ra, rho[a + nb.oxp]);
-                sw += w;
-                if (!ZERO) swz += w * z[a + nb.oxp];
-            }
-            if (nb.hym) {
-                T w = g.cy * face_kappa(ra, rho[a + nb.oym]);
-                sw += w;
-                if (!ZERO) swz += w * z[a + nb.oym];
-            }
-            if (nb.hyp) {
-                T w = g.cy * face_kappa(ra, rho[a + nb.oyp]);
-                sw += w;
-                if (!ZERO) swz += w * z[a + nb.oyp];
-            }
-            if (km >= 0) {
-                T w = g.cz * face_kappa(ra, sel ? rm1 : rm0);
-                sw += w;
-                if (!ZERO) swz += w * (sel ? zm1 : zm0);
-            }
-            if (kp >= 0) {
-                T w = g.cz * face_kappa(ra, sel ? rn1 : rn0);
-                sw += w;
-                if (!ZERO) swz += w * (sel ? zn1 : zn0);
-            }
-            z[a] = (r[a] + swz) / (m[a] + sw);
-            if (ZERO) {
-                const int other = 1 - sel;
-                if (other == 0 || has1) z[col + other + k * sz] = T(0);
-            }
+        const int seln = sel ^ 1;
+        const int kn = min(k + 1, k1 - 1);
+        const int an = col + kn * sz;
+        bool hpn;
+        const int opn = zoff(kn, 1, g.nz, g.pz, sz, hpn);
+        // prefetch plane k+1 (its active member) and the pair two planes up
+        int on[4];
+        T cfn[4], rvn[4], zvn[4];
+        const int actn = an + (seln & d1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            on[q] = seln ? f1.o[q] : f0.o[q];
+            cfn[q] = seln ? f1.c[q] : f0.c[q];
+            rvn[q] = rho[actn + on[q]];
+            zvn[q] = ZERO ? T(0) : z[actn + on[q]];
         }
+        const T rrn = r[actn], mmn = m[actn];
+        const T rnn0 = rho[an + opn], rnn1 = rho[an + opn + d1];
+        T znn0 = T(0), znn1 = T(0);
+        if (!ZERO) {
+            znn0 = z[an + opn];
+            znn1 = z[an + opn + d1];
+        }
+        // plane k: update the active member
+        const T ra = sel ? rc1 : rc0;
+        T sw = T(0), swz = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T w = cf[q] * face_kappa(ra, rv[q]);
+            sw += w;
+            swz += w * zv[q];
+        }
+        const T wzm = czm * face_kappa(ra, sel ? rm1 : rm0);
+        const T wzp = czp * face_kappa(ra, sel ? rn1 : rn0);
+        sw += wzm + wzp;
+        swz += wzm * (sel ? zm1 : zm0) + wzp * (sel ? zn1 : zn0);
+        const T znew = (rr + swz) / (mm + sw);
+        if (sel == 0 || d1) z[a + sel] = znew;
+        if (ZERO && (seln == 0 || d1)) z[a + seln] = T(0);
         // advance one plane. At plane k+1 the other pair member is updated; its z neighbours
         // are the members of planes k and k+2 that this sweep does not write, so the register
         // copies stay valid (the updated member's stale copy is never read again).
-        km = (kp >= 0) ? k : -1;
+        czm = czp;
+        czp = hpn ? g.cz : T(0);
         rm0 = rc0; rm1 = rc1;
         rc0 = rn0; rc1 = rn1;
+        rn0 = rnn0; rn1 = rnn1;
         zm0 = zc0; zm1 = zc1;
         zc0 = zn0; zc1 = zn1;
-        if (k + 1 < k1) {
-            kp = zplane(k + 1, 1, g.nz, g.pz);
-            if (kp >= 0) {
-                rn0 = rho[col + kp * sz];
-                if (has1) rn1 = rho[col + 1 + kp * sz];
-                if (!ZERO) {
-                    zn0 = z[col + kp * sz];
-                    if (has1) zn1 = z[col + 1 + kp * sz];
-                }
-            }
+        zn0 = znn0; zn1 = znn1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[q] = on[q];
+            cf[q] = cfn[q];
+            rv[q] = rvn[q];
+            zv[q] = zvn[q];
         }
+        rr = rrn;
+        mm = mmn;
+        sel = seln;
+        a = an;
     }
 }
 
