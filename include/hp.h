@@ -64,7 +64,9 @@ enum {
 enum {
     HP_MODE_JACOBI_PCG = 0,  /* FP64 CG with diagonal preconditioner */
     HP_MODE_FP64_MGPCG = 1,  /* FP64 CG preconditioned by one geometric-multigrid V-cycle */
-    HP_MODE_MIXED_IR = 2     /* FP64 iterative refinement around an FP32 MG-PCG inner solve */
+    HP_MODE_MIXED_IR = 2,    /* FP64 iterative refinement around an FP32 MG-PCG inner solve */
+    HP_MODE_LEARNED = 3      /* FP64 flexible CG, preconditioner = network then V-cycle (needs
+                                hp_attach_net); stops on the same FP64 true residual */
 };
 
 /* Option keys for hp_set_option / hp_get_option. */
@@ -183,6 +185,57 @@ int hp_residual(hp_handle* h, const double* rhs, const double* p, double* r, dou
 
 /* Deterministic FP64 dot product of device vectors of n entries (synchronises the stream). */
 int hp_dot(hp_handle* h, const double* x, const double* y, long long n, double* out);
+
+/* ---- Learned warm start / preconditioner -------------------------------------------------
+ * A small 3D U-Net (levels n, n/2, n/4 with 16/32/64 channels, 3x3x3 convolutions padded
+ * periodically in x, y and with zeros in z, 2x2x2 mean pooling, nearest upsampling, skip
+ * concatenations, ReLU, 1x1x1 output head) in bfloat16 on the matrix cores with FP32
+ * accumulation. Its input per cell is (b/s, log rho, log c2, p_prev/s) with s = RMS(b); its
+ * output y gives the estimate x = s * out_scale * y of the solution of A x = b. Not part of the
+ * paper's method: it stands beside the multigrid solver, which remains the judge of accuracy.
+ *
+ * Parameters: one flat FP32 device vector of hp_nn_num_params() entries; per convolution
+ * W[o][t][c] (c fastest) then bias[o], in the order in->16, 16->16, 16->32, 32->32, 32->64,
+ * 64->64, 96->32, 32->32, 48->16, 16->16 (taps t = (dz+1)*9 + (dy+1)*3 + (dx+1)); then the head
+ * weights [16] and bias. Activations are channels-last ([cell][channel]).
+ */
+typedef struct hp_net hp_net;
+
+long long hp_nn_num_params(void);
+
+/* Network workspace for an nx x ny x nz grid (each a multiple of 4); training != 0 also
+ * allocates gradients and Adam state. Parameters start at zero. */
+int hp_nn_create(int nx, int ny, int nz, int training, hp_net** out);
+void hp_nn_free(hp_net* net);
+int hp_nn_set_stream(hp_net* net, void* stream);
+const char* hp_nn_last_error(void);
+
+/* Copy parameters in/out (device FP32, hp_nn_num_params() entries). */
+int hp_nn_set_params(hp_net* net, const float* params);
+int hp_nn_get_params(hp_net* net, float* params);
+int hp_nn_get_grad(hp_net* net, float* grad);
+int hp_nn_set_output_scale(hp_net* net, double out_scale);
+
+/* x = s * out_scale * net(b/s, log rho, log c2, p_prev/s); p_prev may be NULL (zeros).
+ * All device FP64 cell arrays. */
+int hp_nn_forward(hp_net* net, const double* b, const double* rho, const double* c2,
+                  const double* p_prev, double* x);
+
+/* One Adam step (lr) on the mean squared error between the network output and
+ * x_target / (s * out_scale); *loss receives the loss before the step (synchronises). */
+int hp_nn_train_step(hp_net* net, const double* b, const double* rho, const double* c2,
+                     const double* p_prev, const double* x_target, float lr, double* loss);
+
+/* Raw access for verification: input features [cell][8] bfloat16 (channels 4..7 zero) ->
+ * y [cell] FP32; loss and parameter gradient of mean (y - target)^2 (hp_nn_get_grad);
+ * Adam step with the current gradient. */
+int hp_nn_forward_raw(hp_net* net, const unsigned short* in, float* y);
+int hp_nn_loss_grad_raw(hp_net* net, const unsigned short* in, const float* target, double* loss);
+int hp_nn_adam(hp_net* net, float lr);
+
+/* Use `net` (same grid as the handle; NULL detaches) in HP_MODE_LEARNED. Allocates two work
+ * vectors of the fine grid. */
+int hp_attach_net(hp_handle* h, hp_net* net);
 
 #ifdef __cplusplus
 }

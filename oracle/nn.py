@@ -132,22 +132,31 @@ def up2_backward(g: np.ndarray) -> np.ndarray:
     return 8.0 * pool2(g)
 
 
-def forward(theta: np.ndarray, inp: np.ndarray, keep: bool = False):
-    """y (nz, ny, nx) from inp (nz, ny, nx, 4). With keep, also the activations for backward."""
+def forward(theta: np.ndarray, inp: np.ndarray, keep: bool = False, bf16: bool = False):
+    """y (nz, ny, nx) from inp (nz, ny, nx, 4). With keep, also the activations for backward.
+
+    bf16=True rounds to bfloat16 where a bfloat16 pipeline stores values: the input features,
+    the convolution weights (not the biases or the head), every convolution output after the
+    ReLU and every pooled tensor. The arithmetic itself stays FP64.
+    """
+    R = bf16_round if bf16 else (lambda a: a)
     layers, w_out, b_out = unpack(theta)
+    if bf16:
+        layers = [(R(W), b) for W, b in layers]
     acts = {}
 
     def cr(name, x, li):
         W, b = layers[li]
         pre = conv3(x, W, b)
-        out = np.maximum(pre, 0.0)
+        out = R(np.maximum(pre, 0.0))
         acts[name] = (x, out)
         return out
 
+    inp = R(inp)
     e1 = cr("c1", cr("c0", inp, 0), 1)
-    p1 = pool2(e1)
+    p1 = R(pool2(e1))
     e2 = cr("c3", cr("c2", p1, 2), 3)
-    p2 = pool2(e2)
+    p2 = R(pool2(e2))
     e3 = cr("c5", cr("c4", p2, 4), 5)
     u3 = np.concatenate([up2(e3), e2], axis=-1)
     d2 = cr("c7", cr("c6", u3, 6), 7)
@@ -156,13 +165,21 @@ def forward(theta: np.ndarray, inp: np.ndarray, keep: bool = False):
     y = d1 @ w_out + b_out
     if keep:
         acts["d1"] = d1
+        acts["layers"] = layers
+        acts["bf16"] = bf16
         return y, acts
     return y
 
 
 def backward(theta: np.ndarray, acts, gy: np.ndarray) -> np.ndarray:
-    """Gradient of sum(gy * y) with respect to the flat parameters."""
-    layers, w_out, b_out = unpack(theta)
+    """Gradient of sum(gy * y) with respect to the flat parameters.
+
+    When the forward pass rounded to bfloat16, the masked gradient at each convolution output
+    (the operand of both backward convolutions) is rounded too; bias gradients use it unrounded.
+    """
+    _, w_out, b_out = unpack(theta)
+    layers = acts["layers"]
+    R = bf16_round if acts["bf16"] else (lambda a: a)
     grads = [None] * len(CONVS)
     d1 = acts["d1"]
     g_wout = np.einsum("kji,kjic->c", gy, d1)
@@ -171,9 +188,9 @@ def backward(theta: np.ndarray, acts, gy: np.ndarray) -> np.ndarray:
 
     def back(name, li, g_out):
         x, out = acts[name]
-        gpre = g_out * (out > 0)
-        gx, gW, gb = conv3_backward(x, layers[li][0], gpre)
-        grads[li] = (gW, gb)
+        pre = g_out * (out > 0)
+        gx, gW, _ = conv3_backward(x, layers[li][0], R(pre))
+        grads[li] = (gW, pre.sum(axis=(0, 1, 2)))
         return gx
 
     g = back("c8", 8, back("c9", 9, g))               # -> gradient of u2 (48 ch)
@@ -188,9 +205,9 @@ def backward(theta: np.ndarray, acts, gy: np.ndarray) -> np.ndarray:
     return pack(grads, g_wout, g_bout)
 
 
-def loss_and_grad(theta, inp, target):
+def loss_and_grad(theta, inp, target, bf16: bool = False):
     """Mean squared error over voxels and its parameter gradient."""
-    y, acts = forward(theta, inp, keep=True)
+    y, acts = forward(theta, inp, keep=True, bf16=bf16)
     diff = y - target
     nvox = diff.size
     loss = float(np.sum(diff * diff) / nvox)

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhp.so")
 
 PERIODIC, NEUMANN = 0, 1
-MODE_JACOBI_PCG, MODE_FP64_MGPCG, MODE_MIXED_IR = 0, 1, 2
+MODE_JACOBI_PCG, MODE_FP64_MGPCG, MODE_MIXED_IR, MODE_LEARNED = 0, 1, 2, 3
 OPT_MODE, OPT_MAX_ITER, OPT_NU_PRE, OPT_NU_POST = 1, 2, 3, 4
 OPT_INNER_TOL, OPT_MAX_OUTER, OPT_COARSEST_MAX = 5, 6, 7
 
@@ -32,6 +32,10 @@ EXPORTS = [
     "hp_apply", "hp_apply_f32", "hp_smooth", "hp_smooth_f32", "hp_restrict_residual",
     "hp_restrict_residual_f32", "hp_prolong_add", "hp_prolong_add_f32", "hp_coarse_solve",
     "hp_coarse_solve_f32", "hp_precond", "hp_precond_f32", "hp_residual", "hp_dot",
+    "hp_nn_num_params", "hp_nn_create", "hp_nn_free", "hp_nn_set_stream", "hp_nn_last_error",
+    "hp_nn_set_params", "hp_nn_get_params", "hp_nn_get_grad", "hp_nn_set_output_scale",
+    "hp_nn_forward", "hp_nn_train_step", "hp_nn_forward_raw", "hp_nn_loss_grad_raw", "hp_nn_adam",
+    "hp_attach_net",
 ]
 
 
@@ -103,6 +107,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                 "hp_precond_f32": (ip, [H, fp, fp]),
                 "hp_residual": (ip, [H, dp, dp, dp, ctypes.POINTER(ctypes.c_double)]),
                 "hp_dot": (ip, [H, dp, dp, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double)]),
+                "hp_nn_num_params": (ctypes.c_longlong, []),
+                "hp_nn_create": (ip, [ip, ip, ip, ip, ctypes.POINTER(ctypes.c_void_p)]),
+                "hp_nn_free": (None, [vp]),
+                "hp_nn_set_stream": (ip, [vp, vp]),
+                "hp_nn_last_error": (ctypes.c_char_p, []),
+                "hp_nn_set_params": (ip, [vp, vp]),
+                "hp_nn_get_params": (ip, [vp, vp]),
+                "hp_nn_get_grad": (ip, [vp, vp]),
+                "hp_nn_set_output_scale": (ip, [vp, ctypes.c_double]),
+                "hp_nn_forward": (ip, [vp, dp, dp, dp, dp, dp]),
+                "hp_nn_train_step": (ip, [vp, dp, dp, dp, dp, dp, ctypes.c_float,
+                                          ctypes.POINTER(ctypes.c_double)]),
+                "hp_nn_forward_raw": (ip, [vp, vp, vp]),
+                "hp_nn_loss_grad_raw": (ip, [vp, vp, vp, ctypes.POINTER(ctypes.c_double)]),
+                "hp_nn_adam": (ip, [vp, ctypes.c_float]),
+                "hp_attach_net": (ip, [H, vp]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -115,6 +135,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
 def _check(rc: int):
     if rc != OK:
         msg = load_library().hp_last_error()
+        raise HPError(rc, msg.decode() if msg else "")
+
+
+def _check_nn(rc: int):
+    if rc != OK:
+        msg = load_library().hp_nn_last_error()
         raise HPError(rc, msg.decode() if msg else "")
 
 
@@ -267,6 +293,98 @@ class Solver:
         _check(self._lib.hp_dot(self._h, _ptr(x, "f64", n, self.device),
                                 _ptr(y, "f64", n, self.device), n, ctypes.byref(out)))
         return out.value
+
+    def attach_net(self, net):
+        self._net = net
+        _check(self._lib.hp_attach_net(self._h, net._h if net is not None else None))
+
+
+def num_params() -> int:
+    return int(load_library().hp_nn_num_params())
+
+
+class Net:
+    """Handle around the learned warm start / preconditioner network (hp_nn_*)."""
+
+    def __init__(self, n, training: bool = False):
+        torch = _torch()
+        lib = load_library()
+        self._lib = lib
+        self.n = tuple(int(v) for v in n)
+        self.ncells = self.n[0] * self.n[1] * self.n[2]
+        self.device = torch.cuda.current_device()
+        self.nparam = num_params()
+        h = ctypes.c_void_p()
+        _check_nn(lib.hp_nn_create(self.n[0], self.n[1], self.n[2], 1 if training else 0,
+                                   ctypes.byref(h)))
+        self._h = h
+        _check_nn(lib.hp_nn_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hp_nn_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _p(self, t, kind, numel):
+        torch = _torch()
+        want = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[kind]
+        if t.dtype != want or t.device.type != "cuda" or not t.is_contiguous() or t.numel() != numel:
+            raise ValueError("expected a contiguous %s cuda tensor of %d entries" % (want, numel))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_params(self, theta):
+        _check_nn(self._lib.hp_nn_set_params(self._h, self._p(theta, "f32", self.nparam)))
+
+    def get_params(self):
+        torch = _torch()
+        out = torch.empty(self.nparam, dtype=torch.float32, device="cuda")
+        _check_nn(self._lib.hp_nn_get_params(self._h, self._p(out, "f32", self.nparam)))
+        return out
+
+    def get_grad(self):
+        torch = _torch()
+        out = torch.empty(self.nparam, dtype=torch.float32, device="cuda")
+        _check_nn(self._lib.hp_nn_get_grad(self._h, self._p(out, "f32", self.nparam)))
+        return out
+
+    def set_output_scale(self, s: float):
+        _check_nn(self._lib.hp_nn_set_output_scale(self._h, float(s)))
+
+    def forward(self, b, rho, c2, p_prev, x):
+        n = self.ncells
+        _check_nn(self._lib.hp_nn_forward(self._h, self._p(b, "f64", n), self._p(rho, "f64", n),
+                                          self._p(c2, "f64", n),
+                                          self._p(p_prev, "f64", n) if p_prev is not None else None,
+                                          self._p(x, "f64", n)))
+
+    def train_step(self, b, rho, c2, p_prev, x_target, lr: float) -> float:
+        n = self.ncells
+        loss = ctypes.c_double()
+        _check_nn(self._lib.hp_nn_train_step(
+            self._h, self._p(b, "f64", n), self._p(rho, "f64", n), self._p(c2, "f64", n),
+            self._p(p_prev, "f64", n) if p_prev is not None else None, self._p(x_target, "f64", n),
+            float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def forward_raw(self, inp_bf16, y):
+        _check_nn(self._lib.hp_nn_forward_raw(self._h, self._p(inp_bf16, "bf16", self.ncells * 8),
+                                              self._p(y, "f32", self.ncells)))
+
+    def loss_grad_raw(self, inp_bf16, target) -> float:
+        loss = ctypes.c_double()
+        _check_nn(self._lib.hp_nn_loss_grad_raw(self._h, self._p(inp_bf16, "bf16", self.ncells * 8),
+                                                self._p(target, "f32", self.ncells),
+                                                ctypes.byref(loss)))
+        return loss.value
+
+    def adam(self, lr: float):
+        _check_nn(self._lib.hp_nn_adam(self._h, float(lr)))
 
 
 def setup(n, h, bc, rho, c2, dt, mode=None) -> Solver:

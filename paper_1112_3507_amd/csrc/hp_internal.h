@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "hp.h"
+
 namespace hp {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
@@ -104,6 +106,18 @@ template <typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
 // flag nonzero if any entry is not finite
 void launch_check_finite(const double* x, int64_t n, int* bad, hipStream_t s);
+
+// y = a x + b y
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+// scal[slot] = value (stream-ordered, graph-safe)
+void launch_set_scalar(double* scal, int slot, double value, hipStream_t s);
+
+// ---- learned stage (hp_nn.hip) ----
+int nn_grid(const hp_net* net, int* nx, int* ny, int* nz);
+// z = s * out_scale * net(r / s, log rho, -log(rho m), 0), s = RMS(r)
+int nn_apply(hp_net* net, hipStream_t stream, const double* r, const double* rho, const double* m,
+             double* z);
+const char* nn_error();
 
 // Number of workgroups the reducing kernels use for these sizes (partials capacity).
 int64_t reduce_blocks_cells(int nx, int ny, int nz);

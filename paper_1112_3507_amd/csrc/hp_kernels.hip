@@ -947,6 +947,24 @@ void launch_check_finite(const double* x, int64_t n, int* bad, hipStream_t s) {
                        0, s, x, n, bad);
 }
 
+__global__ __launch_bounds__(kBlock) void k_axpby(double a, const double* __restrict__ x, double b,
+                                                  double* __restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a, x,
+                       b, y, n);
+}
+
+__global__ void k_set_scalar(double* scal, int slot, double v) { scal[slot] = v; }
+
+void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, scal, slot, value);
+}
+
 // ------------------------------------------------------------------------------------------
 // explicit instantiations
 

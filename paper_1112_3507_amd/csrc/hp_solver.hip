@@ -91,6 +91,9 @@ struct hp_handle {
     int max_outer = 20;
     int coarsest_max = 512;
     hp_stats stats{};
+    // learned stage
+    hp_net* net = nullptr;
+    double *w1 = nullptr, *w2 = nullptr;
 };
 
 namespace {
@@ -449,6 +452,109 @@ int mixed_ir(hp_handle* H, const double* b, double* x, double tol, double bnorm)
                 st.rel_residual);
 }
 
+// Flexible CG (Notay's FCG with one stored direction) with the preconditioner
+// B(r) = g z1 + M (r - g A z1), z1 = network estimate of A^-1 r, M = one V-cycle, and
+// g = <r, z1> / <z1, A z1> the step that minimises the A-norm error of g z1 (0 if the network
+// points uphill or returns non-finite values), so the network stage never makes the
+// correction worse than the V-cycle alone. The network makes B nonlinear, so
+// beta = -<z, q_prev> / <p_prev, q_prev> keeps the new direction A-orthogonal to the previous
+// one. If the residual stops falling (less than 10x over 10 iterations) the solve finishes with
+// plain FP64 MG-PCG from the current iterate. Stops on the same FP64 true residual as the other
+// modes.
+int fcg_learned(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
+    if (!H->net) return fail(HP_EINVAL, "HP_MODE_LEARNED needs a network (hp_attach_net)");
+    LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    Geo<double> g = geo<double>(H, F);
+    hipStream_t s = H->stream;
+    hp_stats& st = H->stats;
+    auto dot = [&](const double* u, const double* v, double* out) -> int {
+        launch_dot<double>(u, v, N, red(H, OP_STORE, S_TMP), s);
+        CHK(check_launch());
+        CHK(read_scalars(H));
+        *out = H->host_scal[S_TMP];
+        return HP_OK;
+    };
+    auto precond = [&](const double* r, double* z) -> int {
+        int rc = nn_apply(H->net, s, r, F.rho, F.m, H->w1);
+        if (rc) return fail(rc, "network: %s", nn_error());
+        launch_apply<double>(g, F.rho, F.m, H->w1, nullptr, H->w2, 0, red(H, OP_NONE), s);
+        double rz1, z1az1;
+        CHK(dot(r, H->w1, &rz1));
+        CHK(dot(H->w1, H->w2, &z1az1));
+        double gam = (rz1 > 0.0 && z1az1 > 0.0 && std::isfinite(rz1) && std::isfinite(z1az1))
+                         ? rz1 / z1az1 : 0.0;
+        launch_axpby(1.0, r, -gam, H->w2, N, s);  // w2 = r - g A z1 (= r when g = 0)
+        if (gam == 0.0) launch_copy<double>(r, H->w2, N, s);
+        vcycle<double>(H, 0, H->w2, z);
+        if (gam != 0.0) launch_axpby(gam, H->w1, 1.0, z, N, s);
+        return check_launch();
+    };
+    std::vector<double> hist;
+    bool restart = true;
+    double pq = 0.0;
+    while (true) {
+        if (restart) {
+            CHK(precond(H->r, H->z));
+            launch_copy<double>(H->z, H->p, N, s);
+            launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_STORE, S_PQ), s);
+            CHK(check_launch());
+            CHK(read_scalars(H));
+            pq = H->host_scal[S_PQ];
+            restart = false;
+        }
+        if (!(pq > 0.0) || !std::isfinite(pq)) return fail(HP_EBREAKDOWN, "FCG breakdown: p^T A p <= 0");
+        double pr;
+        CHK(dot(H->p, H->r, &pr));
+        launch_set_scalar(H->scal, S_ALPHA, pr / pq, s);
+        launch_axpy2_norm<double>(x, H->p, H->r, H->q, N, red(H, OP_STORE, S_RR), s);
+        CHK(check_launch());
+        CHK(read_scalars(H));
+        st.iterations++;
+        double rr = H->host_scal[S_RR];
+        if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite residual in iteration %d", st.iterations);
+        if (std::sqrt(rr) <= tol * bnorm) {
+            double rel;
+            CHK(true_residual(H, b, x, H->z, bnorm, &rel));
+            st.rel_residual = rel;
+            if (rel <= tol) {
+                st.converged = 1;
+                return HP_OK;
+            }
+            launch_copy<double>(H->z, H->r, N, s);
+            st.restarts++;
+            restart = true;
+            if (st.iterations >= H->max_iter) break;
+            continue;
+        }
+        if (st.iterations >= H->max_iter) break;
+        hist.push_back(std::sqrt(rr));
+        if (hist.size() > 10 && hist.back() > 0.1 * hist[hist.size() - 11]) {
+            // the learned stage is not helping: finish with plain FP64 MG-PCG (r is current)
+            st.fallback = 1;
+            int saved = H->mode;
+            H->mode = HP_MODE_FP64_MGPCG;
+            int rc = pcg64(H, b, x, tol, bnorm);
+            H->mode = saved;
+            return rc;
+        }
+        CHK(precond(H->r, H->z));
+        double zq;
+        CHK(dot(H->z, H->q, &zq));
+        launch_set_scalar(H->scal, S_BETA, -zq / pq, s);
+        launch_xpby<double>(H->z, H->p, N, H->scal, s);
+        launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_STORE, S_PQ), s);
+        CHK(check_launch());
+        CHK(read_scalars(H));
+        pq = H->host_scal[S_PQ];
+    }
+    double rel;
+    CHK(true_residual(H, b, x, H->z, bnorm, &rel));
+    st.rel_residual = rel;
+    return fail(HP_ENOCONV, "no convergence in %d iterations (relative residual %.3e)",
+                st.iterations, rel);
+}
+
 int level_ok(const hp_handle* H, int level) {
     if (!H) return fail(HP_EINVAL, "null handle");
     if (level < 0 || level >= (int)H->lv.size()) return fail(HP_EINVAL, "level %d out of range", level);
@@ -649,7 +755,8 @@ int hp_set_option(hp_handle* H, int key, double v) {
     if (!H) return fail(HP_EINVAL, "null handle");
     switch (key) {
         case HP_OPT_MODE:
-            if (v != HP_MODE_JACOBI_PCG && v != HP_MODE_FP64_MGPCG && v != HP_MODE_MIXED_IR)
+            if (v != HP_MODE_JACOBI_PCG && v != HP_MODE_FP64_MGPCG && v != HP_MODE_MIXED_IR &&
+                v != HP_MODE_LEARNED)
                 return fail(HP_EINVAL, "unknown mode");
             H->mode = (int)v;
             return HP_OK;
@@ -740,6 +847,8 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
         rc = HP_OK;
     } else if (H->mode == HP_MODE_MIXED_IR) {
         rc = mixed_ir(H, b, x, tol, bnorm);
+    } else if (H->mode == HP_MODE_LEARNED) {
+        rc = fcg_learned(H, b, x, tol, bnorm);
     } else {
         rc = pcg64(H, b, x, tol, bnorm);
     }
@@ -796,6 +905,24 @@ int hp_residual(hp_handle* H, const double* b, const double* x, double* r, doubl
         double bb = H->host_scal[S_BB];
         *rel = bb > 0.0 ? std::sqrt(H->host_scal[S_RR] / bb) : std::sqrt(H->host_scal[S_RR]);
     }
+    return HP_OK;
+}
+
+int hp_attach_net(hp_handle* H, hp_net* net) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    if (net) {
+        int nx, ny, nz;
+        nn_grid(net, &nx, &ny, &nz);
+        const LevelData& F = H->lv[0];
+        if (nx != F.n[0] || ny != F.n[1] || nz != F.n[2])
+            return fail(HP_EINVAL, "network grid %dx%dx%d differs from the solver grid %dx%dx%d", nx, ny,
+                        nz, F.n[0], F.n[1], F.n[2]);
+        if (!H->w1) {
+            int rc;
+            if ((rc = dalloc(H, &H->w1, F.N)) || (rc = dalloc(H, &H->w2, F.N))) return rc;
+        }
+    }
+    H->net = net;
     return HP_OK;
 }
 

@@ -1,0 +1,150 @@
+"""GPU checks of the learned warm start / preconditioner against the FP64 network oracle.
+
+Forward and gradient parity use inputs and weights rounded to bfloat16 and the oracle's
+bfloat16-emulating mode (it rounds activations, pooled tensors and masked gradients at the same
+points as the GPU pipeline), so what remains is FP32 (MFMA) versus FP64 accumulation order plus
+the rare bfloat16 rounding flips it causes: ~1e-3 relative on outputs, a few 1e-3 on gradients.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import nn
+from paper_1112_3507_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP GPU")]
+
+import paper_1112_3507_amd as hp  # noqa: E402
+
+DEV = "cuda:0"
+SHAPE = (8, 8, 16)     # (nz, ny, nx)
+N3 = (16, 8, 8)        # (nx, ny, nz)
+
+
+def _inputs(seed):
+    rng = np.random.default_rng(seed)
+    theta = (nn.init_params(seed) + 0.02 * rng.standard_normal(nn.num_params())).astype(np.float32)
+    inp = nn.bf16_round(rng.standard_normal(SHAPE + (4,)))
+    target = rng.standard_normal(SHAPE).astype(np.float32)
+    return theta, inp, target
+
+
+def _dev_inp(inp):
+    x8 = np.zeros(SHAPE + (8,), dtype=np.float32)
+    x8[..., :4] = inp
+    return torch.from_numpy(x8).to(DEV).to(torch.bfloat16).contiguous()
+
+
+def test_param_count_matches_oracle():
+    assert hp.num_params() == nn.num_params()
+
+
+def test_forward_parity_bf16():
+    theta, inp, _ = _inputs(0)
+    net = hp.Net(N3, training=False)
+    net.set_params(torch.from_numpy(theta).to(DEV))
+    y = torch.empty(SHAPE, dtype=torch.float32, device=DEV)
+    net.forward_raw(_dev_inp(inp), y)
+    torch.cuda.synchronize()
+    yg = y.cpu().numpy().astype(np.float64)
+    yr = nn.forward(theta.astype(np.float64), inp, bf16=True)
+    err = np.linalg.norm(yg - yr) / np.linalg.norm(yr)
+    assert err <= 5e-3, err
+    assert np.max(np.abs(yg - yr)) <= 2e-2 * np.max(np.abs(yr))
+    net.close()
+
+
+def test_gradient_parity_bf16_and_adam():
+    theta, inp, target = _inputs(1)
+    net = hp.Net(N3, training=True)
+    net.set_params(torch.from_numpy(theta).to(DEV))
+    loss = net.loss_grad_raw(_dev_inp(inp), torch.from_numpy(target).to(DEV))
+    g = net.get_grad().cpu().numpy().astype(np.float64)
+    loss_r, g_r = nn.loss_and_grad(theta.astype(np.float64), inp, target.astype(np.float64), bf16=True)
+    assert abs(loss - loss_r) <= 2e-3 * loss_r
+    offs = np.cumsum([0] + [27 * a * b + b for a, b in nn.CONVS] + [17])
+    for lo, hi in zip(offs[:-1], offs[1:]):
+        a, b = g[lo:hi], g_r[lo:hi]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        assert rel <= 3e-2 and cos >= 0.999, (lo, rel, cos)
+    # one Adam step from zero moments with the GPU gradient
+    lr = 1e-3
+    net.adam(lr)
+    th1 = net.get_params().cpu().numpy().astype(np.float64)
+    ref, _, _ = nn.adam_step(theta.astype(np.float64), g.astype(np.float32).astype(np.float64),
+                             np.zeros_like(g), np.zeros_like(g), 1, lr)
+    assert np.allclose(th1, ref, rtol=1e-5, atol=2e-8)
+    net.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _training_set(n=32, count=6):
+    """FP64 MG-PCG solutions of random polytropes (index in [1, 2], contrast in [3, 30])."""
+    rng = np.random.default_rng(50)
+    samples = []
+    for q in range(count):
+        idx = rng.uniform(1.0, 2.0)
+        con = rng.uniform(3.0, 30.0)
+        p = wl.polytrope((n, n, n), 0.001, seed=60 + q, contrast=con, index=idx)
+        b = wl.rhs_white(p.n, 70 + q)
+        rho = torch.from_numpy(p.rho).to(DEV)
+        c2 = torch.from_numpy(p.c2).to(DEV)
+        bt = torch.from_numpy(b).to(DEV)
+        x = torch.zeros_like(bt)
+        with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as s:
+            st = s.solve(bt, x, tol=1e-10)
+        assert st["converged"]
+        samples.append((bt, rho, c2, x))
+    return samples
+
+
+def test_training_reduces_loss():
+    torch.manual_seed(0)
+    samples = _training_set()
+    net = hp.Net((32, 32, 32), training=True)
+    theta = nn.init_params(3).astype(np.float32)
+    net.set_params(torch.from_numpy(theta).to(DEV))
+    ratio = np.mean([float(x.norm() / b.norm()) for b, _, _, x in samples])
+    net.set_output_scale(ratio)
+    losses = []
+    for step in range(90):
+        b, rho, c2, x = samples[step % len(samples)]
+        losses.append(net.train_step(b, rho, c2, None, x, 3e-3))
+    first = np.mean(losses[:6])
+    last = np.mean(losses[-6:])
+    assert np.isfinite(last) and last < 0.5 * first, (first, last)
+    net.close()
+
+
+def test_learned_fcg_matches_oracle():
+    n = (80, 24, 40)
+    p = wl.polytrope(n, 0.001, seed=1)
+    b = wl.rhs_white(n, 2)
+    xref, _ = oracle.reference_solve(p.n, p.h, p.bc, p.rho, p.c2, p.dt, b)
+    rho = torch.from_numpy(p.rho).to(DEV)
+    c2 = torch.from_numpy(p.c2).to(DEV)
+    bt = torch.from_numpy(b).to(DEV)
+    net = hp.Net(n, training=False)
+    net.set_params(torch.from_numpy(nn.init_params(5).astype(np.float32)).to(DEV))
+    net.set_output_scale(float(np.linalg.norm(xref) / np.linalg.norm(b)))
+    x = torch.zeros_like(bt)
+    with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt, hp.MODE_LEARNED) as s:
+        s.attach_net(net)
+        st = s.solve(bt, x, tol=1e-10)
+    torch.cuda.synchronize()
+    assert st["converged"] and st["rel_residual"] <= 1e-10
+    err = np.linalg.norm(x.cpu().numpy() - xref) / np.linalg.norm(xref)
+    assert err <= 1e-9, err
+    # the network's own warm start is an initial guess only: the solve still meets the bar
+    x0 = torch.empty_like(bt)
+    net.forward(bt, rho, c2, None, x0)
+    with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as s:
+        st = s.solve(bt, x0, tol=1e-10)
+    assert st["converged"]
+    assert np.linalg.norm(x0.cpu().numpy() - xref) / np.linalg.norm(xref) <= 1e-9
+    net.close()
