@@ -103,6 +103,53 @@ def roofline(solver, n_cells, dev):
             "per_launch_ms": round(times[dom], 5), "kernels": kern}
 
 
+def learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base):
+    """The trained network at 256^3, Ma = 0.001: (a) warm start x0 = g net(b) followed by FP64
+    MG-PCG, timed including the network; (b) flexible CG with the network + V-cycle
+    preconditioner. Both stop on the same FP64 true residual 1e-10."""
+    import torch
+    import paper_1112_3507_amd as hp
+    from paper_1112_3507_amd import train as tr
+    path = os.path.join(ROOT, "paper_1112_3507_amd", "weights", "unet128.npz")
+    if not os.path.exists(path):
+        return None
+    theta, scale = tr.load(path)
+    net = hp.Net(p3.n)
+    net.set_params(torch.from_numpy(theta).to(dev))
+    net.set_output_scale(scale)
+    out = {}
+    s = hp.setup(p3.n, p3.h, p3.bc, rho3, c23, p3.dt, hp.MODE_FP64_MGPCG)
+    s.attach_net(net)
+    for name in ("warm_start", "fcg"):
+        log("bench: Ma=0.001 learned %s" % name)
+        if name == "fcg":
+            s.set_option(hp.OPT_MODE, hp.MODE_LEARNED)
+        stats = []
+        for k in range(W + K):
+            if k == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if name == "warm_start":
+                s.warm_start(rhs[k], x)
+            else:
+                x.zero_()
+            st = s.solve(rhs[k], x, tol=TOL)
+            if k >= W:
+                stats.append(st)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        v = K / secs
+        out[name] = {"value": round(v, 3), "unit": "solves/s", "ms_per_step": round(1e3 * secs / K, 4),
+                     "iterations_mean": sum(q["iterations"] for q in stats) / K,
+                     "fallbacks": sum(q["fallback"] for q in stats),
+                     "max_rel_residual": max(q["rel_residual"] for q in stats),
+                     "all_converged": all(q["converged"] for q in stats),
+                     "speedup_vs_fp64_mgpcg": round(v / base, 3)}
+    s.close()
+    net.close()
+    return out
+
+
 def cpu_baseline(p, b, n, mach, budget_s=15.0):
     """The FP64 oracle (CSR Jacobi-PCG) on the host cores, on a bounded sample of iterations.
 
@@ -209,6 +256,10 @@ def main():
                 base = v
             var[name]["speedup_vs_fp64_mgpcg"] = round(v / base, 3)
         result["ma0.001"] = var
+        lv = learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base)
+        if lv is not None:
+            var["learned_warm_start"] = lv["warm_start"]
+            var["learned_fcg"] = lv["fcg"]
         del rho3, c23
 
     if not args.no_cpu_baseline:

@@ -233,9 +233,14 @@ int hp_nn_forward_raw(hp_net* net, const unsigned short* in, float* y);
 int hp_nn_loss_grad_raw(hp_net* net, const unsigned short* in, const float* target, double* loss);
 int hp_nn_adam(hp_net* net, float lr);
 
-/* Use `net` (same grid as the handle; NULL detaches) in HP_MODE_LEARNED. Allocates two work
- * vectors of the fine grid. */
+/* Use `net` (same grid as the handle; NULL detaches) in HP_MODE_LEARNED and hp_warm_start.
+ * Allocates two work vectors of the fine grid. */
 int hp_attach_net(hp_handle* h, hp_net* net);
+
+/* Initial guess x = g y from the attached network, y = net(b, p_prev) (p_prev may be NULL), with
+ * g = <b, y> / <y, A y> the step minimising the A-norm error of x (g = 0, i.e. x = 0, if the
+ * network points uphill). Use before hp_solve; the solve's accuracy does not depend on it. */
+int hp_warm_start(hp_handle* h, const double* b, const double* p_prev, double* x);
 
 #ifdef __cplusplus
 }

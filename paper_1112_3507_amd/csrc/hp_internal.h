@@ -114,9 +114,9 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s);
 
 // ---- learned stage (hp_nn.hip) ----
 int nn_grid(const hp_net* net, int* nx, int* ny, int* nz);
-// z = s * out_scale * net(r / s, log rho, -log(rho m), 0), s = RMS(r)
+// z = s * out_scale * net(r / s, log rho, -log(rho m), p_prev / s), s = RMS(r); p_prev may be null
 int nn_apply(hp_net* net, hipStream_t stream, const double* r, const double* rho, const double* m,
-             double* z);
+             const double* pprev, double* z);
 const char* nn_error();
 
 // Number of workgroups the reducing kernels use for these sizes (partials capacity).

@@ -726,8 +726,98 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Transfer t, const T* __rest
     coarse[I + (int64_t)t.ncx * (J + (int64_t)t.ncy * K)] = acc;
 }
 
+// ---- z-marching transfers for levels coarsened on all three axes ----
+// Weights of the four fine positions 2I-1, 2I, 2I+1, 2I+2 of coarse index I along one axis for
+// R = P^T / 2 (same rule as restrict_taps: Neumann ends folded onto the parent, periodic wrap).
+__device__ __forceinline__ void rweights4(int I, int nf, int periodic, float* w) {
+    const int nc = nf >> 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int i = 2 * I - 1 + q;
+        if (i < 0 || i >= nf) {
+            if (!periodic) { w[q] = 0.0f; continue; }
+            i = (i + nf) % nf;
+        }
+        int parent = i >> 1;
+        int other = (i & 1) ? parent + 1 : parent - 1;
+        if (other < 0 || other >= nc) other = periodic ? (other + nc) % nc : parent;
+        w[q] = 0.5f * ((parent == I ? 0.75f : 0.0f) + (other == I ? 0.25f : 0.0f));
+    }
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// One thread per coarse column (I, J), 64 consecutive I per wave, one coarse row per wave, a
+// chunk of coarse planes per workgroup. The thread loads the fine pair (2I, 2I+1) of each of the
+// four fine rows as one 16-byte vector and takes 2I-1 / 2I+2 from its neighbour lanes; the
+// x-y weighted sum u(k) of each fine plane is reused by the two coarse planes it feeds.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_zm(Transfer t, ZTiles zt,
+                                                        const T* __restrict__ fine,
+                                                        T* __restrict__ coarse) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int lane = threadIdx.x & 63;
+    const int I = bx * 64 + lane;
+    const int J = by * 4 + (threadIdx.x >> 6);
+    const bool valid = I < t.ncx && J < t.ncy;
+    const int Ic = valid ? I : t.ncx - 1, Jc = J < t.ncy ? J : t.ncy - 1;
+    const int K0 = bz * zt.kz, K1 = min(K0 + zt.kz, t.ncz);
+    const int nfx = t.nfx, nfy = t.nfy, nfz = t.nfz;
+    const int sf = nfx * nfy;
+    float wx[4], wy[4];
+    rweights4(Ic, nfx, t.perx, wx);
+    rweights4(Jc, nfy, t.pery, wy);
+    int row[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) row[q] = wrapi(2 * Jc - 1 + q, nfy) * nfx;  // rows with w 0 are harmless
+    const int xl = wrapi(2 * Ic - 1, nfx), xr = wrapi(2 * Ic + 2, nfx);
+    const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == t.ncx - 1);
+    auto plane_sum = [&](int k) -> T {
+        // weighted x-y sum of fine plane k (k already wrapped / valid)
+        const T* base = fine + (int64_t)k * sf;
+        T u = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T* rp = base + row[q];
+            const T f0 = rp[2 * Ic], f1 = rp[2 * Ic + 1];
+            T left = __shfl_up(f1, 1, 64), right = __shfl_down(f0, 1, 64);
+            if (edge_l) left = rp[xl];
+            if (edge_r) right = rp[xr];
+            u += (T)wy[q] * ((T)wx[0] * left + (T)wx[1] * f0 + (T)wx[2] * f1 + (T)wx[3] * right);
+        }
+        return u;
+    };
+    // u of fine planes 2K0-1 and 2K0; plane indices wrap, so a missing Neumann plane reads a
+    // valid plane that then gets weight 0
+    T u0 = plane_sum(wrapi(2 * K0 - 1, nfz));
+    T u1 = plane_sum(wrapi(2 * K0, nfz));
+    for (int K = K0; K < K1; ++K) {
+        float w[4];
+        rweights4(K, nfz, t.perz, w);
+        const T u2 = plane_sum(wrapi(2 * K + 1, nfz));
+        const T u3 = plane_sum(wrapi(2 * K + 2, nfz));
+        if (valid)
+            coarse[(int64_t)K * t.ncx * t.ncy + (int64_t)J * t.ncx + I] =
+                (T)w[0] * u0 + (T)w[1] * u1 + (T)w[2] * u2 + (T)w[3] * u3;
+        // the next coarse plane starts at fine plane 2K+1
+        u0 = u2;
+        u1 = u3;
+    }
+}
+
+static bool transfer_zm(const Transfer& t) {
+    return t.fx && t.fy && t.fz && t.ncx >= 32 && t.ncy >= 4 && t.ncz >= 4;
+}
+
 template <typename T>
 void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s) {
+    if (transfer_zm(t)) {
+        ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64);
+        hipLaunchKernelGGL((k_restrict_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t, zt,
+                           fine, coarse);
+        return;
+    }
     Shape3 sh = cells_shape(t.ncx, t.ncy, t.ncz);
     hipLaunchKernelGGL((k_restrict<T>), sh.grid, sh.block, 0, s, t, fine, coarse);
 }
@@ -776,8 +866,80 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Transfer t, const T* __r
     fine[i + (int64_t)t.nfx * (j + (int64_t)t.nfy * k)] += acc;
 }
 
+// One thread per fine cell pair (2I, 2I+1) of one fine row j, 64 pairs per wave, one fine row
+// per wave, a chunk of fine planes (even start) per workgroup. Both cells have parent column I;
+// the second-nearest column is I-1 for 2I and I+1 for 2I+1 (taken from the neighbour lanes).
+// The x-y interpolation v(K) of coarse planes K-1, K, K+1 is kept in registers while marching.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
+                                                       const T* __restrict__ coarse,
+                                                       T* __restrict__ fine) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int lane = threadIdx.x & 63;
+    const int I = bx * 64 + lane;
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const bool valid = I < t.ncx && j < t.nfy;
+    const int Ic = I < t.ncx ? I : t.ncx - 1, jc = j < t.nfy ? j : t.nfy - 1;
+    const int k0 = bz * zt.kz, k1 = min(k0 + zt.kz, t.nfz);
+    const int ncx = t.ncx, ncy = t.ncy, ncz = t.ncz;
+    const int sc = ncx * ncy;
+    // x neighbours of the parent column (mirror onto the parent at a Neumann end)
+    const int xm = Ic > 0 ? Ic - 1 : (t.perx ? ncx - 1 : Ic);
+    const int xp = Ic < ncx - 1 ? Ic + 1 : (t.perx ? 0 : Ic);
+    // y: parent row and second row
+    const int J = jc >> 1;
+    int J2 = (jc & 1) ? J + 1 : J - 1;
+    if (J2 < 0 || J2 >= ncy) J2 = t.pery ? (J2 + ncy) % ncy : J;
+    const int rowJ = J * ncx, rowJ2 = J2 * ncx;
+    const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == ncx - 1);
+    // v(K) for the two fine columns
+    auto vplane = [&](int K, T& vlo, T& vhi) {
+        const T* cp = coarse + (int64_t)K * sc;
+        const T cy = T(0.75) * cp[rowJ + Ic] + T(0.25) * cp[rowJ2 + Ic];
+        T cl = __shfl_up(cy, 1, 64), cr = __shfl_down(cy, 1, 64);
+        if (edge_l) cl = T(0.75) * cp[rowJ + xm] + T(0.25) * cp[rowJ2 + xm];
+        if (edge_r) cr = T(0.75) * cp[rowJ + xp] + T(0.25) * cp[rowJ2 + xp];
+        vlo = T(0.75) * cy + T(0.25) * cl;
+        vhi = T(0.75) * cy + T(0.25) * cr;
+    };
+    auto zm = [&](int K) { return K > 0 ? K - 1 : (t.perz ? ncz - 1 : K); };
+    auto zp = [&](int K) { return K < ncz - 1 ? K + 1 : (t.perz ? 0 : K); };
+    int K = k0 >> 1;
+    T mlo, mhi, clo, chi, nlo, nhi;
+    vplane(zm(K), mlo, mhi);
+    vplane(K, clo, chi);
+    vplane(zp(K), nlo, nhi);
+    T* fp = fine + (int64_t)jc * t.nfx + 2 * Ic;
+    const int64_t sf = (int64_t)t.nfx * t.nfy;
+    for (int k = k0; k < k1; ++k) {
+        if ((k >> 1) != K) {  // next coarse plane
+            K = k >> 1;
+            mlo = clo; mhi = chi;
+            clo = nlo; chi = nhi;
+            vplane(zp(K), nlo, nhi);
+        }
+        const bool up = k & 1;
+        const T dlo = T(0.75) * clo + T(0.25) * (up ? nlo : mlo);
+        const T dhi = T(0.75) * chi + T(0.25) * (up ? nhi : mhi);
+        if (valid) {
+            T* q = fp + k * sf;
+            q[0] += dlo;
+            q[1] += dhi;
+        }
+    }
+}
+
 template <typename T>
 void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s) {
+    if (transfer_zm(t)) {
+        ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64);
+        zt.kz += zt.kz & 1;  // chunks start on even fine planes
+        zt.tz = (t.nfz + zt.kz - 1) / zt.kz;
+        hipLaunchKernelGGL((k_prolong_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t, zt,
+                           coarse, fine);
+        return;
+    }
     Shape3 sh = cells_shape(t.nfx, t.nfy, t.nfz);
     hipLaunchKernelGGL((k_prolong_add<T>), sh.grid, sh.block, 0, s, t, coarse, fine);
 }

@@ -1045,11 +1045,11 @@ int nn_grid(const hp_net* N, int* nx, int* ny, int* nz) {
     *nz = N->lv[0].nz;
     return HP_OK;
 }
-// z = s * out_scale * net(r / s, log rho, -log(rho m), 0), s = RMS(r)
+// z = s * out_scale * net(r / s, log rho, -log(rho m), p_prev / s), s = RMS(r)
 int nn_apply(hp_net* N, hipStream_t stream, const double* r, const double* rho, const double* m,
-             double* z) {
+             const double* pprev, double* z) {
     N->stream = stream;
-    int rc = features(N, r, rho, nullptr, m, nullptr);
+    int rc = features(N, r, rho, nullptr, m, pprev);
     if (rc) return rc;
     if ((rc = forward_net(N))) return rc;
     const int64_t V = N->lv[0].nv;

@@ -476,7 +476,7 @@ int fcg_learned(hp_handle* H, const double* b, double* x, double tol, double bno
         return HP_OK;
     };
     auto precond = [&](const double* r, double* z) -> int {
-        int rc = nn_apply(H->net, s, r, F.rho, F.m, H->w1);
+        int rc = nn_apply(H->net, s, r, F.rho, F.m, nullptr, H->w1);
         if (rc) return fail(rc, "network: %s", nn_error());
         launch_apply<double>(g, F.rho, F.m, H->w1, nullptr, H->w2, 0, red(H, OP_NONE), s);
         double rz1, z1az1;
@@ -924,6 +924,31 @@ int hp_attach_net(hp_handle* H, hp_net* net) {
     }
     H->net = net;
     return HP_OK;
+}
+
+int hp_warm_start(hp_handle* H, const double* b, const double* p_prev, double* x) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (!H->net) return fail(HP_EINVAL, "hp_warm_start needs a network (hp_attach_net)");
+    if (!b || !x) return fail(HP_EINVAL, "null vector");
+    LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    hipStream_t s = H->stream;
+    int rc = nn_apply(H->net, s, b, F.rho, F.m, p_prev, x);
+    if (rc) return fail(rc, "network: %s", nn_error());
+    launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, nullptr, H->w2, 0, red(H, OP_NONE), s);
+    launch_dot<double>(b, x, N, red(H, OP_STORE, S_TMP), s);
+    CHK(check_launch());
+    CHK(read_scalars(H));
+    const double bx = H->host_scal[S_TMP];
+    launch_dot<double>(x, H->w2, N, red(H, OP_STORE, S_TMP), s);
+    CHK(check_launch());
+    CHK(read_scalars(H));
+    const double xax = H->host_scal[S_TMP];
+    const double gam = (bx > 0.0 && xax > 0.0 && std::isfinite(bx) && std::isfinite(xax)) ? bx / xax : 0.0;
+    launch_axpby(0.0, x, gam, x, N, s);
+    if (gam == 0.0) launch_fill<double>(x, 0.0, N, s);
+    return check_launch();
 }
 
 int hp_dot(hp_handle* H, const double* x, const double* y, long long n, double* out) {

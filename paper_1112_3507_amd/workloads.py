@@ -92,6 +92,28 @@ def rhs_white(n, seed: int) -> np.ndarray:
     return b - b.mean()
 
 
+def rhs_smooth(n, seed: int, modes: int = 16, kmax: int = 4) -> np.ndarray:
+    """Smooth field: sum of `modes` terms a cos(2 pi (kx x + ky y) + phi) cos(pi kz z), minus mean.
+
+    a ~ N(0, 1), kx, ky in {-kmax..kmax}, kz in {0..kmax}, phi ~ U(0, 2 pi) (PCG64, `seed`);
+    coordinates are cell centres of the unit box.
+    """
+    nx, ny, nz = (int(v) for v in n)
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    b = np.zeros((nz, ny, nx))
+    for _ in range(modes):
+        a = rng.standard_normal()
+        kx, ky = rng.integers(-kmax, kmax + 1, size=2)
+        kz = rng.integers(0, kmax + 1)
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        hor = np.cos(2 * np.pi * (kx * x[None, :] + ky * y[:, None]) + phi)
+        b += a * np.cos(np.pi * kz * z)[:, None, None] * hor[None, :, :]
+    return b - b.mean()
+
+
 def rhs_modes_2d(nx: int, nz: int, seed: int, modes: int = 8) -> np.ndarray:
     """Sum of `modes` terms a_j sin(2 pi kx_j x) cos(pi kz_j z) on cell centres of the unit box.
 

@@ -6,6 +6,7 @@ points as the GPU pipeline), so what remains is FP32 (MFMA) versus FP64 accumula
 the rare bfloat16 rounding flips it causes: ~1e-3 relative on outputs, a few 1e-3 on gradients.
 """
 import functools
+import os
 
 import numpy as np
 import pytest
@@ -148,3 +149,57 @@ def test_learned_fcg_matches_oracle():
     assert st["converged"]
     assert np.linalg.norm(x0.cpu().numpy() - xref) / np.linalg.norm(xref) <= 1e-9
     net.close()
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1112_3507_amd", "weights", "unet128.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained checkpoint")
+def test_trained_network_gain():
+    """What training gains: A-norm error of the warm start x0 = g net(b) and learned-FCG
+    iterations, trained checkpoint vs the untrained (initial) network vs plain MG-PCG, on a
+    held-out 128^3 polytrope at Ma = 0.001 with a white and a smooth right-hand side."""
+    from paper_1112_3507_amd import train as tr
+    n = (128, 128, 128)
+    p = wl.polytrope(n, 0.001, seed=424242, contrast=12.0, index=1.4)
+    rho = torch.from_numpy(p.rho).to(DEV)
+    c2 = torch.from_numpy(p.c2).to(DEV)
+    theta_t, scale = tr.load(WEIGHTS)
+    nets = {"trained": hp.Net(n), "untrained": hp.Net(n)}
+    nets["trained"].set_params(torch.from_numpy(theta_t).to(DEV))
+    nets["untrained"].set_params(torch.from_numpy(tr.he_uniform(0)).to(DEV))
+    for v in nets.values():
+        v.set_output_scale(scale)
+    report = {}
+    with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as s:
+        for kind, b in (("white", wl.rhs_white(n, 9001)), ("smooth", wl.rhs_smooth(n, 9002))):
+            bt = torch.from_numpy(b).to(DEV)
+            s.set_option(hp.OPT_MODE, hp.MODE_FP64_MGPCG)
+            xr = torch.zeros_like(bt)
+            s.solve(bt, xr, tol=1e-12)
+            ax = torch.empty_like(bt)
+            s.apply(0, xr, ax)
+            xnorm = float(torch.dot(xr.flatten(), ax.flatten())) ** 0.5
+            x = torch.zeros_like(bt)
+            its0 = s.solve(bt, x, tol=1e-10)["iterations"]
+            for name, net in nets.items():
+                s.attach_net(net)
+                x0 = torch.empty_like(bt)
+                s.warm_start(bt, x0)
+                e = x0 - xr
+                s.apply(0, e, ax)
+                err = float(torch.dot(e.flatten(), ax.flatten())) ** 0.5 / xnorm
+                s.set_option(hp.OPT_MODE, hp.MODE_FP64_MGPCG)
+                its_ws = s.solve(bt, x0, tol=1e-10)["iterations"]
+                s.set_option(hp.OPT_MODE, hp.MODE_LEARNED)
+                x = torch.zeros_like(bt)
+                st = s.solve(bt, x, tol=1e-10)
+                report[(kind, name)] = (err, its_ws, st["iterations"], st["fallback"], its0)
+            s.attach_net(None)
+    for k, v in sorted(report.items()):
+        print("gain %s %-9s warm-start A-err %.3e  MGPCG its after warm start %d  "
+              "learned-FCG its %d (fallback %d)  plain MGPCG its %d" % (k[0], k[1], *v), flush=True)
+    for kind in ("white", "smooth"):
+        assert report[(kind, "trained")][0] < report[(kind, "untrained")][0]
+        assert report[(kind, "trained")][0] < 0.9
