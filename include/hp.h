@@ -233,6 +233,13 @@ int hp_nn_forward_raw(hp_net* net, const unsigned short* in, float* y);
 int hp_nn_loss_grad_raw(hp_net* net, const unsigned short* in, const float* target, double* loss);
 int hp_nn_adam(hp_net* net, float lr);
 
+/* One Adam step on the relative A-norm error of the network's estimate of the solution x of
+ * A x = b (A of the handle; the net must be a training network on the same grid):
+ * loss = <e, A e> / <x, A x>, e = s * out_scale * net(b, log rho, log c2, p_prev) - x.
+ * *loss receives the loss before the step (synchronises). */
+int hp_nn_train_step_anorm(hp_handle* h, hp_net* net, const double* b, const double* p_prev,
+                           const double* x, float lr, double* loss);
+
 /* Use `net` (same grid as the handle; NULL detaches) in HP_MODE_LEARNED and hp_warm_start.
  * Allocates two work vectors of the fine grid. */
 int hp_attach_net(hp_handle* h, hp_net* net);

@@ -35,7 +35,7 @@ EXPORTS = [
     "hp_nn_num_params", "hp_nn_create", "hp_nn_free", "hp_nn_set_stream", "hp_nn_last_error",
     "hp_nn_set_params", "hp_nn_get_params", "hp_nn_get_grad", "hp_nn_set_output_scale",
     "hp_nn_forward", "hp_nn_train_step", "hp_nn_forward_raw", "hp_nn_loss_grad_raw", "hp_nn_adam",
-    "hp_attach_net", "hp_warm_start",
+    "hp_attach_net", "hp_warm_start", "hp_nn_train_step_anorm",
 ]
 
 
@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                 "hp_nn_adam": (ip, [vp, ctypes.c_float]),
                 "hp_attach_net": (ip, [H, vp]),
                 "hp_warm_start": (ip, [H, dp, dp, dp]),
+                "hp_nn_train_step_anorm": (ip, [H, vp, dp, dp, dp, ctypes.c_float,
+                                                ctypes.POINTER(ctypes.c_double)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -298,6 +300,13 @@ class Solver:
     def attach_net(self, net):
         self._net = net
         _check(self._lib.hp_attach_net(self._h, net._h if net is not None else None))
+
+    def train_step_anorm(self, net, rhs, x, lr, p_prev=None) -> float:
+        loss = ctypes.c_double()
+        _check(self._lib.hp_nn_train_step_anorm(
+            self._h, net._h, self._vec(rhs, 0), self._vec(p_prev, 0) if p_prev is not None else None,
+            self._vec(x, 0), float(lr), ctypes.byref(loss)))
+        return loss.value
 
     def warm_start(self, rhs, x, p_prev=None):
         _check(self._lib.hp_warm_start(self._h, self._vec(rhs, 0),

@@ -62,8 +62,10 @@ void launch_setup_coef(const double* rho, const double* c2, double* rho_out, dou
                        float* rho32, float* m32, int64_t n, int* bad, hipStream_t s);
 void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m_f,
                          double* rho_c, double* m_c, float* rho32_c, float* m32_c, hipStream_t s);
-void launch_jacobi_diag(const Geo<double>& g, const double* rho, const double* m, double* dinv,
-                        hipStream_t s);
+// dinv = 1 / (m + sum of face weights) in FP64 and (if dinv32) FP32
+void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const double* rho,
+                        const double* m, const float* rho32, const float* m32, double* dinv,
+                        float* dinv32, hipStream_t s);
 
 // y = A x (mode 0), y = A x with <x, y> reduced (mode 1), y = b - A x (mode 2),
 // y = b - A x with <y, y> reduced (mode 3).
@@ -73,6 +75,20 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
 template <typename T>
 void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                  hipStream_t s);
+// red-black half sweep that also reduces <r, z> (all cells, final values) under rc;
+// returns false (and does nothing) when the level uses the small-grid kernels
+template <typename T>
+bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
+                     const RedCtl& rc, hipStream_t s);
+// zero-guess red half sweep followed by a black half sweep, in one pass (needs dinv);
+// returns false (and does nothing) when the level uses the small-grid kernels
+// t = r - A z on red cells and 0 on black cells (valid right after a black half sweep);
+// false when the level uses the small-grid kernels
+template <typename T>
+bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
+                      hipStream_t s);
+template <typename T>
+bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s);
 template <typename T>
 void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z,
                       hipStream_t s);
@@ -118,6 +134,12 @@ int nn_grid(const hp_net* net, int* nx, int* ny, int* nz);
 int nn_apply(hp_net* net, hipStream_t stream, const double* r, const double* rho, const double* m,
              const double* pprev, double* z);
 const char* nn_error();
+// training with a loss computed by the solver: forward pass, d = estimate - x, backward + Adam
+// from the physical-units output gradient coef * q
+int nn_train_forward(hp_net* net, hipStream_t stream, const double* b, const double* rho,
+                     const double* m, const double* pprev);
+int nn_output_minus(hp_net* net, const double* x, double* d);
+int nn_train_backward(hp_net* net, const double* q, double coef, float lr);
 
 // Number of workgroups the reducing kernels use for these sizes (partials capacity).
 int64_t reduce_blocks_cells(int nx, int ny, int nz);

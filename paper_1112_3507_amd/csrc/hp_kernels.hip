@@ -230,9 +230,15 @@ void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m
                        rho32_c, m32_c);
 }
 
-__global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, const double* __restrict__ rho,
+// inverse diagonal 1 / (m_a + sum_f w_f) in FP64, and its FP32 counterpart computed from the
+// FP32 coefficient copies (so each precision's smoother uses its own operator's diagonal)
+__global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, Geo<float> g32,
+                                                        const double* __restrict__ rho,
                                                         const double* __restrict__ m,
-                                                        double* __restrict__ dinv) {
+                                                        const float* __restrict__ rho32,
+                                                        const float* __restrict__ m32,
+                                                        double* __restrict__ dinv,
+                                                        float* __restrict__ dinv32) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y * blockDim.y + threadIdx.y;
     int k = blockIdx.z * blockDim.z + threadIdx.z;
@@ -242,12 +248,19 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, const dou
     double d = m[a];
     for_faces(g, i, j, k, a, [&](int nb, double c) { d += c * face_kappa(ra, rho[nb]); });
     dinv[a] = 1.0 / d;
+    if (dinv32) {
+        float ra32 = rho32[a];
+        float d32 = m32[a];
+        for_faces(g32, i, j, k, a, [&](int nb, float c) { d32 += c * face_kappa(ra32, rho32[nb]); });
+        dinv32[a] = 1.0f / d32;
+    }
 }
 
-void launch_jacobi_diag(const Geo<double>& g, const double* rho, const double* m, double* dinv,
-                        hipStream_t s) {
+void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const double* rho,
+                        const double* m, const float* rho32, const float* m32, double* dinv,
+                        float* dinv32, hipStream_t s) {
     Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
-    hipLaunchKernelGGL(k_jacobi_diag, sh.grid, sh.block, 0, s, g, rho, m, dinv);
+    hipLaunchKernelGGL(k_jacobi_diag, sh.grid, sh.block, 0, s, g, g32, rho, m, rho32, m32, dinv, dinv32);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -294,14 +307,14 @@ __device__ __forceinline__ void ztile(const ZTiles& t, int& bx, int& by, int& bz
     bz = (int)(L / ((unsigned)t.tx * t.ty));
 }
 
-static ZTiles ztiles(int nx, int ny, int nz, int xw) {
+static ZTiles ztiles(int nx, int ny, int nz, int xw, int kmin = 8) {
     ZTiles t;
     t.tx = (nx + xw - 1) / xw;
     t.ty = (ny + 3) / 4;
     int cols = t.tx * t.ty;
     t.kz = nz;
-    // aim for >= 2048 workgroups (8 per CU) with chunks of at least 8 planes
-    while (t.kz > 8 && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < 2048) t.kz = (t.kz + 1) / 2;
+    // aim for >= 2048 workgroups (8 per CU) with chunks of at least kmin planes
+    while (t.kz > kmin && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < 2048) t.kz = (t.kz + 1) / 2;
     t.tz = (nz + t.kz - 1) / t.kz;
     return t;
 }
@@ -530,17 +543,23 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zero(Geo<T> g, const T* __restr
 // (the in-plane neighbours of its active member, its r and m, the pair two planes up) are
 // issued before plane k is computed. ZERO: first red sweep from z = 0 (red cells r / D, black
 // cells 0; no z loads).
-template <typename T, bool ZERO>
+// DOT: also reduce <r, z> over every cell with the final values (the other member's z is
+// unchanged by the sweep), one partial per workgroup.
+// RESID: instead of updating z, write the residual t = r - A z of the cells of `colour` to `t`
+// and 0 for the other colour (exact right after a Gauss-Seidel half sweep of the other colour).
+template <typename T, bool ZERO, bool DOT, bool RESID = false>
 __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
                                                     const T* __restrict__ m,
                                                     const T* __restrict__ r, T* __restrict__ z,
-                                                    int colour) {
+                                                    int colour, double* __restrict__ partials,
+                                                    T* __restrict__ t = nullptr) {
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int i0 = (bx * 64 + (threadIdx.x & 63)) * 2;
     const int j = by * 4 + (threadIdx.x >> 6);
-    if (i0 >= g.nx || j >= g.ny) return;
+    double dsum = 0.0;
+    if (i0 < g.nx && j < g.ny) {
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
     const int sz = g.nx * g.ny;
@@ -614,9 +633,18 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
         const T wzp = czp * face_kappa(ra, sel ? rn1 : rn0);
         sw += wzm + wzp;
         swz += wzm * (sel ? zm1 : zm0) + wzp * (sel ? zn1 : zn0);
-        const T znew = (rr + swz) / (mm + sw);
-        if (sel == 0 || d1) z[a + sel] = znew;
+        if (RESID) {
+            const T zs = sel ? zc1 : zc0;
+            if (sel == 0 || d1) t[a + sel] = rr + swz - (mm + sw) * zs;
+            if (seln == 0 || d1) t[a + seln] = T(0);
+        }
+        const T znew = RESID ? T(0) : (rr + swz) / (mm + sw);
+        if (!RESID && (sel == 0 || d1)) z[a + sel] = znew;
         if (ZERO && (seln == 0 || d1)) z[a + seln] = T(0);
+        if (DOT) {
+            if (sel == 0 || d1) dsum += (double)rr * (double)znew;
+            if (seln == 0 || d1) dsum += (double)r[a + seln] * (double)(seln ? zc1 : zc0);
+        }
         // advance one plane. At plane k+1 the other pair member is updated; its z neighbours
         // are the members of planes k and k+2 that this sweep does not write, so the register
         // copies stay valid (the updated member's stale copy is never read again).
@@ -640,6 +668,110 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
         sel = seln;
         a = an;
     }
+    }
+    if (DOT) block_partial(dsum, partials);
+}
+
+// Pre-smoothing from z = 0 in one pass: a red half sweep from zero gives z_red = r dinv (a
+// pointwise value), so the following black half sweep can use r dinv of its red neighbours
+// directly: z_black = dinv_b (r_b + sum_f w_f r_nb dinv_nb). Each thread owns a cell pair; the
+// red-neighbour values q = r dinv of the pairs one plane up and down are kept in registers.
+// Same result as the zero-guess red sweep followed by a black sweep.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_presmooth_zm(Geo<T> g, ZTiles zt,
+                                                         const T* __restrict__ rho,
+                                                         const T* __restrict__ dinv,
+                                                         const T* __restrict__ r,
+                                                         T* __restrict__ z) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int i0 = (bx * 64 + (threadIdx.x & 63)) * 2;
+    const int j = by * 4 + (threadIdx.x >> 6);
+    if (i0 >= g.nx || j >= g.ny) return;
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
+    const int sz = g.nx * g.ny;
+    const int d1 = (i0 + 1 < g.nx) ? 1 : 0;
+    const FaceTab<T> f0(g, i0, j), f1(g, i0 + d1, j);
+    const int col = i0 + g.nx * j;
+    int a = col + k0 * sz;
+    bool hm, hp;
+    const int om = zoff(k0, -1, g.nz, g.pz, sz, hm);
+    const int op = zoff(k0, 1, g.nz, g.pz, sz, hp);
+    T czm = hm ? g.cz : T(0), czp = hp ? g.cz : T(0);
+    // pair values at planes k-1 (m), k (c), k+1 (n): rho and q = r * dinv
+    T rc0 = rho[a], rc1 = rho[a + d1];
+    T rm0 = rho[a + om], rm1 = rho[a + om + d1];
+    T rn0 = rho[a + op], rn1 = rho[a + op + d1];
+    T qc0 = r[a] * dinv[a], qc1 = r[a + d1] * dinv[a + d1];
+    T qm0 = r[a + om] * dinv[a + om], qm1 = r[a + om + d1] * dinv[a + om + d1];
+    T qn0 = r[a + op] * dinv[a + op], qn1 = r[a + op + d1] * dinv[a + op + d1];
+    for (int k = k0; k < k1; ++k) {
+        const int red = (j + k) & 1;   // pair member of colour red (i0 is even)
+        const int blk = red ^ 1;
+        const int kn = min(k + 1, k1 - 1);
+        const int an = col + kn * sz;
+        bool hpn;
+        const int opn = zoff(kn, 1, g.nz, g.pz, sz, hpn);
+        // prefetch the pair two planes up
+        const T rnn0 = rho[an + opn], rnn1 = rho[an + opn + d1];
+        const T qnn0 = r[an + opn] * dinv[an + opn];
+        const T qnn1 = r[an + opn + d1] * dinv[an + opn + d1];
+        // black member: in-plane neighbours are red, z neighbours are the red members up/down
+        const int ab = a + blk;
+        int o[4];
+        T cf[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[q] = blk ? f1.o[q] : f0.o[q];
+            cf[q] = blk ? f1.c[q] : f0.c[q];
+        }
+        const T rb = blk ? rc1 : rc0;
+        T sw = T(0), swq = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T w = cf[q] * face_kappa(rb, rho[ab + o[q]]);
+            sw += w;
+            swq += w * (r[ab + o[q]] * dinv[ab + o[q]]);
+        }
+        const T wzm = czm * face_kappa(rb, blk ? rm1 : rm0);
+        const T wzp = czp * face_kappa(rb, blk ? rn1 : rn0);
+        swq += wzm * (blk ? qm1 : qm0) + wzp * (blk ? qn1 : qn0);
+        const T zb = (r[ab] + swq) * dinv[ab];
+        if (red == 0 || d1) z[a + red] = red ? qc1 : qc0;
+        if (blk == 0 || d1) z[ab] = zb;
+        (void)sw;
+        // advance one plane
+        czm = czp;
+        czp = hpn ? g.cz : T(0);
+        rm0 = rc0; rm1 = rc1;
+        rc0 = rn0; rc1 = rn1;
+        rn0 = rnn0; rn1 = rnn1;
+        qm0 = qc0; qm1 = qc1;
+        qc0 = qn0; qc1 = qn1;
+        qn0 = qnn0; qn1 = qnn1;
+        a = an;
+    }
+}
+
+// residual after a black half sweep: t = r - A z on red cells, 0 on black cells
+template <typename T>
+bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
+                      hipStream_t s) {
+    if (!use_zm(g.nx, g.ny, g.nz)) return false;
+    ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+    hipLaunchKernelGGL((k_rbgs_zm<T, false, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
+                       s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
+    return true;
+}
+
+template <typename T>
+bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s) {
+    if (!use_zm(g.nx, g.ny, g.nz)) return false;
+    ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+    hipLaunchKernelGGL((k_presmooth_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt, rho,
+                       dinv, r, z);
+    return true;
 }
 
 template <typename T>
@@ -647,8 +779,8 @@ void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, in
                  hipStream_t s) {
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
-        hipLaunchKernelGGL((k_rbgs_zm<T, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
-                           g, zt, rho, m, r, z, colour);
+        hipLaunchKernelGGL((k_rbgs_zm<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
+                           s, g, zt, rho, m, r, z, colour, nullptr);
         return;
     }
     Shape3 sh = cells_shape((g.nx + 1) / 2, g.ny, g.nz);
@@ -656,12 +788,24 @@ void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, in
 }
 
 template <typename T>
+bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
+                     const RedCtl& rc, hipStream_t s) {
+    if (!use_zm(g.nx, g.ny, g.nz)) return false;
+    ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+    const int nb = zt.tx * zt.ty * zt.tz;
+    hipLaunchKernelGGL((k_rbgs_zm<T, false, true>), dim3(nb), dim3(kBlock), 0, s, g, zt, rho, m, r, z,
+                       colour, rc.partials);
+    finalize(rc, nb, s);
+    return true;
+}
+
+template <typename T>
 void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z,
                       hipStream_t s) {
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
-        hipLaunchKernelGGL((k_rbgs_zm<T, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
-                           g, zt, rho, m, r, z, 0);
+        hipLaunchKernelGGL((k_rbgs_zm<T, true, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
+                           s, g, zt, rho, m, r, z, 0, nullptr);
         return;
     }
     Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
@@ -813,7 +957,7 @@ static bool transfer_zm(const Transfer& t) {
 template <typename T>
 void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s) {
     if (transfer_zm(t)) {
-        ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64);
+        ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64, 2);
         hipLaunchKernelGGL((k_restrict_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t, zt,
                            fine, coarse);
         return;
@@ -933,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
 template <typename T>
 void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s) {
     if (transfer_zm(t)) {
-        ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64);
+        ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64, 2);
         zt.kz += zt.kz & 1;  // chunks start on even fine planes
         zt.tz = (t.nfz + zt.kz - 1) / zt.kz;
         hipLaunchKernelGGL((k_prolong_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t, zt,
@@ -1136,6 +1280,12 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
     template void launch_rbgs<T>(const Geo<T>&, const T*, const T*, const T*, T*, int,          \
                                  hipStream_t);                                                  \
     template void launch_rbgs_zero<T>(const Geo<T>&, const T*, const T*, const T*, T*,          \
+                                      hipStream_t);                                             \
+    template bool launch_rbgs_dot<T>(const Geo<T>&, const T*, const T*, const T*, T*, int,      \
+                                     const RedCtl&, hipStream_t);                               \
+    template bool launch_presmooth<T>(const Geo<T>&, const T*, const T*, const T*, T*,          \
+                                      hipStream_t);                                             \
+    template bool launch_resid_red<T>(const Geo<T>&, const T*, const T*, const T*, const T*, T*, \
                                       hipStream_t);                                             \
     template void launch_restrict<T>(const Transfer&, const T*, T*, hipStream_t);               \
     template void launch_prolong_add<T>(const Transfer&, const T*, T*, hipStream_t);            \

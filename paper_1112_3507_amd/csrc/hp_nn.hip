@@ -539,6 +539,18 @@ __global__ void k_output(const float* __restrict__ y, const double* __restrict__
     if (v < n) x[v] = (double)y[v] * ss[1] * oscale;
 }
 
+__global__ void k_output_minus(const float* __restrict__ y, const double* __restrict__ ss, double oscale,
+                               const double* __restrict__ x, double* __restrict__ d, int64_t n) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) d[v] = (double)y[v] * ss[1] * oscale - x[v];
+}
+
+__global__ void k_scaled_grad(const double* __restrict__ q, const double* __restrict__ ss, double oscale,
+                              double coef, float* __restrict__ gy, int64_t n) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) gy[v] = (float)(coef * ss[1] * oscale * q[v]);
+}
+
 // target in network units: t = x / (s * out_scale)
 __global__ void k_target(const double* __restrict__ x, const double* __restrict__ ss, double oscale,
                          float* __restrict__ t, int64_t n) {
@@ -910,15 +922,11 @@ int hp_nn_forward_raw(hp_net* N, const unsigned short* in, float* y) {
     return HP_OK;
 }
 
-// loss and gradient for the input already in x0 and the target in t (network units)
-int loss_grad(hp_net* N, double* loss) {
+// backward pass from the output gradient in gy (FP32, network units) to the parameter gradient
+int backward_net(hp_net* N) {
     const Level& L0 = N->lv[0];
     const int64_t V = L0.nv;
-    int rc = forward_net(N);
-    if (rc) return rc;
-    const int nb = 1024;
-    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, N->stream, N->y, N->t, N->gy, V, N->dpart);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, N->stream, N->dpart, nb, N->ss + 2);
+    int rc;
     // head
     const int64_t hrows = (V + 255) / 256;
     hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)hrows), dim3(64), 0, N->stream, N->gy, N->act[9],
@@ -958,7 +966,18 @@ int loss_grad(hp_net* N, double* loss) {
     hipLaunchKernelGGL(k_split_grad, dim3(nblk(V * 16)), dim3(256), 0, N->stream, N->gin, 16, 0, 0,
                        N->gact[0], nullptr, L0.nx, L0.ny, L0.nz);
     if ((rc = backward_conv(N, 0))) return rc;
-    if ((rc = check())) return rc;
+    return check();
+}
+
+// mean squared error loss and gradient for the input already in x0 and the target in t
+int loss_grad(hp_net* N, double* loss) {
+    const int64_t V = N->lv[0].nv;
+    int rc = forward_net(N);
+    if (rc) return rc;
+    const int nb = 1024;
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, N->stream, N->y, N->t, N->gy, V, N->dpart);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, N->stream, N->dpart, nb, N->ss + 2);
+    if ((rc = backward_net(N))) return rc;
     if (loss) {
         double h[4];
         if (hipMemcpyAsync(h, N->ss, 4 * sizeof(double), hipMemcpyDeviceToHost, N->stream) != hipSuccess ||
@@ -1057,4 +1076,31 @@ int nn_apply(hp_net* N, hipStream_t stream, const double* r, const double* rho, 
     return check();
 }
 const char* nn_error() { return g_nn_err.c_str(); }
+
+int nn_train_forward(hp_net* N, hipStream_t stream, const double* b, const double* rho,
+                     const double* m, const double* pprev) {
+    if (!N->training) return nfail(HP_EINVAL, "not a training network");
+    N->stream = stream;
+    int rc = features(N, b, rho, nullptr, m, pprev);
+    if (rc) return rc;
+    return forward_net(N);
+}
+
+// d = s * out_scale * y - x (physical units, FP64)
+int nn_output_minus(hp_net* N, const double* x, double* d) {
+    const int64_t V = N->lv[0].nv;
+    hipLaunchKernelGGL(k_output_minus, dim3(nblk(V)), dim3(256), 0, N->stream, N->y, N->ss, N->out_scale,
+                       x, d, V);
+    return check();
+}
+
+// gy = coef * s * out_scale * q  (chain rule from physical to network units), then backward + Adam
+int nn_train_backward(hp_net* N, const double* q, double coef, float lr) {
+    const int64_t V = N->lv[0].nv;
+    hipLaunchKernelGGL(k_scaled_grad, dim3(nblk(V)), dim3(256), 0, N->stream, q, N->ss, N->out_scale, coef,
+                       N->gy, V);
+    int rc = backward_net(N);
+    if (rc) return rc;
+    return adam(N, lr);
+}
 }  // namespace hp

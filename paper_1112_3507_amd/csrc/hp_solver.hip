@@ -49,8 +49,8 @@ struct LevelData {
     double h[3];
     int coarsened[3];  // relative to the finer level
     int64_t N;
-    double *rho = nullptr, *m = nullptr;
-    float *rho32 = nullptr, *m32 = nullptr;
+    double *rho = nullptr, *m = nullptr, *dinv = nullptr;
+    float *rho32 = nullptr, *m32 = nullptr, *dinv32 = nullptr;
     double *r = nullptr, *z = nullptr, *t = nullptr;
     float *r32 = nullptr, *z32 = nullptr, *t32 = nullptr;
 };
@@ -73,7 +73,7 @@ struct hp_handle {
     int nc = 0;
     double* ainv = nullptr;
     std::vector<double> host_ainv;
-    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     double* scal = nullptr;
     double* partials = nullptr;
@@ -249,7 +249,9 @@ int load_coefficients(hp_handle* H, const double* rho, const double* c2, double 
                             C.m32, H->stream);
         CHK(check_launch());
     }
-    launch_jacobi_diag(geo<double>(H, F), F.rho, F.m, H->dinv, H->stream);
+    for (auto& L : H->lv)
+        launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
+                           L.dinv32, H->stream);
     CHK(check_launch());
     return build_coarse_inverse(H);
 }
@@ -271,26 +273,34 @@ template <> const double* lvl_rho<double>(const LevelData& L) { return L.rho; }
 template <> const double* lvl_m<double>(const LevelData& L) { return L.m; }
 template <> const float* lvl_rho<float>(const LevelData& L) { return L.rho32; }
 template <> const float* lvl_m<float>(const LevelData& L) { return L.m32; }
+template <typename T> const T* lvl_dinv(const LevelData& L);
+template <> const double* lvl_dinv<double>(const LevelData& L) { return L.dinv; }
+template <> const float* lvl_dinv<float>(const LevelData& L) { return L.dinv32; }
 
+// V-cycle z = M r on level l. With dot != nullptr (level 0 only) the final red half sweep also
+// reduces <r, z> under *dot; returns true if it did (else the caller reduces separately).
 template <typename T>
-void vcycle(hp_handle* H, int l, const T* r, T* z) {
+bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) {
     LevelData& L = H->lv[l];
     hipStream_t s = H->stream;
     if (l == (int)H->lv.size() - 1) {
         launch_coarse_solve<T>(H->ainv, H->nc, r, z, s);
-        return;
+        return false;
     }
     Geo<T> g = geo<T>(H, L);
     const T* rho = lvl_rho<T>(L);
     const T* m = lvl_m<T>(L);
-    launch_rbgs_zero<T>(g, rho, m, r, z, s);
-    launch_rbgs<T>(g, rho, m, r, z, 1, s);
+    if (!launch_presmooth<T>(g, rho, lvl_dinv<T>(L), r, z, s)) {
+        launch_rbgs_zero<T>(g, rho, m, r, z, s);
+        launch_rbgs<T>(g, rho, m, r, z, 1, s);
+    }
     for (int it = 1; it < H->nu_pre; ++it) {
         launch_rbgs<T>(g, rho, m, r, z, 0, s);
         launch_rbgs<T>(g, rho, m, r, z, 1, s);
     }
     T* t = lvl_t<T>(L);
-    launch_apply<T>(g, rho, m, z, r, t, 2, red(H, OP_NONE), s);
+    // after the black half sweep the residual vanishes on black cells
+    if (!launch_resid_red<T>(g, rho, m, r, z, t, s)) launch_apply<T>(g, rho, m, z, r, t, 2, red(H, OP_NONE), s);
     LevelData& C = H->lv[l + 1];
     Transfer tr = transfer(H, l);
     launch_restrict<T>(tr, t, lvl_r<T>(C), s);
@@ -298,8 +308,11 @@ void vcycle(hp_handle* H, int l, const T* r, T* z) {
     launch_prolong_add<T>(tr, lvl_z<T>(C), z, s);
     for (int it = 0; it < H->nu_post; ++it) {
         launch_rbgs<T>(g, rho, m, r, z, 1, s);
+        if (dot && it == H->nu_post - 1) return launch_rbgs_dot<T>(g, rho, m, r, z, 0, *dot, s) ||
+                                                (launch_rbgs<T>(g, rho, m, r, z, 0, s), false);
         launch_rbgs<T>(g, rho, m, r, z, 0, s);
     }
+    return false;
 }
 
 int read_scalars(hp_handle* H) {
@@ -313,10 +326,10 @@ int read_scalars(hp_handle* H) {
 void precond64(hp_handle* H, const double* r, double* z, int op) {
     int64_t N = H->lv[0].N;
     if (H->mode == HP_MODE_JACOBI_PCG) {
-        launch_jacobi_apply(H->dinv, r, z, N, red(H, op), H->stream);
+        launch_jacobi_apply(H->lv[0].dinv, r, z, N, red(H, op), H->stream);
     } else {
-        vcycle<double>(H, 0, r, z);
-        launch_dot<double>(r, z, N, red(H, op), H->stream);
+        RedCtl rc = red(H, op);
+        if (!vcycle<double>(H, 0, r, z, &rc)) launch_dot<double>(r, z, N, rc, H->stream);
     }
 }
 
@@ -345,9 +358,9 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         if (restart) {
             precond64(H, H->r, H->z, OP_RZINIT);
             launch_copy<double>(H->z, H->p, N, s);
+            launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
             restart = false;
         }
-        launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
         launch_axpy2_norm<double>(x, H->p, H->r, H->q, N, red(H, OP_STORE, S_RR), s);
         CHK(check_launch());
         CHK(read_scalars(H));
@@ -372,6 +385,7 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         if (st.iterations >= H->max_iter) break;
         precond64(H, H->r, H->z, OP_BETA);
         launch_xpby<double>(H->z, H->p, N, H->scal, s);
+        launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
     }
     double rel;
     CHK(true_residual(H, b, x, H->z, bnorm, &rel));
@@ -387,12 +401,14 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
     Geo<float> g = geo<float>(H, F);
     hipStream_t s = H->stream;
     launch_fill<float>(H->x32, 0.0f, N, s);
-    vcycle<float>(H, 0, H->r32, H->z32);
-    launch_dot<float>(H->r32, H->z32, N, red(H, OP_RZINIT), s);
+    {
+        RedCtl rc = red(H, OP_RZINIT);
+        if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, N, rc, s);
+    }
     launch_copy<float>(H->z32, H->p32, N, s);
+    launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
     *its = 0;
     while (*its < budget) {
-        launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
         launch_axpy2_norm<float>(H->x32, H->p32, H->r32, H->q32, N, red(H, OP_STORE, S_RR), s);
         CHK(check_launch());
         CHK(read_scalars(H));
@@ -401,9 +417,10 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
         double rr = H->host_scal[S_RR];
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite inner residual");
         if (std::sqrt(rr) <= eta) break;
-        vcycle<float>(H, 0, H->r32, H->z32);
-        launch_dot<float>(H->r32, H->z32, N, red(H, OP_BETA), s);
+        RedCtl rc = red(H, OP_BETA);
+        if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, N, rc, s);
         launch_xpby<float>(H->z32, H->p32, N, H->scal, s);
+        launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
     }
     return HP_OK;
 }
@@ -695,7 +712,8 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
     for (size_t l = 0; l < H->lv.size(); ++l) {
         LevelData& L = H->lv[l];
         if ((rc = dalloc(H, &L.rho, L.N)) || (rc = dalloc(H, &L.m, L.N)) ||
-            (rc = dalloc(H, &L.rho32, L.N)) || (rc = dalloc(H, &L.m32, L.N)))
+            (rc = dalloc(H, &L.rho32, L.N)) || (rc = dalloc(H, &L.m32, L.N)) ||
+            (rc = dalloc(H, &L.dinv, L.N)) || (rc = dalloc(H, &L.dinv32, L.N)))
             return bail(rc);
         if (l > 0) {
             if ((rc = dalloc(H, &L.r, L.N)) || (rc = dalloc(H, &L.z, L.N)) ||
@@ -708,7 +726,7 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
     }
     if ((rc = dalloc(H, &H->ainv, (int64_t)H->nc * H->nc))) return bail(rc);
     if ((rc = dalloc(H, &H->r, N)) || (rc = dalloc(H, &H->z, N)) || (rc = dalloc(H, &H->p, N)) ||
-        (rc = dalloc(H, &H->q, N)) || (rc = dalloc(H, &H->dinv, N)))
+        (rc = dalloc(H, &H->q, N)))
         return bail(rc);
     if ((rc = dalloc(H, &H->x32, N)) || (rc = dalloc(H, &H->r32, N)) ||
         (rc = dalloc(H, &H->z32, N)) || (rc = dalloc(H, &H->p32, N)) || (rc = dalloc(H, &H->q32, N)))
@@ -948,6 +966,44 @@ int hp_warm_start(hp_handle* H, const double* b, const double* p_prev, double* x
     const double gam = (bx > 0.0 && xax > 0.0 && std::isfinite(bx) && std::isfinite(xax)) ? bx / xax : 0.0;
     launch_axpby(0.0, x, gam, x, N, s);
     if (gam == 0.0) launch_fill<double>(x, 0.0, N, s);
+    return check_launch();
+}
+
+int hp_nn_train_step_anorm(hp_handle* H, hp_net* net, const double* b, const double* p_prev,
+                           const double* x, float lr, double* loss) {
+    if (!H || !net) return fail(HP_EINVAL, "null handle or network");
+    g_err.clear();
+    if (!b || !x) return fail(HP_EINVAL, "null vector");
+    if (!(lr > 0.f)) return fail(HP_EINVAL, "learning rate must be positive");
+    int nx, ny, nz;
+    nn_grid(net, &nx, &ny, &nz);
+    LevelData& F = H->lv[0];
+    if (nx != F.n[0] || ny != F.n[1] || nz != F.n[2]) return fail(HP_EINVAL, "network grid differs from the solver grid");
+    if (!H->w1) {
+        int rc;
+        if ((rc = dalloc(H, &H->w1, F.N)) || (rc = dalloc(H, &H->w2, F.N))) return rc;
+    }
+    const int64_t N = F.N;
+    hipStream_t s = H->stream;
+    Geo<double> g = geo<double>(H, F);
+    int rc = nn_train_forward(net, s, b, F.rho, F.m, p_prev);
+    if (rc) return fail(rc, "network: %s", nn_error());
+    // <x, A x>
+    launch_apply<double>(g, F.rho, F.m, x, nullptr, H->w2, 0, red(H, OP_NONE), s);
+    launch_dot<double>(x, H->w2, N, red(H, OP_STORE, S_TMP), s);
+    CHK(check_launch());
+    CHK(read_scalars(H));
+    const double xax = H->host_scal[S_TMP];
+    if (!(xax > 0.0)) return fail(HP_EINVAL, "target must be nonzero");
+    // d = estimate - x, q = A d, loss = <d, q> / <x, A x>
+    if ((rc = nn_output_minus(net, x, H->w1))) return fail(rc, "network: %s", nn_error());
+    launch_apply<double>(g, F.rho, F.m, H->w1, nullptr, H->w2, 0, red(H, OP_NONE), s);
+    launch_dot<double>(H->w1, H->w2, N, red(H, OP_STORE, S_TMP), s);
+    CHK(check_launch());
+    CHK(read_scalars(H));
+    if (loss) *loss = H->host_scal[S_TMP] / xax;
+    // dL/d(estimate) = 2 A d / <x, A x>
+    if ((rc = nn_train_backward(net, H->w2, 2.0 / xax, lr))) return fail(rc, "network: %s", nn_error());
     return check_launch();
 }
 

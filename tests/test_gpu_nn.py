@@ -122,6 +122,30 @@ def test_training_reduces_loss():
     net.close()
 
 
+def test_anorm_training_reduces_loss():
+    """Training on the relative A-norm error through the solver handle lowers it."""
+    n = (32, 32, 32)
+    p = wl.polytrope(n, 0.001, seed=81)
+    rho = torch.from_numpy(p.rho).to(DEV)
+    c2 = torch.from_numpy(p.c2).to(DEV)
+    net = hp.Net(n, training=True)
+    net.set_params(torch.from_numpy(nn.init_params(4).astype(np.float32)).to(DEV))
+    losses = []
+    with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as s:
+        data = []
+        for q in range(4):
+            bt = torch.from_numpy(wl.rhs_white(n, 90 + q)).to(DEV)
+            x = torch.zeros_like(bt)
+            s.solve(bt, x, tol=1e-10)
+            data.append((bt, x))
+        for step in range(80):
+            bt, x = data[step % 4]
+            net.set_output_scale(float(x.norm() / bt.norm()))
+            losses.append(s.train_step_anorm(net, bt, x, 2e-3))
+    assert np.isfinite(losses[-1]) and np.mean(losses[-4:]) < 0.5 * np.mean(losses[:4]), losses[::10]
+    net.close()
+
+
 def test_learned_fcg_matches_oracle():
     n = (80, 24, 40)
     p = wl.polytrope(n, 0.001, seed=1)
