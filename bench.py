@@ -33,7 +33,8 @@ ALG_BYTES = {
     # q = A p with <p, q>: read p, rho, m; write q
     "apply": 32.0,
     # one red-black half sweep: read rho (all cells), r, m and the other colour's z (half the
-    # cells each), write this colour's z (half)
+    # cells each), write this colour's z (half); the split layout of the finest level lets the
+    # kernel touch only these
     "rbgs_half_sweep": 24.0,
 }
 
@@ -80,27 +81,66 @@ def kernel_time_ms(fn, reps=50):
     return e0.elapsed_time(e1) / reps
 
 
-def roofline(solver, n_cells, dev):
-    """Per-launch duration of the level-0 kernels; roofline of the dominant one."""
+def roofline(solver, rhs, x, n_cells, dev, warmup):
+    """Roofline of the dominant finest-level kernel class, measured live: the solver's own
+    HIP-event timing (on its stream) of every black post-smoothing half sweep and every CG
+    operator apply inside FP64 solves of the benchmark's right-hand sides; a plain device copy
+    of 1 GiB (beyond the 256 MB last-level cache) as the measured streaming reference."""
     import torch
-    x = torch.randn(n_cells, dtype=torch.float64, device=dev)
-    y = torch.empty_like(x)
-    r = torch.randn(n_cells, dtype=torch.float64, device=dev)
-    times = {
-        "apply": kernel_time_ms(lambda: solver.apply(0, x, y)),
-        "rbgs_half_sweep": kernel_time_ms(lambda: solver.smooth(0, r, x, 1)),
-    }
-    # launches per CG iteration on level 0: 2 operator applies (CG + residual before
-    # restriction), 3 half sweeps (+1 zero-guess sweep)
-    per_iter = {"apply": 2 * times["apply"], "rbgs_half_sweep": 3 * times["rbgs_half_sweep"]}
+    import paper_1112_3507_amd as hp
+    solver.set_option(hp.OPT_KERNEL_TIMING, 1)
+    acc = {"rbgs_half_sweep": [0.0, 0], "apply": [0.0, 0]}
+    for k in range(len(rhs) - warmup):
+        x.zero_()
+        st = solver.solve(rhs[warmup + k], x, tol=TOL)
+        acc["rbgs_half_sweep"][0] += st["sweep_ms"] * st["timed_sweeps"]
+        acc["rbgs_half_sweep"][1] += st["timed_sweeps"]
+        acc["apply"][0] += st["apply_ms"] * st["timed_applies"]
+        acc["apply"][1] += st["timed_applies"]
+    solver.set_option(hp.OPT_KERNEL_TIMING, 0)
+    times = {k: v[0] / max(v[1], 1) for k, v in acc.items()}
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    copy_ms = kernel_time_ms(lambda: dst.copy_(src), reps=20)
+    del src, dst
+    # finest-level launches per CG iteration: four passes shaped like a half sweep (the fused
+    # zero-guess pre-smooth, the red sweep with the residual, the black and the red post-sweeps)
+    # and one operator apply
+    per_iter = {"rbgs_half_sweep": 4 * times["rbgs_half_sweep"], "apply": times["apply"]}
     dom = max(per_iter, key=per_iter.get)
     gbs = ALG_BYTES[dom] * n_cells / (times[dom] * 1e-3) / 1e9
-    kern = {k: {"ms": round(v, 5), "alg_bytes_per_cell": ALG_BYTES[k],
-                "achieved_GBs": round(ALG_BYTES[k] * n_cells / (v * 1e-3) / 1e9, 1)}
+    kern = {k: {"ms": round(v, 5), "launches_timed": acc[k][1], "alg_bytes_per_cell": ALG_BYTES[k],
+                "achieved_GBs": round(ALG_BYTES[k] * n_cells / (v * 1e-3) / 1e9, 1) if v > 0 else None}
             for k, v in times.items()}
+    copy_gbs = 2.0 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "per_launch_ms": round(times[dom], 5), "kernels": kern}
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, n_cells),
+            "per_launch_ms": round(times[dom], 5), "kernels": kern,
+            "copy_reference": {"bytes": 2 * (1 << 30), "ms": round(copy_ms, 5), "GBs": round(copy_gbs, 1),
+                               "frac_of_copy": round(gbs / copy_gbs, 4)}}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cube.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1112_3507_amd", "csrc", "hp_kernels.hip")
+
+
+def measured_traffic(kernel, n_cells):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the reading of a plain copy of known size), or
+    None when there is none for this size or the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_FILE).read(), re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if d.get("n_cells") != n_cells or d.get("kernels_source_sha256") != sha:
+        return None
+    return d.get("per_launch_bytes", {}).get(kernel)
 
 
 def learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base):
@@ -231,7 +271,7 @@ def main():
     log("bench: %.2f solves/s, %.1f iterations/solve" % (value, result["iterations_mean"]))
 
     if not args.no_roofline:
-        result["roofline"] = roofline(solver, p.ncells, dev)
+        result["roofline"] = roofline(solver, rhs, x, p.ncells, dev, W)
         log("bench: roofline %s" % json.dumps(result["roofline"]))
     solver.close()
 

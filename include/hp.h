@@ -77,7 +77,14 @@ enum {
     HP_OPT_NU_POST = 4,       /* post-smoothing sweeps, 1..8; default 1 */
     HP_OPT_INNER_TOL = 5,     /* MIXED_IR: relative residual reduction per inner solve; 1e-5 */
     HP_OPT_MAX_OUTER = 6,     /* MIXED_IR: refinement-step cap; default 20 */
-    HP_OPT_COARSEST_MAX = 7   /* read-only after setup: max cells of the coarsest level (512) */
+    HP_OPT_COARSEST_MAX = 7,  /* read-only after setup: max cells of the coarsest level (512) */
+    HP_OPT_LAYOUT = 8         /* finest-level storage inside the handle: 1 = red-black split (each
+                                 x row stores its red cells, then its black cells; the default
+                                 where the grid allows it: nx even, nx >= 64, ny >= 4, nz >= 8
+                                 and every axis coarsened at least once), 0 = natural order.
+                                 Vectors passed through this API are always in natural order;
+                                 setting 1 where the grid does not allow it is HP_EINVAL */,
+    HP_OPT_KERNEL_TIMING = 9  /* 1: time finest-level kernels inside FP64 solves (hp_stats); 0 */
 };
 
 /* Statistics of the last hp_solve. */
@@ -91,6 +98,12 @@ typedef struct {
     int levels;            /* multigrid levels */
     int status;            /* return code of the solve */
     int fallback;          /* MIXED_IR: 1 if refinement stagnated and FP64 MG-PCG finished */
+    /* with HP_OPT_KERNEL_TIMING on (FP64 solves): finest-level launches timed with HIP events on
+       the handle's stream during the solve, and their average duration */
+    int timed_sweeps;      /* red-black half sweeps (the black post-smoothing sweep) */
+    double sweep_ms;
+    int timed_applies;     /* operator applies q = A p of the CG iteration */
+    double apply_ms;
 } hp_stats;
 
 /*

@@ -20,6 +20,8 @@ PERIODIC, NEUMANN = 0, 1
 MODE_JACOBI_PCG, MODE_FP64_MGPCG, MODE_MIXED_IR, MODE_LEARNED = 0, 1, 2, 3
 OPT_MODE, OPT_MAX_ITER, OPT_NU_PRE, OPT_NU_POST = 1, 2, 3, 4
 OPT_INNER_TOL, OPT_MAX_OUTER, OPT_COARSEST_MAX = 5, 6, 7
+OPT_LAYOUT = 8  # finest-level storage inside the handle: 1 red-black split, 0 natural
+OPT_KERNEL_TIMING = 9  # 1: time finest-level sweeps and applies inside FP64 solves
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENAN, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6, -7
 _CODE_NAMES = {EINVAL: "HP_EINVAL", EDOMAIN: "HP_EDOMAIN", ENOMEM: "HP_ENOMEM", EHIP: "HP_EHIP",
@@ -58,7 +60,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
                 ("converged", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("time_ms", ctypes.c_double),
-                ("levels", ctypes.c_int), ("status", ctypes.c_int), ("fallback", ctypes.c_int)]
+                ("levels", ctypes.c_int), ("status", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("timed_sweeps", ctypes.c_int), ("sweep_ms", ctypes.c_double),
+                ("timed_applies", ctypes.c_int), ("apply_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -47,7 +47,12 @@ struct Geo {
     int nx, ny, nz;
     int px, py, pz;        // 1 if the axis has a periodic wrap face (periodic and n >= 2)
     T cx, cy, cz;          // dt^2 / h_d^2
+    int split;             // 1: arrays of this level use the red-black split layout
 };
+
+// Red-black split layout (finest level, nx even): each x row of nx cells holds its nx/2 red
+// cells and then its nx/2 black cells, both in x order, so cell (i, j, k) of colour
+// c = (i + j + k) & 1 sits at (j + ny k) nx + c nx/2 + i/2.
 
 // Coarsening relation between level l (fine) and l+1 (coarse).
 struct Transfer {
@@ -55,6 +60,7 @@ struct Transfer {
     int ncx, ncy, ncz;     // coarse sizes
     int fx, fy, fz;        // 1 if the axis is coarsened
     int perx, pery, perz;  // 1 if the axis is periodic
+    int fsplit;            // 1 if the fine level uses the red-black split layout
 };
 
 // ---- launchers (hp_kernels.hip); all asynchronous on `s` ----
@@ -80,22 +86,31 @@ void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, in
 template <typename T>
 bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                      const RedCtl& rc, hipStream_t s);
-// zero-guess red half sweep followed by a black half sweep, in one pass (needs dinv);
-// returns false (and does nothing) when the level uses the small-grid kernels
-// t = r - A z on red cells and 0 on black cells (valid right after a black half sweep);
-// false when the level uses the small-grid kernels
+// t = r - A z on red cells (valid right after a black half sweep, when the residual vanishes on
+// black cells); black cells of t are set to 0 in the natural layout and left unwritten in the
+// split layout. False (nothing done) when the level uses the small-grid kernels.
 template <typename T>
 bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
                       hipStream_t s);
+// zero-guess red half sweep followed by a black half sweep, in one pass (needs dinv);
+// false (nothing done) when the level uses the small-grid kernels
 template <typename T>
 bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s);
 template <typename T>
 void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z,
                       hipStream_t s);
+// coarse = R fine. red_only: the fine black cells are zero (a residual from launch_resid_red)
+// and are not read in the split layout.
 template <typename T>
-void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s);
+void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s,
+                     bool red_only = false);
 template <typename T>
 void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s);
+// natural <-> red-black split layout of one finest-level vector (src and dst differ)
+template <typename T>
+void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split, hipStream_t s);
+// whether the finest level can use the split layout (t: transfer to level 1, or null)
+bool split_layout_ok(int nx, int ny, int nz, const Transfer* t);
 template <typename T>
 void launch_coarse_solve(const double* ainv, int nc, const T* b, T* x, hipStream_t s);
 

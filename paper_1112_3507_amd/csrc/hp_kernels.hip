@@ -15,6 +15,9 @@
 // the z neighbours of the current plane in registers so every array is streamed once. Tiles are
 // numbered so that each of the 8 XCDs (which receive workgroups round-robin) works on one
 // contiguous range of z chunks, keeping y halos in its own L2.
+#include <initializer_list>
+#include <type_traits>
+
 #include "hp_internal.h"
 
 #include <algorithm>
@@ -457,17 +460,505 @@ __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
     if (MODE == 1 || MODE == 3) block_partial(part, partials);
 }
 
+// Cell pairs (i0, i0 + 1), i0 even, loaded and stored as one 2-vector; needs nx even and
+// 2-vector-aligned arrays.
+template <typename T>
+struct Pair {
+    T v0, v1;
+};
+template <typename T>
+__device__ __forceinline__ Pair<T> ldp(const T* __restrict__ p) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    const V v = *reinterpret_cast<const V*>(p);
+    return {(T)v.x, (T)v.y};
+}
+template <typename T>
+__device__ __forceinline__ void stp(T* __restrict__ p, T v0, T v1) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    V v;
+    v.x = v0;
+    v.y = v1;
+    *reinterpret_cast<V*>(p) = v;
+}
+
+// Operator apply over cell pairs: the same z march and face order as k_apply_zm, with half the
+// memory instructions (pair loads for the cell, its y and z neighbours, m and b; two scalar
+// loads for the outer x neighbours) and the pair's shared x face weighted once.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
+                                                     const T* __restrict__ rho,
+                                                     const T* __restrict__ m,
+                                                     const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y,
+                                                     double* __restrict__ partials) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int i0 = (bx * 64 + (threadIdx.x & 63)) * 2;
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
+    const int sz = g.nx * g.ny;
+    double part = 0.0;
+    if (i0 < g.nx && j < g.ny) {
+        const FaceTab<T> f0(g, i0, j), f1(g, i0 + 1, j);
+        const int oxl = f0.o[0], oxr = 1 + f1.o[1];   // outer x neighbours, from the pair base
+        const T cxl = f0.c[0], cxr = f1.c[1];
+        const int oym = f0.o[2], oyp = f0.o[3];
+        const T cym = f0.c[2], cyp = f0.c[3];
+        const int col = i0 + g.nx * j;
+        int a = col + k0 * sz;
+        bool hm, hp;
+        const int om = zoff(k0, -1, g.nz, g.pz, sz, hm);
+        const int op = zoff(k0, 1, g.nz, g.pz, sz, hp);
+        Pair<T> xc = ldp(x + a), rc = ldp(rho + a);
+        const Pair<T> xm0 = ldp(x + a + om), rm0 = ldp(rho + a + om);
+        Pair<T> xm = xm0;
+        T wzm0 = hm ? g.cz * face_kappa(rc.v0, rm0.v0) : T(0);
+        T wzm1 = hm ? g.cz * face_kappa(rc.v1, rm0.v1) : T(0);
+        Pair<T> xn = ldp(x + a + op), rn = ldp(rho + a + op);
+        T czp = hp ? g.cz : T(0);
+        T xl = x[a + oxl], xr = x[a + oxr], rl = rho[a + oxl], rr = rho[a + oxr];
+        Pair<T> xym = ldp(x + a + oym), xyp = ldp(x + a + oyp);
+        Pair<T> rym = ldp(rho + a + oym), ryp = ldp(rho + a + oyp);
+        Pair<T> mv = ldp(m + a);
+        Pair<T> bv = {T(0), T(0)};
+        if (MODE >= 2) bv = ldp(b + a);
+        for (int k = k0; k < k1; ++k) {
+            // prefetch plane k+1 (clamped to the chunk) and the pair two planes up
+            const int kn = min(k + 1, k1 - 1);
+            const int an = col + kn * sz;
+            bool hpn;
+            const int opn = zoff(kn, 1, g.nz, g.pz, sz, hpn);
+            const T xln = x[an + oxl], xrn = x[an + oxr], rln = rho[an + oxl], rrn = rho[an + oxr];
+            const Pair<T> xymn = ldp(x + an + oym), xypn = ldp(x + an + oyp);
+            const Pair<T> rymn = ldp(rho + an + oym), rypn = ldp(rho + an + oyp);
+            const Pair<T> mvn = ldp(m + an);
+            Pair<T> bvn = {T(0), T(0)};
+            if (MODE >= 2) bvn = ldp(b + an);
+            const Pair<T> xnn = ldp(x + an + opn), rnn = ldp(rho + an + opn);
+            // plane k
+            const T wx = g.cx * face_kappa(rc.v0, rc.v1);
+            const T wzp0 = czp * face_kappa(rc.v0, rn.v0);
+            const T wzp1 = czp * face_kappa(rc.v1, rn.v1);
+            T acc0 = mv.v0 * xc.v0;
+            acc0 += cxl * face_kappa(rc.v0, rl) * (xc.v0 - xl);
+            acc0 += wx * (xc.v0 - xc.v1);
+            acc0 += cym * face_kappa(rc.v0, rym.v0) * (xc.v0 - xym.v0);
+            acc0 += cyp * face_kappa(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
+            acc0 += wzm0 * (xc.v0 - xm.v0);
+            acc0 += wzp0 * (xc.v0 - xn.v0);
+            T acc1 = mv.v1 * xc.v1;
+            acc1 += wx * (xc.v1 - xc.v0);
+            acc1 += cxr * face_kappa(rc.v1, rr) * (xc.v1 - xr);
+            acc1 += cym * face_kappa(rc.v1, rym.v1) * (xc.v1 - xym.v1);
+            acc1 += cyp * face_kappa(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
+            acc1 += wzm1 * (xc.v1 - xm.v1);
+            acc1 += wzp1 * (xc.v1 - xn.v1);
+            if (MODE >= 2) {
+                acc0 = bv.v0 - acc0;
+                acc1 = bv.v1 - acc1;
+            }
+            stp(y + a, acc0, acc1);
+            if (MODE == 1) part += (double)xc.v0 * (double)acc0 + (double)xc.v1 * (double)acc1;
+            if (MODE == 3) part += (double)acc0 * (double)acc0 + (double)acc1 * (double)acc1;
+            // advance: the z+ faces of plane k are the z- faces of plane k+1
+            wzm0 = wzp0;
+            wzm1 = wzp1;
+            xm = xc;
+            xc = xn;
+            rc = rn;
+            xn = xnn;
+            rn = rnn;
+            czp = hpn ? g.cz : T(0);
+            xl = xln; xr = xrn; rl = rln; rr = rrn;
+            xym = xymn; xyp = xypn; rym = rymn; ryp = rypn;
+            mv = mvn;
+            bv = bvn;
+            a = an;
+        }
+    }
+    if (MODE == 1 || MODE == 3) block_partial(part, partials);
+}
+
+// ---- red-black split layout (finest level) ----
+// Thread (t, j) owns the cell pair (2t, 2t+1) of row j: half position t of the red and of the
+// black half of the row. Cell 2t has the colour of the row parity p = (j + k) & 1; cell 2t-1
+// (half position t-1) the other colour and cell 2t+2 (half position t+1) the same colour. The
+// y and z neighbour rows have parity 1 - p, so there cell 2t has colour 1 - p.
+
+__device__ __forceinline__ int srow(int j, int k, int nx, int ny) { return (k * ny + j) * nx; }
+
+// values of the cells (2t, 2t+1) of the row at rb whose parity is par
+template <typename T>
+__device__ __forceinline__ Pair<T> lds(const T* __restrict__ a, int rb, int hx, int t, int par) {
+    const T r = a[rb + t], b = a[rb + hx + t];
+    return par ? Pair<T>{b, r} : Pair<T>{r, b};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_relayout(const T* __restrict__ src, T* __restrict__ dst,
+                                                     int nx, int ny, int64_t npairs, int to_split) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npairs) return;
+    const int hx = nx >> 1;
+    const int64_t row = q / hx;
+    const int t = (int)(q - row * hx);
+    const int p = (int)((row % ny + row / ny) & 1);
+    const int64_t rb = row * nx;
+    const int64_t ae = rb + p * hx + t, ao = rb + (1 - p) * hx + t;
+    if (to_split) {
+        const T v0 = src[rb + 2 * t], v1 = src[rb + 2 * t + 1];
+        dst[ae] = v0;
+        dst[ao] = v1;
+    } else {
+        const T v0 = src[ae], v1 = src[ao];
+        dst[rb + 2 * t] = v0;
+        dst[rb + 2 * t + 1] = v1;
+    }
+}
+
+// plane below / above k (the plane itself where a Neumann end has no face)
+__device__ __forceinline__ int kbelow(int k, int nz, int pz) { return k > 0 ? k - 1 : (pz ? nz - 1 : k); }
+__device__ __forceinline__ int kabove(int k, int nz, int pz) { return k < nz - 1 ? k + 1 : (pz ? 0 : k); }
+
+// Per-thread neighbour rows and face factors of column pair t, row j (absent faces: factor 0 and
+// an in-bounds stand-in index).
+template <typename T>
+struct SplitCol {
+    int tm, tp, jm, jp;
+    T cxl, cxr, cym, cyp;
+    __device__ __forceinline__ SplitCol(const Geo<T>& g, int t, int j) {
+        const int hx = g.nx >> 1;
+        tm = t > 0 ? t - 1 : hx - 1;
+        tp = t < hx - 1 ? t + 1 : 0;
+        cxl = (t > 0 || g.px) ? g.cx : T(0);       // x- face of cell 2t
+        cxr = (t < hx - 1 || g.px) ? g.cx : T(0);  // x+ face of cell 2t+1
+        jm = j > 0 ? j - 1 : (g.py ? g.ny - 1 : j);
+        jp = j < g.ny - 1 ? j + 1 : (g.py ? 0 : j);
+        cym = (j > 0 || g.py) ? g.cy : T(0);
+        cyp = (j < g.ny - 1 || g.py) ? g.cy : T(0);
+    }
+};
+
+// Operator apply in the split layout: the pair march of k_apply_zp with each pair read from the
+// two halves of its row.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply_zs(Geo<T> g, ZTiles zt,
+                                                     const T* __restrict__ rho,
+                                                     const T* __restrict__ m,
+                                                     const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y,
+                                                     double* __restrict__ partials) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int hx = g.nx >> 1;
+    const int t = bx * 64 + (threadIdx.x & 63);
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
+    double part = 0.0;
+    if (t < hx && j < g.ny) {
+        const int nx = g.nx, ny = g.ny;
+        const SplitCol<T> sc(g, t, j);
+        int k = k0;
+        int p = (j + k) & 1;
+        int rb = srow(j, k, nx, ny);
+        Pair<T> xc = lds(x, rb, hx, t, p), rc = lds(rho, rb, hx, t, p);
+        const int km = kbelow(k, g.nz, g.pz), kp = kabove(k, g.nz, g.pz);
+        const Pair<T> xm0 = lds(x, srow(j, km, nx, ny), hx, t, p ^ 1);
+        const Pair<T> rm0 = lds(rho, srow(j, km, nx, ny), hx, t, p ^ 1);
+        Pair<T> xm = xm0;
+        const T czm0 = (k > 0 || g.pz) ? g.cz : T(0);
+        T wzm0 = czm0 * face_kappa(rc.v0, rm0.v0);
+        T wzm1 = czm0 * face_kappa(rc.v1, rm0.v1);
+        Pair<T> xn = lds(x, srow(j, kp, nx, ny), hx, t, p ^ 1);
+        Pair<T> rn = lds(rho, srow(j, kp, nx, ny), hx, t, p ^ 1);
+        T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
+        T xl = x[rb + (1 - p) * hx + sc.tm], xr = x[rb + p * hx + sc.tp];
+        T rl = rho[rb + (1 - p) * hx + sc.tm], rr = rho[rb + p * hx + sc.tp];
+        Pair<T> xym = lds(x, srow(sc.jm, k, nx, ny), hx, t, p ^ 1);
+        Pair<T> xyp = lds(x, srow(sc.jp, k, nx, ny), hx, t, p ^ 1);
+        Pair<T> rym = lds(rho, srow(sc.jm, k, nx, ny), hx, t, p ^ 1);
+        Pair<T> ryp = lds(rho, srow(sc.jp, k, nx, ny), hx, t, p ^ 1);
+        Pair<T> mv = lds(m, rb, hx, t, p);
+        Pair<T> bv = {T(0), T(0)};
+        if (MODE >= 2) bv = lds(b, rb, hx, t, p);
+        for (; k < k1; ++k) {
+            // prefetch plane k+1 (clamped to the chunk) and the pair two planes up
+            const int kn = min(k + 1, k1 - 1);
+            const int pn = (j + kn) & 1;
+            const int rbn = srow(j, kn, nx, ny);
+            const int knn = kabove(kn, g.nz, g.pz);
+            const T czpn = (kn < g.nz - 1 || g.pz) ? g.cz : T(0);
+            const T xln = x[rbn + (1 - pn) * hx + sc.tm], xrn = x[rbn + pn * hx + sc.tp];
+            const T rln = rho[rbn + (1 - pn) * hx + sc.tm], rrn = rho[rbn + pn * hx + sc.tp];
+            const Pair<T> xymn = lds(x, srow(sc.jm, kn, nx, ny), hx, t, pn ^ 1);
+            const Pair<T> xypn = lds(x, srow(sc.jp, kn, nx, ny), hx, t, pn ^ 1);
+            const Pair<T> rymn = lds(rho, srow(sc.jm, kn, nx, ny), hx, t, pn ^ 1);
+            const Pair<T> rypn = lds(rho, srow(sc.jp, kn, nx, ny), hx, t, pn ^ 1);
+            const Pair<T> mvn = lds(m, rbn, hx, t, pn);
+            Pair<T> bvn = {T(0), T(0)};
+            if (MODE >= 2) bvn = lds(b, rbn, hx, t, pn);
+            const Pair<T> xnn = lds(x, srow(j, knn, nx, ny), hx, t, pn ^ 1);
+            const Pair<T> rnn = lds(rho, srow(j, knn, nx, ny), hx, t, pn ^ 1);
+            // plane k
+            const T wx = g.cx * face_kappa(rc.v0, rc.v1);
+            const T wzp0 = czp * face_kappa(rc.v0, rn.v0);
+            const T wzp1 = czp * face_kappa(rc.v1, rn.v1);
+            T acc0 = mv.v0 * xc.v0;
+            acc0 += sc.cxl * face_kappa(rc.v0, rl) * (xc.v0 - xl);
+            acc0 += wx * (xc.v0 - xc.v1);
+            acc0 += sc.cym * face_kappa(rc.v0, rym.v0) * (xc.v0 - xym.v0);
+            acc0 += sc.cyp * face_kappa(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
+            acc0 += wzm0 * (xc.v0 - xm.v0);
+            acc0 += wzp0 * (xc.v0 - xn.v0);
+            T acc1 = mv.v1 * xc.v1;
+            acc1 += wx * (xc.v1 - xc.v0);
+            acc1 += sc.cxr * face_kappa(rc.v1, rr) * (xc.v1 - xr);
+            acc1 += sc.cym * face_kappa(rc.v1, rym.v1) * (xc.v1 - xym.v1);
+            acc1 += sc.cyp * face_kappa(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
+            acc1 += wzm1 * (xc.v1 - xm.v1);
+            acc1 += wzp1 * (xc.v1 - xn.v1);
+            if (MODE >= 2) {
+                acc0 = bv.v0 - acc0;
+                acc1 = bv.v1 - acc1;
+            }
+            y[rb + p * hx + t] = acc0;
+            y[rb + (1 - p) * hx + t] = acc1;
+            if (MODE == 1) part += (double)xc.v0 * (double)acc0 + (double)xc.v1 * (double)acc1;
+            if (MODE == 3) part += (double)acc0 * (double)acc0 + (double)acc1 * (double)acc1;
+            // advance: the z+ faces of plane k are the z- faces of plane k+1
+            wzm0 = wzp0;
+            wzm1 = wzp1;
+            xm = xc;
+            xc = xn;
+            rc = rn;
+            xn = xnn;
+            rn = rnn;
+            czp = czpn;
+            xl = xln; xr = xrn; rl = rln; rr = rrn;
+            xym = xymn; xyp = xypn; rym = rymn; ryp = rypn;
+            mv = mvn;
+            bv = bvn;
+            p = pn;
+            rb = rbn;
+        }
+    }
+    if (MODE == 1 || MODE == 3) block_partial(part, partials);
+}
+
+// Half sweep of colour c in the split layout: one thread per cell of colour c (half position t
+// of row j), marching in z. Every neighbour has the other colour: x neighbours at half positions
+// t (the pair partner) and t-1 or t+1, y neighbours at t in rows j-1 and j+1, z neighbours at t
+// in the planes below and above; the other colour's z and rho at t of three consecutive planes
+// stay in registers. DOT also reduces <r, z> over both colours; RESID instead writes
+// t = r - A z on the cells of colour c only.
+template <typename T, bool DOT, bool RESID>
+__global__ __launch_bounds__(kBlock) void k_rbgs_zs(Geo<T> g, ZTiles zt,
+                                                    const T* __restrict__ rho,
+                                                    const T* __restrict__ m,
+                                                    const T* __restrict__ r, T* __restrict__ z,
+                                                    int colour, double* __restrict__ partials,
+                                                    T* __restrict__ tout) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int hx = g.nx >> 1;
+    const int t = bx * 64 + (threadIdx.x & 63);
+    const int j = by * 4 + (threadIdx.x >> 6);
+    double dsum = 0.0;
+    if (t < hx && j < g.ny) {
+        const int nx = g.nx, ny = g.ny;
+        const int ch = colour * hx, oh = (colour ^ 1) * hx;
+        const SplitCol<T> sc(g, t, j);
+        const int k0 = bz * zt.kz;
+        const int k1 = min(k0 + zt.kz, g.nz);
+        int k = k0;
+        int rb = srow(j, k, nx, ny);
+        // other colour at t: planes k-1, k, k+1
+        const int rbm = srow(j, kbelow(k, g.nz, g.pz), nx, ny);
+        const int rbp = srow(j, kabove(k, g.nz, g.pz), nx, ny);
+        T zom = z[rbm + oh + t], zoc = z[rb + oh + t], zon = z[rbp + oh + t];
+        T rom = rho[rbm + oh + t], roc = rho[rb + oh + t], ron = rho[rbp + oh + t];
+        // this plane's cell of colour c and its in-plane neighbours
+        int e = ((j + k) & 1) ^ colour;  // 0: the cell is 2t (extra x neighbour at t-1), 1: 2t+1
+        int tx = e ? sc.tp : sc.tm;
+        T ra = rho[rb + ch + t], rr = r[rb + ch + t], mm = m[rb + ch + t];
+        T zx = z[rb + oh + tx], rx = rho[rb + oh + tx];
+        T zy0 = z[srow(sc.jm, k, nx, ny) + oh + t], ry0 = rho[srow(sc.jm, k, nx, ny) + oh + t];
+        T zy1 = z[srow(sc.jp, k, nx, ny) + oh + t], ry1 = rho[srow(sc.jp, k, nx, ny) + oh + t];
+        T ro_r = DOT ? r[rb + oh + t] : T(0);
+        for (; k < k1; ++k) {
+            const int kn = min(k + 1, k1 - 1);
+            const int rbn = srow(j, kn, nx, ny);
+            const int en = ((j + kn) & 1) ^ colour;
+            const int txn = en ? sc.tp : sc.tm;
+            const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
+            // prefetch plane k+1 and the other colour two planes up
+            const T ran = rho[rbn + ch + t], rrn = r[rbn + ch + t], mmn = m[rbn + ch + t];
+            const T zxn = z[rbn + oh + txn], rxn = rho[rbn + oh + txn];
+            const int rby0 = srow(sc.jm, kn, nx, ny), rby1 = srow(sc.jp, kn, nx, ny);
+            const T zy0n = z[rby0 + oh + t], ry0n = rho[rby0 + oh + t];
+            const T zy1n = z[rby1 + oh + t], ry1n = rho[rby1 + oh + t];
+            const T zonn = z[rbnn + oh + t], ronn = rho[rbnn + oh + t];
+            const T ro_rn = DOT ? r[rbn + oh + t] : T(0);
+            // plane k; faces in the order x-, x+, y-, y+, z-, z+
+            const T czm = (k > 0 || g.pz) ? g.cz : T(0);
+            const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
+            const T wp = g.cx * face_kappa(ra, roc);                    // pair partner
+            const T we = (e ? sc.cxr : sc.cxl) * face_kappa(ra, rx);    // outer x neighbour
+            const T w0 = e ? wp : we, v0 = e ? zoc : zx;
+            const T w1 = e ? we : wp, v1 = e ? zx : zoc;
+            T sw = w0, swz = w0 * v0;
+            sw += w1;
+            swz += w1 * v1;
+            const T wy0 = sc.cym * face_kappa(ra, ry0), wy1 = sc.cyp * face_kappa(ra, ry1);
+            sw += wy0;
+            swz += wy0 * zy0;
+            sw += wy1;
+            swz += wy1 * zy1;
+            const T wzm = czm * face_kappa(ra, rom), wzp = czp * face_kappa(ra, ron);
+            sw += wzm + wzp;
+            swz += wzm * zom + wzp * zon;
+            if (RESID) {
+                const T zs = z[rb + ch + t];
+                tout[rb + ch + t] = rr + swz - (mm + sw) * zs;
+            } else {
+                const T znew = (rr + swz) / (mm + sw);
+                z[rb + ch + t] = znew;
+                if (DOT) dsum += (double)rr * (double)znew + (double)ro_r * (double)zoc;
+            }
+            // advance one plane (the other colour is not written by this sweep)
+            zom = zoc; zoc = zon; zon = zonn;
+            rom = roc; roc = ron; ron = ronn;
+            ra = ran; rr = rrn; mm = mmn;
+            zx = zxn; rx = rxn;
+            zy0 = zy0n; ry0 = ry0n; zy1 = zy1n; ry1 = ry1n;
+            ro_r = ro_rn;
+            e = en;
+            rb = rbn;
+        }
+    }
+    if (DOT) block_partial(dsum, partials);
+}
+
+// Zero-guess pre-smoothing in the split layout, one pass: z_red = r dinv on red cells and
+// z_black = dinv_b (r_b + sum_f w_f (r dinv)_nb) on black cells, whose neighbours are all red.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_presmooth_zs(Geo<T> g, ZTiles zt,
+                                                         const T* __restrict__ rho,
+                                                         const T* __restrict__ dinv,
+                                                         const T* __restrict__ r,
+                                                         T* __restrict__ z) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int hx = g.nx >> 1;
+    const int t = bx * 64 + (threadIdx.x & 63);
+    const int j = by * 4 + (threadIdx.x >> 6);
+    if (t >= hx || j >= g.ny) return;
+    const int nx = g.nx, ny = g.ny;
+    const SplitCol<T> sc(g, t, j);
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
+    int k = k0;
+    int rb = srow(j, k, nx, ny);
+    // red cells at t: q = r dinv and rho for planes k-1, k, k+1
+    const int rbm = srow(j, kbelow(k, g.nz, g.pz), nx, ny);
+    const int rbp = srow(j, kabove(k, g.nz, g.pz), nx, ny);
+    T qm = r[rbm + t] * dinv[rbm + t], qc = r[rb + t] * dinv[rb + t], qn = r[rbp + t] * dinv[rbp + t];
+    T rom = rho[rbm + t], roc = rho[rb + t], ron = rho[rbp + t];
+    // black cell of this plane and its in-plane red neighbours
+    int e = ((j + k) & 1) ^ 1;
+    int tx = e ? sc.tp : sc.tm;
+    T rb_rho = rho[rb + hx + t], rb_r = r[rb + hx + t], rb_d = dinv[rb + hx + t];
+    T qx = r[rb + tx] * dinv[rb + tx], rx = rho[rb + tx];
+    int rby0 = srow(sc.jm, k, nx, ny), rby1 = srow(sc.jp, k, nx, ny);
+    T qy0 = r[rby0 + t] * dinv[rby0 + t], ry0 = rho[rby0 + t];
+    T qy1 = r[rby1 + t] * dinv[rby1 + t], ry1 = rho[rby1 + t];
+    for (; k < k1; ++k) {
+        const int kn = min(k + 1, k1 - 1);
+        const int rbn = srow(j, kn, nx, ny);
+        const int en = ((j + kn) & 1) ^ 1;
+        const int txn = en ? sc.tp : sc.tm;
+        const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
+        // prefetch plane k+1 and the red cell two planes up
+        const T rb_rhon = rho[rbn + hx + t], rb_rn = r[rbn + hx + t], rb_dn = dinv[rbn + hx + t];
+        const T qxn = r[rbn + txn] * dinv[rbn + txn], rxn = rho[rbn + txn];
+        rby0 = srow(sc.jm, kn, nx, ny);
+        rby1 = srow(sc.jp, kn, nx, ny);
+        const T qy0n = r[rby0 + t] * dinv[rby0 + t], ry0n = rho[rby0 + t];
+        const T qy1n = r[rby1 + t] * dinv[rby1 + t], ry1n = rho[rby1 + t];
+        const T qnn = r[rbnn + t] * dinv[rbnn + t], ronn = rho[rbnn + t];
+        // plane k; faces of the black cell in the order x-, x+, y-, y+, z-, z+
+        const T czm = (k > 0 || g.pz) ? g.cz : T(0);
+        const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
+        const T wp = g.cx * face_kappa(rb_rho, roc);
+        const T we = (e ? sc.cxr : sc.cxl) * face_kappa(rb_rho, rx);
+        T swq = (e ? wp : we) * (e ? qc : qx);
+        swq += (e ? we : wp) * (e ? qx : qc);
+        swq += sc.cym * face_kappa(rb_rho, ry0) * qy0;
+        swq += sc.cyp * face_kappa(rb_rho, ry1) * qy1;
+        const T wzm = czm * face_kappa(rb_rho, rom), wzp = czp * face_kappa(rb_rho, ron);
+        swq += wzm * qm + wzp * qn;
+        z[rb + t] = qc;
+        z[rb + hx + t] = (rb_r + swq) * rb_d;
+        // advance one plane
+        qm = qc; qc = qn; qn = qnn;
+        rom = roc; roc = ron; ron = ronn;
+        rb_rho = rb_rhon; rb_r = rb_rn; rb_d = rb_dn;
+        qx = qxn; rx = rxn;
+        qy0 = qy0n; ry0 = ry0n; qy1 = qy1n; ry1 = ry1n;
+        e = en;
+        rb = rbn;
+    }
+}
+
 static bool use_zm(int nx, int ny, int nz) { return nx >= 64 && ny >= 4 && nz >= 8; }
+// largest workgroup count of the reducing z-march launches of a level (one partial per group):
+// cells (x width 64), cell pairs (width 128) and the split layout (64 half positions)
 static int64_t zm_blocks(int nx, int ny, int nz) {
-    ZTiles t = ztiles(nx, ny, nz, 64);
-    return (int64_t)t.tx * t.ty * t.tz;
+    int64_t nb = 0;
+    for (int v = 0; v < 3; ++v) {
+        ZTiles t = v == 0 ? ztiles(nx, ny, nz, 64) : v == 1 ? ztiles(nx, ny, nz, 128)
+                                                             : ztiles(std::max(nx >> 1, 1), ny, nz, 64);
+        nb = std::max<int64_t>(nb, (int64_t)t.tx * t.ty * t.tz);
+    }
+    return nb;
+}
+
+// pair kernels: z-march shape, nx even and every array aligned for 2-vector access
+template <typename T>
+static bool use_zp(const Geo<T>& g, std::initializer_list<const T*> arrays) {
+    if (sizeof(T) != 8 || !use_zm(g.nx, g.ny, g.nz) || (g.nx & 1)) return false;
+    for (const T* p : arrays)
+        if (p && (reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T))) != 0) return false;
+    return true;
 }
 
 template <typename T>
 void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T* b, T* y,
                   int mode, const RedCtl& rc, hipStream_t s) {
     int nb;
-    if (use_zm(g.nx, g.ny, g.nz)) {
+    if (g.split) {
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
+        nb = zt.tx * zt.ty * zt.tz;
+        dim3 grid(nb), block(kBlock);
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((k_apply_zs<T, 0>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 1: hipLaunchKernelGGL((k_apply_zs<T, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 2: hipLaunchKernelGGL((k_apply_zs<T, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            default: hipLaunchKernelGGL((k_apply_zs<T, 3>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+        }
+    } else if (use_zp(g, {rho, m, x, b, y})) {
+        ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+        nb = zt.tx * zt.ty * zt.tz;
+        dim3 grid(nb), block(kBlock);
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((k_apply_zp<T, 0>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 1: hipLaunchKernelGGL((k_apply_zp<T, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 2: hipLaunchKernelGGL((k_apply_zp<T, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            default: hipLaunchKernelGGL((k_apply_zp<T, 3>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+        }
+    } else if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 64);
         nb = zt.tx * zt.ty * zt.tz;
         dim3 grid(nb), block(kBlock);
@@ -758,6 +1249,12 @@ __global__ __launch_bounds__(kBlock) void k_presmooth_zm(Geo<T> g, ZTiles zt,
 template <typename T>
 bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
                       hipStream_t s) {
+    if (g.split) {
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
+        hipLaunchKernelGGL((k_rbgs_zs<T, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
+                           g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
+        return true;
+    }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
     hipLaunchKernelGGL((k_rbgs_zm<T, false, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
@@ -767,6 +1264,12 @@ bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, con
 
 template <typename T>
 bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s) {
+    if (g.split) {
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
+        hipLaunchKernelGGL((k_presmooth_zs<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt,
+                           rho, dinv, r, z);
+        return true;
+    }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
     hipLaunchKernelGGL((k_presmooth_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt, rho,
@@ -777,6 +1280,12 @@ bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, 
 template <typename T>
 void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                  hipStream_t s) {
+    if (g.split) {
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
+        hipLaunchKernelGGL((k_rbgs_zs<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
+                           g, zt, rho, m, r, z, colour, nullptr, nullptr);
+        return;
+    }
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
         hipLaunchKernelGGL((k_rbgs_zm<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
@@ -790,6 +1299,14 @@ void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, in
 template <typename T>
 bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                      const RedCtl& rc, hipStream_t s) {
+    if (g.split) {
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
+        const int nb = zt.tx * zt.ty * zt.tz;
+        hipLaunchKernelGGL((k_rbgs_zs<T, true, false>), dim3(nb), dim3(kBlock), 0, s, g, zt, rho, m, r, z,
+                           colour, rc.partials, nullptr);
+        finalize(rc, nb, s);
+        return true;
+    }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
     const int nb = zt.tx * zt.ty * zt.tz;
@@ -802,6 +1319,11 @@ bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z
 template <typename T>
 void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z,
                       hipStream_t s) {
+    if (g.split) {
+        launch_fill<T>(z, T(0), (int64_t)g.nx * g.ny * g.nz, s);
+        launch_rbgs<T>(g, rho, m, r, z, 0, s);
+        return;
+    }
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
         hipLaunchKernelGGL((k_rbgs_zm<T, true, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
@@ -895,7 +1417,9 @@ __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >
 // chunk of coarse planes per workgroup. The thread loads the fine pair (2I, 2I+1) of each of the
 // four fine rows as one 16-byte vector and takes 2I-1 / 2I+2 from its neighbour lanes; the
 // x-y weighted sum u(k) of each fine plane is reused by the two coarse planes it feeds.
-template <typename T>
+// SPLIT: the fine level uses the red-black split layout (the pair (2I, 2I+1) of a fine row sits
+// at half position I of its two halves); RED_ONLY: its black cells are zero and not read.
+template <typename T, bool SPLIT, bool RED_ONLY>
 __global__ __launch_bounds__(kBlock) void k_restrict_zm(Transfer t, ZTiles zt,
                                                         const T* __restrict__ fine,
                                                         T* __restrict__ coarse) {
@@ -912,11 +1436,15 @@ __global__ __launch_bounds__(kBlock) void k_restrict_zm(Transfer t, ZTiles zt,
     float wx[4], wy[4];
     rweights4(Ic, nfx, t.perx, wx);
     rweights4(Jc, nfy, t.pery, wy);
-    int row[4];
+    int row[4], jr[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) row[q] = wrapi(2 * Jc - 1 + q, nfy) * nfx;  // rows with w 0 are harmless
+    for (int q = 0; q < 4; ++q) {
+        jr[q] = wrapi(2 * Jc - 1 + q, nfy);  // rows with w 0 are harmless
+        row[q] = jr[q] * nfx;
+    }
     const int xl = wrapi(2 * Ic - 1, nfx), xr = wrapi(2 * Ic + 2, nfx);
     const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == t.ncx - 1);
+    const int hf = nfx >> 1;
     auto plane_sum = [&](int k) -> T {
         // weighted x-y sum of fine plane k (k already wrapped / valid)
         const T* base = fine + (int64_t)k * sf;
@@ -924,10 +1452,30 @@ __global__ __launch_bounds__(kBlock) void k_restrict_zm(Transfer t, ZTiles zt,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const T* rp = base + row[q];
-            const T f0 = rp[2 * Ic], f1 = rp[2 * Ic + 1];
-            T left = __shfl_up(f1, 1, 64), right = __shfl_down(f0, 1, 64);
-            if (edge_l) left = rp[xl];
-            if (edge_r) right = rp[xr];
+            T f0, f1, left, right;
+            if (SPLIT) {
+                // cell 2I has the row's parity as colour; 2I-1 the other one, 2I+2 the same
+                const int pf = (jr[q] + k) & 1;
+                if (RED_ONLY) {
+                    const T v = rp[Ic];
+                    f0 = pf ? T(0) : v;
+                    f1 = pf ? v : T(0);
+                } else {
+                    f0 = rp[pf * hf + Ic];
+                    f1 = rp[(1 - pf) * hf + Ic];
+                }
+                left = __shfl_up(f1, 1, 64);
+                right = __shfl_down(f0, 1, 64);
+                if (edge_l) left = (RED_ONLY && !pf) ? T(0) : rp[(1 - pf) * hf + (xl >> 1)];
+                if (edge_r) right = (RED_ONLY && pf) ? T(0) : rp[pf * hf + (xr >> 1)];
+            } else {
+                f0 = rp[2 * Ic];
+                f1 = rp[2 * Ic + 1];
+                left = __shfl_up(f1, 1, 64);
+                right = __shfl_down(f0, 1, 64);
+                if (edge_l) left = rp[xl];
+                if (edge_r) right = rp[xr];
+            }
             u += (T)wy[q] * ((T)wx[0] * left + (T)wx[1] * f0 + (T)wx[2] * f1 + (T)wx[3] * right);
         }
         return u;
@@ -955,11 +1503,16 @@ static bool transfer_zm(const Transfer& t) {
 }
 
 template <typename T>
-void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s) {
+void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
         ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64, 2);
-        hipLaunchKernelGGL((k_restrict_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t, zt,
-                           fine, coarse);
+        const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlock);
+        if (!t.fsplit)
+            hipLaunchKernelGGL((k_restrict_zm<T, false, false>), grid, block, 0, s, t, zt, fine, coarse);
+        else if (red_only)
+            hipLaunchKernelGGL((k_restrict_zm<T, true, true>), grid, block, 0, s, t, zt, fine, coarse);
+        else
+            hipLaunchKernelGGL((k_restrict_zm<T, true, false>), grid, block, 0, s, t, zt, fine, coarse);
         return;
     }
     Shape3 sh = cells_shape(t.ncx, t.ncy, t.ncz);
@@ -1014,7 +1567,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Transfer t, const T* __r
 // per wave, a chunk of fine planes (even start) per workgroup. Both cells have parent column I;
 // the second-nearest column is I-1 for 2I and I+1 for 2I+1 (taken from the neighbour lanes).
 // The x-y interpolation v(K) of coarse planes K-1, K, K+1 is kept in registers while marching.
-template <typename T>
+template <typename T, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
                                                        const T* __restrict__ coarse,
                                                        T* __restrict__ fine) {
@@ -1067,9 +1620,17 @@ __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
         const T dlo = T(0.75) * clo + T(0.25) * (up ? nlo : mlo);
         const T dhi = T(0.75) * chi + T(0.25) * (up ? nhi : mhi);
         if (valid) {
-            T* q = fp + k * sf;
-            q[0] += dlo;
-            q[1] += dhi;
+            if (SPLIT) {
+                // cell 2I has the colour of the row's parity
+                const int p = (jc + k) & 1, hf = t.nfx >> 1;
+                T* q = fine + ((int64_t)k * t.nfy + jc) * t.nfx + Ic;
+                q[p * hf] += dlo;
+                q[(1 - p) * hf] += dhi;
+            } else {
+                T* q = fp + k * sf;
+                q[0] += dlo;
+                q[1] += dhi;
+            }
         }
     }
 }
@@ -1080,12 +1641,28 @@ void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t
         ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64, 2);
         zt.kz += zt.kz & 1;  // chunks start on even fine planes
         zt.tz = (t.nfz + zt.kz - 1) / zt.kz;
-        hipLaunchKernelGGL((k_prolong_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t, zt,
-                           coarse, fine);
+        if (t.fsplit)
+            hipLaunchKernelGGL((k_prolong_zm<T, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t,
+                               zt, coarse, fine);
+        else
+            hipLaunchKernelGGL((k_prolong_zm<T, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t,
+                               zt, coarse, fine);
         return;
     }
     Shape3 sh = cells_shape(t.nfx, t.nfy, t.nfz);
     hipLaunchKernelGGL((k_prolong_add<T>), sh.grid, sh.block, 0, s, t, coarse, fine);
+}
+
+template <typename T>
+void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split, hipStream_t s) {
+    const int64_t npairs = (int64_t)(nx >> 1) * ny * nz;
+    const int64_t blocks = (npairs + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((k_relayout<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, nx, ny, npairs,
+                       to_split);
+}
+
+bool split_layout_ok(int nx, int ny, int nz, const Transfer* t) {
+    return use_zm(nx, ny, nz) && (nx % 2 == 0) && t && transfer_zm(*t);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1287,7 +1864,8 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
                                       hipStream_t);                                             \
     template bool launch_resid_red<T>(const Geo<T>&, const T*, const T*, const T*, const T*, T*, \
                                       hipStream_t);                                             \
-    template void launch_restrict<T>(const Transfer&, const T*, T*, hipStream_t);               \
+    template void launch_restrict<T>(const Transfer&, const T*, T*, hipStream_t, bool);         \
+    template void launch_relayout<T>(const T*, T*, int, int, int, int, hipStream_t);            \
     template void launch_prolong_add<T>(const Transfer&, const T*, T*, hipStream_t);            \
     template void launch_coarse_solve<T>(const double*, int, const T*, T*, hipStream_t);        \
     template void launch_dot<T>(const T*, const T*, int64_t, const RedCtl&, hipStream_t);       \

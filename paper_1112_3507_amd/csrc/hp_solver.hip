@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 using namespace hp;
@@ -53,6 +54,7 @@ struct LevelData {
     float *rho32 = nullptr, *m32 = nullptr, *dinv32 = nullptr;
     double *r = nullptr, *z = nullptr, *t = nullptr;
     float *r32 = nullptr, *z32 = nullptr, *t32 = nullptr;
+    int split = 0;  // arrays of this level are in the red-black split layout
 };
 
 bool can_coarsen(int n, int bc) {
@@ -75,6 +77,10 @@ struct hp_handle {
     std::vector<double> host_ainv;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    // split layout of the finest level: whether it is wanted, split copies of the caller's rhs and
+    // iterate, natural copies of rho and m for the network
+    int want_split = 0;
+    double *bs = nullptr, *xs = nullptr, *rho_nat = nullptr, *m_nat = nullptr;
     double* scal = nullptr;
     double* partials = nullptr;
     int* flag = nullptr;
@@ -91,9 +97,14 @@ struct hp_handle {
     int max_outer = 20;
     int coarsest_max = 512;
     hp_stats stats{};
+    // kernel timing inside solves: event pool and the (class, first event) of each timed launch
+    int timing = 0;
+    std::vector<hipEvent_t> tev;
+    std::vector<std::pair<int, int>> spans;
+    size_t tev_used = 0;
     // learned stage
     hp_net* net = nullptr;
-    double *w1 = nullptr, *w2 = nullptr;
+    double *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
 };
 
 namespace {
@@ -122,6 +133,7 @@ Geo<T> geo(const hp_handle* H, const LevelData& L) {
     g.cx = (T)(dt2 / (L.h[0] * L.h[0]));
     g.cy = (T)(dt2 / (L.h[1] * L.h[1]));
     g.cz = (T)(dt2 / (L.h[2] * L.h[2]));
+    g.split = L.split;
     return g;
 }
 
@@ -135,6 +147,7 @@ Transfer transfer(const hp_handle* H, int l) {
     t.perx = H->bc.x == HP_BC_PERIODIC;
     t.pery = H->bc.y == HP_BC_PERIODIC;
     t.perz = H->bc.z == HP_BC_PERIODIC;
+    t.fsplit = F.split;
     return t;
 }
 
@@ -151,6 +164,32 @@ int check_launch() {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(HP_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     return HP_OK;
+}
+
+// ---- kernel timing (HP_OPT_KERNEL_TIMING) ----
+enum { TIME_SWEEP = 0, TIME_APPLY = 1 };
+
+hipEvent_t timing_event(hp_handle* H) {
+    if (H->tev_used == H->tev.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        H->tev.push_back(e);
+    }
+    return H->tev[H->tev_used++];
+}
+
+// brackets one launch: time_begin before it, time_end right after it, on the handle's stream
+void time_begin(hp_handle* H, int cls) {
+    if (!H->timing) return;
+    const size_t first = H->tev_used;
+    hipEvent_t a = timing_event(H), b = timing_event(H);
+    if (!a || !b) return;
+    (void)hipEventRecord(a, H->stream);
+    H->spans.push_back({cls, (int)first});
+}
+void time_end(hp_handle* H) {
+    if (!H->timing || H->spans.empty()) return;
+    (void)hipEventRecord(H->tev[H->spans.back().second + 1], H->stream);
 }
 
 // ---- coarsest level: dense FP64 operator, Cholesky, symmetric inverse (host) ----
@@ -229,6 +268,56 @@ int build_coarse_inverse(hp_handle* H) {
     return HP_OK;
 }
 
+// ---- finest-level storage order ----
+
+bool split_allowed(const hp_handle* H) {
+    if (H->lv.size() < 2) return false;
+    const LevelData& F = H->lv[0];
+    Transfer t = transfer(H, 0);
+    return split_layout_ok(F.n[0], F.n[1], F.n[2], &t);
+}
+
+// Bring the finest level's coefficient arrays to the natural (0) or split (1) layout; the
+// relayout goes through the CG scratch vectors p and p32.
+int set_layout(hp_handle* H, int split) {
+    LevelData& F = H->lv[0];
+    if (F.split == split) return HP_OK;
+    if (split && !split_allowed(H)) return fail(HP_EINVAL, "the grid does not allow the split layout");
+    const int64_t N = F.N;
+    hipStream_t s = H->stream;
+    if (split && !H->bs) {
+        int rc;
+        if ((rc = dalloc(H, &H->bs, N)) || (rc = dalloc(H, &H->xs, N)) ||
+            (rc = dalloc(H, &H->rho_nat, N)) || (rc = dalloc(H, &H->m_nat, N)))
+            return rc;
+    }
+    if (split) {
+        HIPCHK(hipMemcpyAsync(H->rho_nat, F.rho, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(H->m_nat, F.m, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    for (double* a : {F.rho, F.m, F.dinv}) {
+        launch_relayout<double>(a, H->p, F.n[0], F.n[1], F.n[2], split, s);
+        launch_copy<double>(H->p, a, N, s);
+    }
+    for (float* a : {F.rho32, F.m32, F.dinv32}) {
+        launch_relayout<float>(a, H->p32, F.n[0], F.n[1], F.n[2], split, s);
+        launch_copy<float>(H->p32, a, N, s);
+    }
+    CHK(check_launch());
+    F.split = split;
+    return HP_OK;
+}
+
+// rho and m of the finest level in natural order (for the network's features)
+const double* rho_natural(const hp_handle* H) { return H->lv[0].split ? H->rho_nat : H->lv[0].rho; }
+const double* m_natural(const hp_handle* H) { return H->lv[0].split ? H->m_nat : H->lv[0].m; }
+
+template <typename T>
+void relayout0(hp_handle* H, const T* src, T* dst, int to_split) {
+    const LevelData& F = H->lv[0];
+    launch_relayout<T>(src, dst, F.n[0], F.n[1], F.n[2], to_split, H->stream);
+}
+
 // ---- coefficients of every level ----
 
 int load_coefficients(hp_handle* H, const double* rho, const double* c2, double dt) {
@@ -236,6 +325,7 @@ int load_coefficients(hp_handle* H, const double* rho, const double* c2, double 
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HP_EINVAL, "dt must be positive and finite");
     H->dt = dt;
     LevelData& F = H->lv[0];
+    F.split = 0;  // every array below is recomputed in natural order
     *H->host_flag = 0;
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
     launch_setup_coef(rho, c2, F.rho, F.m, F.rho32, F.m32, F.N, H->flag, H->stream);
@@ -253,7 +343,8 @@ int load_coefficients(hp_handle* H, const double* rho, const double* c2, double 
         launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
                            L.dinv32, H->stream);
     CHK(check_launch());
-    return build_coarse_inverse(H);
+    CHK(build_coarse_inverse(H));
+    return H->want_split ? set_layout(H, 1) : HP_OK;
 }
 
 // ---- V-cycle ----
@@ -300,14 +391,18 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
     }
     T* t = lvl_t<T>(L);
     // after the black half sweep the residual vanishes on black cells
-    if (!launch_resid_red<T>(g, rho, m, r, z, t, s)) launch_apply<T>(g, rho, m, z, r, t, 2, red(H, OP_NONE), s);
+    const bool red_res = launch_resid_red<T>(g, rho, m, r, z, t, s);
+    if (!red_res) launch_apply<T>(g, rho, m, z, r, t, 2, red(H, OP_NONE), s);
     LevelData& C = H->lv[l + 1];
     Transfer tr = transfer(H, l);
-    launch_restrict<T>(tr, t, lvl_r<T>(C), s);
+    launch_restrict<T>(tr, t, lvl_r<T>(C), s, red_res);
     vcycle<T>(H, l + 1, lvl_r<T>(C), lvl_z<T>(C));
     launch_prolong_add<T>(tr, lvl_z<T>(C), z, s);
     for (int it = 0; it < H->nu_post; ++it) {
+        const bool timed = (l == 0 && sizeof(T) == 8);
+        if (timed) time_begin(H, TIME_SWEEP);
         launch_rbgs<T>(g, rho, m, r, z, 1, s);
+        if (timed) time_end(H);
         if (dot && it == H->nu_post - 1) return launch_rbgs_dot<T>(g, rho, m, r, z, 0, *dot, s) ||
                                                 (launch_rbgs<T>(g, rho, m, r, z, 0, s), false);
         launch_rbgs<T>(g, rho, m, r, z, 0, s);
@@ -385,7 +480,9 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         if (st.iterations >= H->max_iter) break;
         precond64(H, H->r, H->z, OP_BETA);
         launch_xpby<double>(H->z, H->p, N, H->scal, s);
+        time_begin(H, TIME_APPLY);
         launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
+        time_end(H);
     }
     double rel;
     CHK(true_residual(H, b, x, H->z, bnorm, &rel));
@@ -493,7 +590,14 @@ int fcg_learned(hp_handle* H, const double* b, double* x, double tol, double bno
         return HP_OK;
     };
     auto precond = [&](const double* r, double* z) -> int {
-        int rc = nn_apply(H->net, s, r, F.rho, F.m, nullptr, H->w1);
+        int rc;
+        if (F.split) {  // the network works in natural order
+            relayout0<double>(H, r, H->w2, 0);
+            rc = nn_apply(H->net, s, H->w2, H->rho_nat, H->m_nat, nullptr, H->w3);
+            if (!rc) relayout0<double>(H, H->w3, H->w1, 1);
+        } else {
+            rc = nn_apply(H->net, s, r, F.rho, F.m, nullptr, H->w1);
+        }
         if (rc) return fail(rc, "network: %s", nn_error());
         launch_apply<double>(g, F.rho, F.m, H->w1, nullptr, H->w2, 0, red(H, OP_NONE), s);
         double rz1, z1az1;
@@ -578,11 +682,29 @@ int level_ok(const hp_handle* H, int level) {
     return HP_OK;
 }
 
+// Scratch vectors of the finest level for the building blocks, which take and return natural
+// order: a split finest level is relaid through the CG work vectors p and q (FP64) or p32 and
+// q32 (FP32), which hold nothing between solves.
+template <typename T> T* tmp_a(hp_handle* H);
+template <typename T> T* tmp_b(hp_handle* H);
+template <> double* tmp_a<double>(hp_handle* H) { return H->p; }
+template <> double* tmp_b<double>(hp_handle* H) { return H->q; }
+template <> float* tmp_a<float>(hp_handle* H) { return H->p32; }
+template <> float* tmp_b<float>(hp_handle* H) { return H->q32; }
+
 template <typename T>
 int apply_t(hp_handle* H, int level, const T* x, T* y) {
     CHK(level_ok(H, level));
     if (!x || !y) return fail(HP_EINVAL, "null vector");
     LevelData& L = H->lv[level];
+    if (L.split) {
+        T *a = tmp_a<T>(H), *c = tmp_b<T>(H);
+        relayout0<T>(H, x, a, 1);
+        launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), a, nullptr, c, 0, red(H, OP_NONE),
+                        H->stream);
+        relayout0<T>(H, c, y, 0);
+        return check_launch();
+    }
     launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), x, nullptr, y, 0, red(H, OP_NONE),
                     H->stream);
     return check_launch();
@@ -594,6 +716,14 @@ int smooth_t(hp_handle* H, int level, const T* r, T* z, int colour) {
     if (!r || !z) return fail(HP_EINVAL, "null vector");
     if (colour != 0 && colour != 1) return fail(HP_EINVAL, "colour must be 0 or 1");
     LevelData& L = H->lv[level];
+    if (L.split) {
+        T *a = tmp_a<T>(H), *c = tmp_b<T>(H);
+        relayout0<T>(H, r, a, 1);
+        relayout0<T>(H, z, c, 1);
+        launch_rbgs<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), a, c, colour, H->stream);
+        relayout0<T>(H, c, z, 0);
+        return check_launch();
+    }
     launch_rbgs<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), r, z, colour, H->stream);
     return check_launch();
 }
@@ -604,6 +734,13 @@ int restrict_t(hp_handle* H, int level, const T* r, const T* z, T* rc) {
     if (level + 1 >= (int)H->lv.size()) return fail(HP_EINVAL, "no coarser level below %d", level);
     if (!r || !z || !rc) return fail(HP_EINVAL, "null vector");
     LevelData& L = H->lv[level];
+    if (L.split) {
+        T *a = tmp_a<T>(H), *c = tmp_b<T>(H);
+        relayout0<T>(H, r, a, 1);
+        relayout0<T>(H, z, c, 1);
+        r = a;
+        z = c;
+    }
     launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), z, r, lvl_t<T>(L), 2, red(H, OP_NONE),
                     H->stream);
     launch_restrict<T>(transfer(H, level), lvl_t<T>(L), rc, H->stream);
@@ -615,6 +752,13 @@ int prolong_t(hp_handle* H, int level, const T* ec, T* z) {
     CHK(level_ok(H, level));
     if (level + 1 >= (int)H->lv.size()) return fail(HP_EINVAL, "no coarser level below %d", level);
     if (!ec || !z) return fail(HP_EINVAL, "null vector");
+    if (H->lv[level].split) {
+        T* a = tmp_a<T>(H);
+        relayout0<T>(H, z, a, 1);
+        launch_prolong_add<T>(transfer(H, level), ec, a, H->stream);
+        relayout0<T>(H, a, z, 0);
+        return check_launch();
+    }
     launch_prolong_add<T>(transfer(H, level), ec, z, H->stream);
     return check_launch();
 }
@@ -631,6 +775,13 @@ template <typename T>
 int precond_t(hp_handle* H, const T* r, T* z) {
     if (!H) return fail(HP_EINVAL, "null handle");
     if (!r || !z) return fail(HP_EINVAL, "null vector");
+    if (H->lv[0].split) {
+        T *a = tmp_a<T>(H), *c = tmp_b<T>(H);
+        relayout0<T>(H, r, a, 1);
+        vcycle<T>(H, 0, a, c);
+        relayout0<T>(H, c, z, 0);
+        return check_launch();
+    }
     vcycle<T>(H, 0, r, z);
     return check_launch();
 }
@@ -745,6 +896,7 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
         return bail(fail(HP_EHIP, "hipEventCreate failed"));
     if (hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), H->stream) != hipSuccess)
         return bail(fail(HP_EHIP, "hipMemsetAsync failed"));
+    H->want_split = split_allowed(H) ? 1 : 0;
     if ((rc = load_coefficients(H, rho, c2, dt))) return bail(rc);
     H->stats.levels = (int)H->lv.size();
     *out = H;
@@ -760,6 +912,7 @@ void hp_free(hp_handle* H) {
     if (H->host_flag) (void)hipHostFree(H->host_flag);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
+    for (hipEvent_t e : H->tev) (void)hipEventDestroy(e);
     delete H;
 }
 
@@ -795,6 +948,17 @@ int hp_set_option(hp_handle* H, int key, double v) {
             if (!(v >= 1)) return fail(HP_EINVAL, "max_outer must be >= 1");
             H->max_outer = (int)v;
             return HP_OK;
+        case HP_OPT_KERNEL_TIMING:
+            if (v != 0.0 && v != 1.0) return fail(HP_EINVAL, "kernel timing must be 0 or 1");
+            H->timing = (int)v;
+            return HP_OK;
+        case HP_OPT_LAYOUT: {
+            if (v != 0.0 && v != 1.0) return fail(HP_EINVAL, "layout must be 0 (natural) or 1 (split)");
+            if (v == 1.0 && !split_allowed(H)) return fail(HP_EINVAL, "the grid does not allow the split layout");
+            int rc = set_layout(H, (int)v);
+            if (rc == HP_OK) H->want_split = (int)v;
+            return rc;
+        }
         default:
             return fail(HP_EINVAL, "unknown or read-only option %d", key);
     }
@@ -810,6 +974,8 @@ int hp_get_option(const hp_handle* H, int key, double* v) {
         case HP_OPT_INNER_TOL: *v = H->inner_tol; return HP_OK;
         case HP_OPT_MAX_OUTER: *v = H->max_outer; return HP_OK;
         case HP_OPT_COARSEST_MAX: *v = H->coarsest_max; return HP_OK;
+        case HP_OPT_LAYOUT: *v = H->lv[0].split; return HP_OK;
+        case HP_OPT_KERNEL_TIMING: *v = H->timing; return HP_OK;
         default: return fail(HP_EINVAL, "unknown option %d", key);
     }
 }
@@ -838,12 +1004,22 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     LevelData& F = H->lv[0];
     const int64_t N = F.N;
     hipStream_t s = H->stream;
+    H->spans.clear();
+    H->tev_used = 0;
     HIPCHK(hipEventRecord(H->ev0, s));
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), s));
     HIPCHK(hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), s));
     launch_check_finite(b, N, H->flag, s);
     launch_check_finite(x, N, H->flag, s);
     launch_dot<double>(b, b, N, red(H, OP_STORE, S_BB), s);
+    // in the split layout the solve runs on split copies of b and x; x is copied back at the end
+    double* xu = x;
+    if (F.split) {
+        relayout0<double>(H, b, H->bs, 1);
+        relayout0<double>(H, x, H->xs, 1);
+        b = H->bs;
+        x = H->xs;
+    }
     launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
     int rc = check_launch();
     if (rc) return rc;
@@ -855,7 +1031,7 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     }
     double bnorm = std::sqrt(H->host_scal[S_BB]);
     if (bnorm == 0.0) {
-        launch_fill<double>(x, 0.0, N, s);
+        launch_fill<double>(xu, 0.0, N, s);
         st.converged = 1;
         st.rel_residual = 0.0;
         rc = HP_OK;
@@ -870,11 +1046,25 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     } else {
         rc = pcg64(H, b, x, tol, bnorm);
     }
+    if (F.split && bnorm != 0.0) relayout0<double>(H, x, xu, 0);
     HIPCHK(hipEventRecord(H->ev1, s));
     HIPCHK(hipEventSynchronize(H->ev1));
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, H->ev0, H->ev1);
     st.time_ms = ms;
+    for (const auto& sp : H->spans) {
+        float d = 0.0f;
+        if (hipEventElapsedTime(&d, H->tev[sp.second], H->tev[sp.second + 1]) != hipSuccess) continue;
+        if (sp.first == TIME_SWEEP) {
+            st.timed_sweeps++;
+            st.sweep_ms += d;
+        } else {
+            st.timed_applies++;
+            st.apply_ms += d;
+        }
+    }
+    if (st.timed_sweeps) st.sweep_ms /= st.timed_sweeps;
+    if (st.timed_applies) st.apply_ms /= st.timed_applies;
     st.status = rc;
     return rc;
 }
@@ -915,7 +1105,15 @@ int hp_residual(hp_handle* H, const double* b, const double* x, double* r, doubl
     if (!H) return fail(HP_EINVAL, "null handle");
     if (!b || !x || !r) return fail(HP_EINVAL, "null vector");
     LevelData& F = H->lv[0];
-    launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, r, 3, red(H, OP_STORE, S_RR), H->stream);
+    if (F.split) {
+        relayout0<double>(H, b, H->p, 1);
+        relayout0<double>(H, x, H->q, 1);
+        launch_apply<double>(geo<double>(H, F), F.rho, F.m, H->q, H->p, H->z, 3, red(H, OP_STORE, S_RR),
+                             H->stream);
+        relayout0<double>(H, H->z, r, 0);
+    } else {
+        launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, r, 3, red(H, OP_STORE, S_RR), H->stream);
+    }
     launch_dot<double>(b, b, F.N, red(H, OP_STORE, S_BB), H->stream);
     CHK(check_launch());
     if (rel) {
@@ -937,7 +1135,9 @@ int hp_attach_net(hp_handle* H, hp_net* net) {
                         nz, F.n[0], F.n[1], F.n[2]);
         if (!H->w1) {
             int rc;
-            if ((rc = dalloc(H, &H->w1, F.N)) || (rc = dalloc(H, &H->w2, F.N))) return rc;
+            if ((rc = dalloc(H, &H->w1, F.N)) || (rc = dalloc(H, &H->w2, F.N)) ||
+                (rc = dalloc(H, &H->w3, F.N)))
+                return rc;
         }
     }
     H->net = net;
@@ -952,14 +1152,19 @@ int hp_warm_start(hp_handle* H, const double* b, const double* p_prev, double* x
     LevelData& F = H->lv[0];
     const int64_t N = F.N;
     hipStream_t s = H->stream;
-    int rc = nn_apply(H->net, s, b, F.rho, F.m, p_prev, x);
+    int rc = nn_apply(H->net, s, b, rho_natural(H), m_natural(H), p_prev, x);
     if (rc) return fail(rc, "network: %s", nn_error());
-    launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, nullptr, H->w2, 0, red(H, OP_NONE), s);
+    const double* xa = x;  // x in the finest level's layout
+    if (F.split) {
+        relayout0<double>(H, x, H->p, 1);
+        xa = H->p;
+    }
+    launch_apply<double>(geo<double>(H, F), F.rho, F.m, xa, nullptr, H->w2, 0, red(H, OP_NONE), s);
     launch_dot<double>(b, x, N, red(H, OP_STORE, S_TMP), s);
     CHK(check_launch());
     CHK(read_scalars(H));
     const double bx = H->host_scal[S_TMP];
-    launch_dot<double>(x, H->w2, N, red(H, OP_STORE, S_TMP), s);
+    launch_dot<double>(xa, H->w2, N, red(H, OP_STORE, S_TMP), s);
     CHK(check_launch());
     CHK(read_scalars(H));
     const double xax = H->host_scal[S_TMP];
@@ -986,24 +1191,39 @@ int hp_nn_train_step_anorm(hp_handle* H, hp_net* net, const double* b, const dou
     const int64_t N = F.N;
     hipStream_t s = H->stream;
     Geo<double> g = geo<double>(H, F);
-    int rc = nn_train_forward(net, s, b, F.rho, F.m, p_prev);
+    int rc = nn_train_forward(net, s, b, rho_natural(H), m_natural(H), p_prev);
     if (rc) return fail(rc, "network: %s", nn_error());
-    // <x, A x>
-    launch_apply<double>(g, F.rho, F.m, x, nullptr, H->w2, 0, red(H, OP_NONE), s);
-    launch_dot<double>(x, H->w2, N, red(H, OP_STORE, S_TMP), s);
+    // <x, A x> (A in the finest level's layout)
+    const double* xa = x;
+    if (F.split) {
+        relayout0<double>(H, x, H->p, 1);
+        xa = H->p;
+    }
+    launch_apply<double>(g, F.rho, F.m, xa, nullptr, H->w2, 0, red(H, OP_NONE), s);
+    launch_dot<double>(xa, H->w2, N, red(H, OP_STORE, S_TMP), s);
     CHK(check_launch());
     CHK(read_scalars(H));
     const double xax = H->host_scal[S_TMP];
     if (!(xax > 0.0)) return fail(HP_EINVAL, "target must be nonzero");
     // d = estimate - x, q = A d, loss = <d, q> / <x, A x>
     if ((rc = nn_output_minus(net, x, H->w1))) return fail(rc, "network: %s", nn_error());
-    launch_apply<double>(g, F.rho, F.m, H->w1, nullptr, H->w2, 0, red(H, OP_NONE), s);
-    launch_dot<double>(H->w1, H->w2, N, red(H, OP_STORE, S_TMP), s);
+    const double* da = H->w1;
+    if (F.split) {
+        relayout0<double>(H, H->w1, H->p, 1);
+        da = H->p;
+    }
+    launch_apply<double>(g, F.rho, F.m, da, nullptr, H->w2, 0, red(H, OP_NONE), s);
+    launch_dot<double>(da, H->w2, N, red(H, OP_STORE, S_TMP), s);
     CHK(check_launch());
     CHK(read_scalars(H));
     if (loss) *loss = H->host_scal[S_TMP] / xax;
-    // dL/d(estimate) = 2 A d / <x, A x>
-    if ((rc = nn_train_backward(net, H->w2, 2.0 / xax, lr))) return fail(rc, "network: %s", nn_error());
+    // dL/d(estimate) = 2 A d / <x, A x>, handed to the network in natural order
+    const double* gd = H->w2;
+    if (F.split) {
+        relayout0<double>(H, H->w2, H->q, 0);
+        gd = H->q;
+    }
+    if ((rc = nn_train_backward(net, gd, 2.0 / xax, lr))) return fail(rc, "network: %s", nn_error());
     return check_launch();
 }
 

@@ -146,7 +146,8 @@ def test_anorm_training_reduces_loss():
     net.close()
 
 
-def test_learned_fcg_matches_oracle():
+@pytest.mark.parametrize("layout", [1, 0])
+def test_learned_fcg_matches_oracle(layout):
     n = (80, 24, 40)
     p = wl.polytrope(n, 0.001, seed=1)
     b = wl.rhs_white(n, 2)
@@ -159,6 +160,7 @@ def test_learned_fcg_matches_oracle():
     net.set_output_scale(float(np.linalg.norm(xref) / np.linalg.norm(b)))
     x = torch.zeros_like(bt)
     with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt, hp.MODE_LEARNED) as s:
+        s.set_option(hp.OPT_LAYOUT, layout)
         s.attach_net(net)
         st = s.solve(bt, x, tol=1e-10)
     torch.cuda.synchronize()
@@ -173,6 +175,37 @@ def test_learned_fcg_matches_oracle():
     assert st["converged"]
     assert np.linalg.norm(x0.cpu().numpy() - xref) / np.linalg.norm(xref) <= 1e-9
     net.close()
+
+
+def test_network_paths_agree_across_layouts():
+    """Warm start and A-norm training step give the same values with the natural and the split
+    storage of the finest level (the network itself always sees natural order)."""
+    n = (64, 16, 16)
+    p = wl.polytrope(n, 0.001, seed=7)
+    rho = torch.from_numpy(p.rho).to(DEV)
+    c2 = torch.from_numpy(p.c2).to(DEV)
+    bt = torch.from_numpy(wl.rhs_white(n, 8)).to(DEV)
+    theta = torch.from_numpy(nn.init_params(6).astype(np.float32)).to(DEV)
+    out = {}
+    for layout in (1, 0):
+        net = hp.Net(n, training=True)
+        net.set_params(theta)
+        net.set_output_scale(1e-3)
+        with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as s:
+            s.set_option(hp.OPT_LAYOUT, layout)
+            x = torch.zeros_like(bt)
+            assert s.solve(bt, x, tol=1e-10)["converged"]
+            s.attach_net(net)
+            x0 = torch.empty_like(bt)
+            s.warm_start(bt, x0)
+            loss = s.train_step_anorm(net, bt, x, 1e-3)
+            s.attach_net(None)
+        out[layout] = (x0.cpu().numpy(), loss, net.get_params().cpu().numpy())
+        net.close()
+    a, b = out[1], out[0]
+    assert np.linalg.norm(a[0] - b[0]) <= 1e-12 * np.linalg.norm(b[0])
+    assert abs(a[1] - b[1]) <= 1e-9 * abs(b[1])
+    assert np.allclose(a[2], b[2], rtol=1e-5, atol=1e-9)
 
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),

@@ -44,8 +44,16 @@ def relerr(a, b):
                  / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300))
 
 
-def make(p, mode=None):
-    return hp.setup(p.n, p.h, p.bc, dev(p.rho), dev(p.c2), p.dt, mode)
+def make(p, mode=None, layout=None):
+    s = hp.setup(p.n, p.h, p.bc, dev(p.rho), dev(p.c2), p.dt, mode)
+    if layout is not None:
+        s.set_option(hp.OPT_LAYOUT, layout)
+        assert s.get_option(hp.OPT_LAYOUT) == layout
+    return s
+
+
+# finest-level storage: red-black split (the default where the grid allows it) and natural
+LAYOUTS = [1, 0]
 
 
 @functools.lru_cache(maxsize=None)
@@ -82,13 +90,14 @@ def test_hierarchy_matches_oracle_levels():
             assert np.allclose(h, L.h, rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_apply_parity_every_level(f32):
+def test_apply_parity_every_level(f32, layout):
     p = problem(RAGGED, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(0)
     dt = torch.float32 if f32 else torch.float64
-    with make(p) as s:
+    with make(p, layout=layout) as s:
         for l, L in enumerate(lv):
             x = rng.standard_normal(L.shape)
             y = torch.empty(L.shape, dtype=dt, device=DEV)
@@ -97,13 +106,14 @@ def test_apply_parity_every_level(f32):
             assert relerr(host(y), ref) <= (2e-5 if f32 else 1e-13), (l, f32)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_smoother_half_sweeps_parity(f32):
+def test_smoother_half_sweeps_parity(f32, layout):
     p = problem(RAGGED, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(1)
     dt = torch.float32 if f32 else torch.float64
-    with make(p) as s:
+    with make(p, layout=layout) as s:
         for l, L in enumerate(lv[:-1]):
             r = rng.standard_normal(L.shape)
             z0 = rng.standard_normal(L.shape)
@@ -119,13 +129,14 @@ def test_smoother_half_sweeps_parity(f32):
                 assert relerr(host(zt), ref) <= (2e-5 if f32 else 1e-12), (l, c)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_restrict_and_prolong_parity(f32):
+def test_restrict_and_prolong_parity(f32, layout):
     p = problem(RAGGED, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(2)
     dt = torch.float32 if f32 else torch.float64
-    with make(p) as s:
+    with make(p, layout=layout) as s:
         for l in range(len(lv) - 1):
             Lf, Lc = lv[l], lv[l + 1]
             r = rng.standard_normal(Lf.shape)
@@ -147,13 +158,14 @@ def test_restrict_and_prolong_parity(f32):
             assert relerr(host(zt), zf + mg.prolong(Lf, Lc, ec)) <= (1e-6 if f32 else 1e-15), l
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_coarse_solve_and_vcycle_parity(f32):
+def test_coarse_solve_and_vcycle_parity(f32, layout):
     p = problem(RAGGED, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(3)
     dt = torch.float32 if f32 else torch.float64
-    with make(p) as s:
+    with make(p, layout=layout) as s:
         Lc = lv[-1]
         b = rng.standard_normal(Lc.shape)
         if f32:
@@ -195,6 +207,35 @@ def test_mixed_ir_matches_oracle():
         st = s.solve(dev(b), x, tol=1e-10)
     assert st["converged"] and st["rel_residual"] <= 1e-10 and st["outer_iterations"] >= 1
     assert relerr(host(x), xref) <= 1e-9
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_layouts_give_the_same_solve(mode):
+    """Natural and red-black split storage of the finest level: both solves meet the bar against
+    the oracle, and agree with each other to solver accuracy."""
+    p = problem(RAGGED, 0.001)
+    b, xref = reference(RAGGED, 0.001, 1, 2)
+    m = hp.MODE_MIXED_IR if mode == "mixed" else hp.MODE_FP64_MGPCG
+    xs = {}
+    for layout in LAYOUTS:
+        with make(p, m, layout=layout) as s:
+            x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+            st = s.solve(dev(b), x, tol=1e-10)
+            assert st["converged"] and st["rel_residual"] <= 1e-10, (layout, st)
+            xs[layout] = host(x)
+            assert relerr(xs[layout], xref) <= 1e-9, layout
+    assert relerr(xs[1], xs[0]) <= 1e-9
+
+
+def test_layout_option():
+    """The split layout is the default where the grid allows it and refused where it does not."""
+    with make(problem(RAGGED, 0.001)) as s:
+        assert s.get_option(hp.OPT_LAYOUT) == 1
+    small = problem((32, 8, 8), 0.001)
+    with make(small) as s:
+        assert s.get_option(hp.OPT_LAYOUT) == 0
+        with pytest.raises(hp.HPError):
+            s.set_option(hp.OPT_LAYOUT, 1)
 
 
 def test_jacobi_pcg_config0():
