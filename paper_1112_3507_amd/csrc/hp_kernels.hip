@@ -59,17 +59,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sum over the workgroup in a fixed order; result valid in thread 0. Every thread must call.
 __device__ double block_sum(double v) {
-    __shared__ double ws[kBlock / 64];
+    __shared__ double ws[16];
     const int tid = flat_tid();
+    const int nw = (blockDim.x * blockDim.y * blockDim.z) >> 6;
     v = wave_sum(v);
     __syncthreads();
     if ((tid & 63) == 0) ws[tid >> 6] = v;
     __syncthreads();
     double s = 0.0;
-    if (tid == 0) {
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += ws[w];
-    }
+    if (tid == 0)
+        for (int w = 0; w < nw; ++w) s += ws[w];
     return s;
 }
 
@@ -310,14 +309,16 @@ __device__ __forceinline__ void ztile(const ZTiles& t, int& bx, int& by, int& bz
     bz = (int)(L / ((unsigned)t.tx * t.ty));
 }
 
-static ZTiles ztiles(int nx, int ny, int nz, int xw, int kmin = 8) {
+// Workgroups of `rows` waves, one x row of xw columns per wave.
+static ZTiles ztiles(int nx, int ny, int nz, int xw, int kmin = 8, int rows = 4) {
     ZTiles t;
     t.tx = (nx + xw - 1) / xw;
-    t.ty = (ny + 3) / 4;
+    t.ty = (ny + rows - 1) / rows;
     int cols = t.tx * t.ty;
     t.kz = nz;
-    // aim for >= 2048 workgroups (8 per CU) with chunks of at least kmin planes
-    while (t.kz > kmin && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < 2048) t.kz = (t.kz + 1) / 2;
+    // aim for >= 8192 waves (32 per CU) with chunks of at least kmin planes
+    const int target = 8192 / rows;
+    while (t.kz > kmin && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < target) t.kz = (t.kz + 1) / 2;
     t.tz = (nz + t.kz - 1) / t.kz;
     return t;
 }
@@ -581,6 +582,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
 }
 
 // ---- red-black split layout (finest level) ----
+#ifndef HP_ZS_ROWS
+#define HP_ZS_ROWS 4
+#endif
+constexpr int kRowsS = HP_ZS_ROWS;     // x rows (waves) per workgroup of the split-layout kernels
+constexpr int kBlockS = 64 * kRowsS;
 // Thread (t, j) owns the cell pair (2t, 2t+1) of row j: half position t of the red and of the
 // black half of the row. Cell 2t has the colour of the row parity p = (j + k) & 1; cell 2t-1
 // (half position t-1) the other colour and cell 2t+2 (half position t+1) the same colour. The
@@ -643,7 +649,7 @@ struct SplitCol {
 // Operator apply in the split layout: the pair march of k_apply_zp with each pair read from the
 // two halves of its row.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_apply_zs(Geo<T> g, ZTiles zt,
+__global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
                                                      const T* __restrict__ m,
                                                      const T* __restrict__ x,
@@ -653,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_zs(Geo<T> g, ZTiles zt,
     ztile(zt, bx, by, bz);
     const int hx = g.nx >> 1;
     const int t = bx * 64 + (threadIdx.x & 63);
-    const int j = by * 4 + (threadIdx.x >> 6);
+    const int j = by * kRowsS + (threadIdx.x >> 6);
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
     double part = 0.0;
@@ -754,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_zs(Geo<T> g, ZTiles zt,
 // stay in registers. DOT also reduces <r, z> over both colours; RESID instead writes
 // t = r - A z on the cells of colour c only.
 template <typename T, bool DOT, bool RESID>
-__global__ __launch_bounds__(kBlock) void k_rbgs_zs(Geo<T> g, ZTiles zt,
+__global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
                                                     const T* __restrict__ m,
                                                     const T* __restrict__ r, T* __restrict__ z,
@@ -764,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zs(Geo<T> g, ZTiles zt,
     ztile(zt, bx, by, bz);
     const int hx = g.nx >> 1;
     const int t = bx * 64 + (threadIdx.x & 63);
-    const int j = by * 4 + (threadIdx.x >> 6);
+    const int j = by * kRowsS + (threadIdx.x >> 6);
     double dsum = 0.0;
     if (t < hx && j < g.ny) {
         const int nx = g.nx, ny = g.ny;
@@ -844,7 +850,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zs(Geo<T> g, ZTiles zt,
 // Zero-guess pre-smoothing in the split layout, one pass: z_red = r dinv on red cells and
 // z_black = dinv_b (r_b + sum_f w_f (r dinv)_nb) on black cells, whose neighbours are all red.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_presmooth_zs(Geo<T> g, ZTiles zt,
+__global__ __launch_bounds__(kBlockS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
                                                          const T* __restrict__ rho,
                                                          const T* __restrict__ dinv,
                                                          const T* __restrict__ r,
@@ -853,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void k_presmooth_zs(Geo<T> g, ZTiles zt,
     ztile(zt, bx, by, bz);
     const int hx = g.nx >> 1;
     const int t = bx * 64 + (threadIdx.x & 63);
-    const int j = by * 4 + (threadIdx.x >> 6);
+    const int j = by * kRowsS + (threadIdx.x >> 6);
     if (t >= hx || j >= g.ny) return;
     const int nx = g.nx, ny = g.ny;
     const SplitCol<T> sc(g, t, j);
@@ -919,7 +925,7 @@ static int64_t zm_blocks(int nx, int ny, int nz) {
     int64_t nb = 0;
     for (int v = 0; v < 3; ++v) {
         ZTiles t = v == 0 ? ztiles(nx, ny, nz, 64) : v == 1 ? ztiles(nx, ny, nz, 128)
-                                                             : ztiles(std::max(nx >> 1, 1), ny, nz, 64);
+                                                             : ztiles(std::max(nx >> 1, 1), ny, nz, 64, 8, kRowsS);
         nb = std::max<int64_t>(nb, (int64_t)t.tx * t.ty * t.tz);
     }
     return nb;
@@ -939,9 +945,9 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
                   int mode, const RedCtl& rc, hipStream_t s) {
     int nb;
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
         nb = zt.tx * zt.ty * zt.tz;
-        dim3 grid(nb), block(kBlock);
+        dim3 grid(nb), block(kBlockS);
         switch (mode) {
             case 0: hipLaunchKernelGGL((k_apply_zs<T, 0>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
             case 1: hipLaunchKernelGGL((k_apply_zs<T, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
@@ -1250,8 +1256,8 @@ template <typename T>
 bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
                       hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
-        hipLaunchKernelGGL((k_rbgs_zs<T, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        hipLaunchKernelGGL((k_rbgs_zs<T, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s,
                            g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
         return true;
     }
@@ -1265,8 +1271,8 @@ bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, con
 template <typename T>
 bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
-        hipLaunchKernelGGL((k_presmooth_zs<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt,
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        hipLaunchKernelGGL((k_presmooth_zs<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s, g, zt,
                            rho, dinv, r, z);
         return true;
     }
@@ -1281,8 +1287,8 @@ template <typename T>
 void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                  hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
-        hipLaunchKernelGGL((k_rbgs_zs<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        hipLaunchKernelGGL((k_rbgs_zs<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s,
                            g, zt, rho, m, r, z, colour, nullptr, nullptr);
         return;
     }
@@ -1300,9 +1306,9 @@ template <typename T>
 bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                      const RedCtl& rc, hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64);
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
         const int nb = zt.tx * zt.ty * zt.tz;
-        hipLaunchKernelGGL((k_rbgs_zs<T, true, false>), dim3(nb), dim3(kBlock), 0, s, g, zt, rho, m, r, z,
+        hipLaunchKernelGGL((k_rbgs_zs<T, true, false>), dim3(nb), dim3(kBlockS), 0, s, g, zt, rho, m, r, z,
                            colour, rc.partials, nullptr);
         finalize(rc, nb, s);
         return true;
