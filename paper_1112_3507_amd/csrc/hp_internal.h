@@ -124,6 +124,14 @@ void launch_axpy2_norm(T* x, const T* p, T* r, const T* q, int64_t n, const RedC
 // p = z + beta p (beta = scal[S_BETA])
 template <typename T>
 void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s);
+// deferred iterate update: r -= alpha q with ||r||^2 under rc; then x += alpha p and
+// p = z + beta p in one pass; x += alpha p alone where the iteration ends (alpha = scal[S_ALPHA])
+template <typename T>
+void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s);
+template <typename T>
+void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s);
+template <typename T>
+void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s);
 // z = dinv * r with <r, z> reduced
 void launch_jacobi_apply(const double* dinv, const double* r, double* z, int64_t n,
                          const RedCtl& rc, hipStream_t s);

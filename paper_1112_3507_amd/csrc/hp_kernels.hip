@@ -1753,6 +1753,61 @@ void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s)
                        s, z, p, n, scal);
 }
 
+// The CG iterate update deferred by one iteration: r -= alpha q with ||r||^2 first, then
+// x += alpha p together with the next direction p = z + beta p (p is read once for both).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy_norm(T* __restrict__ r, const T* __restrict__ q,
+                                                      int64_t n, RedCtl rc) {
+    const T alpha = (T)rc.scal[S_ALPHA];
+    double acc = 0.0;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x; a < n; a += stride) {
+        T ra = r[a] - alpha * q[a];
+        r[a] = ra;
+        acc += (double)ra * (double)ra;
+    }
+    block_partial(acc, rc.partials);
+}
+
+template <typename T>
+void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpy_norm<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, r, q, n, rc);
+    finalize(rc, vec_blocks(n), s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_xpby_x(const T* __restrict__ z, T* __restrict__ p,
+                                                   T* __restrict__ x, int64_t n,
+                                                   const double* __restrict__ scal) {
+    const T alpha = (T)scal[S_ALPHA], beta = (T)scal[S_BETA];
+    int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (a < n) {
+        const T pa = p[a];
+        x[a] += alpha * pa;
+        p[a] = z[a] + beta * pa;
+    }
+}
+
+template <typename T>
+void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s) {
+    hipLaunchKernelGGL((k_xpby_x<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, z, p, x, n, scal);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy_alpha(T* __restrict__ x, const T* __restrict__ p,
+                                                       int64_t n, const double* __restrict__ scal) {
+    const T alpha = (T)scal[S_ALPHA];
+    int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (a < n) x[a] += alpha * p[a];
+}
+
+template <typename T>
+void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpy_alpha<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, x, p, n, scal);
+}
+
 __global__ __launch_bounds__(kBlock) void k_jacobi_apply(const double* __restrict__ dinv,
                                                          const double* __restrict__ r,
                                                          double* __restrict__ z, int64_t n,
@@ -1877,6 +1932,9 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
     template void launch_dot<T>(const T*, const T*, int64_t, const RedCtl&, hipStream_t);       \
     template void launch_axpy2_norm<T>(T*, const T*, T*, const T*, int64_t, const RedCtl&,      \
                                        hipStream_t);                                            \
+    template void launch_axpy_norm<T>(T*, const T*, int64_t, const RedCtl&, hipStream_t);       \
+    template void launch_xpby_x<T>(const T*, T*, T*, int64_t, const double*, hipStream_t);      \
+    template void launch_axpy_alpha<T>(T*, const T*, int64_t, const double*, hipStream_t);      \
     template void launch_xpby<T>(const T*, T*, int64_t, const double*, hipStream_t);            \
     template void launch_fill<T>(T*, T, int64_t, hipStream_t);                                  \
     template void launch_copy<T>(const T*, T*, int64_t, hipStream_t);

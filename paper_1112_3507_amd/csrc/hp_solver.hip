@@ -456,13 +456,16 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
             launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
             restart = false;
         }
-        launch_axpy2_norm<double>(x, H->p, H->r, H->q, N, red(H, OP_STORE, S_RR), s);
+        // r -= alpha q now; x += alpha p is deferred to the next direction update (or the exit)
+        launch_axpy_norm<double>(H->r, H->q, N, red(H, OP_STORE, S_RR), s);
         CHK(check_launch());
         CHK(read_scalars(H));
         st.iterations++;
         if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
         double rr = H->host_scal[S_RR];
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite residual in iteration %d", st.iterations);
+        if (std::sqrt(rr) <= tol * bnorm || st.iterations >= H->max_iter)
+            launch_axpy_alpha<double>(x, H->p, N, H->scal, s);
         if (std::sqrt(rr) <= tol * bnorm) {
             double rel;
             CHK(true_residual(H, b, x, H->z, bnorm, &rel));
@@ -479,7 +482,7 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         }
         if (st.iterations >= H->max_iter) break;
         precond64(H, H->r, H->z, OP_BETA);
-        launch_xpby<double>(H->z, H->p, N, H->scal, s);
+        launch_xpby_x<double>(H->z, H->p, x, N, H->scal, s);
         time_begin(H, TIME_APPLY);
         launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
         time_end(H);
@@ -506,19 +509,21 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
     launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
     *its = 0;
     while (*its < budget) {
-        launch_axpy2_norm<float>(H->x32, H->p32, H->r32, H->q32, N, red(H, OP_STORE, S_RR), s);
+        // r -= alpha q; x += alpha p is deferred to the next direction update (or the end)
+        launch_axpy_norm<float>(H->r32, H->q32, N, red(H, OP_STORE, S_RR), s);
         CHK(check_launch());
         CHK(read_scalars(H));
         (*its)++;
         if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "inner CG breakdown");
         double rr = H->host_scal[S_RR];
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite inner residual");
-        if (std::sqrt(rr) <= eta) break;
+        if (std::sqrt(rr) <= eta || *its >= budget) break;
         RedCtl rc = red(H, OP_BETA);
         if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, N, rc, s);
-        launch_xpby<float>(H->z32, H->p32, N, H->scal, s);
+        launch_xpby_x<float>(H->z32, H->p32, H->x32, N, H->scal, s);
         launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
     }
+    if (*its > 0) launch_axpy_alpha<float>(H->x32, H->p32, N, H->scal, s);
     return HP_OK;
 }
 
