@@ -309,8 +309,11 @@ __device__ __forceinline__ void ztile(const ZTiles& t, int& bx, int& by, int& bz
     bz = (int)(L / ((unsigned)t.tx * t.ty));
 }
 
-// Workgroups of `rows` waves, one x row of xw columns per wave.
-static ZTiles ztiles(int nx, int ny, int nz, int xw, int kmin = 8, int rows = 4) {
+// Workgroups of `rows` waves, one x row of xw columns per wave; z chunks of at least kmin planes.
+#ifndef HP_ZMIN
+#define HP_ZMIN 4
+#endif
+static ZTiles ztiles(int nx, int ny, int nz, int xw, int kmin = HP_ZMIN, int rows = 4) {
     ZTiles t;
     t.tx = (nx + xw - 1) / xw;
     t.ty = (ny + rows - 1) / rows;
@@ -925,7 +928,7 @@ static int64_t zm_blocks(int nx, int ny, int nz) {
     int64_t nb = 0;
     for (int v = 0; v < 3; ++v) {
         ZTiles t = v == 0 ? ztiles(nx, ny, nz, 64) : v == 1 ? ztiles(nx, ny, nz, 128)
-                                                             : ztiles(std::max(nx >> 1, 1), ny, nz, 64, 8, kRowsS);
+                                                             : ztiles(std::max(nx >> 1, 1), ny, nz, 64, HP_ZMIN, kRowsS);
         nb = std::max<int64_t>(nb, (int64_t)t.tx * t.ty * t.tz);
     }
     return nb;
@@ -945,7 +948,7 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
                   int mode, const RedCtl& rc, hipStream_t s) {
     int nb;
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
         nb = zt.tx * zt.ty * zt.tz;
         dim3 grid(nb), block(kBlockS);
         switch (mode) {
@@ -1256,7 +1259,7 @@ template <typename T>
 bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
                       hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
         hipLaunchKernelGGL((k_rbgs_zs<T, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s,
                            g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
         return true;
@@ -1271,7 +1274,7 @@ bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, con
 template <typename T>
 bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
         hipLaunchKernelGGL((k_presmooth_zs<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s, g, zt,
                            rho, dinv, r, z);
         return true;
@@ -1287,7 +1290,7 @@ template <typename T>
 void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                  hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
         hipLaunchKernelGGL((k_rbgs_zs<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s,
                            g, zt, rho, m, r, z, colour, nullptr, nullptr);
         return;
@@ -1306,7 +1309,7 @@ template <typename T>
 bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                      const RedCtl& rc, hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, 8, kRowsS);
+        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
         const int nb = zt.tx * zt.ty * zt.tz;
         hipLaunchKernelGGL((k_rbgs_zs<T, true, false>), dim3(nb), dim3(kBlockS), 0, s, g, zt, rho, m, r, z,
                            colour, rc.partials, nullptr);
