@@ -88,10 +88,12 @@ bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z
                      const RedCtl& rc, hipStream_t s);
 // t = r - A z on red cells (valid right after a black half sweep, when the residual vanishes on
 // black cells); black cells of t are set to 0 in the natural layout and left unwritten in the
-// split layout. False (nothing done) when the level uses the small-grid kernels.
+// split layout. zero_guess: z is the one-pass zero-guess pre-smoothing (red values r dinv), so
+// the split kernel forms t = sum_f w_f z_black without reading r and m. False (nothing done)
+// when the level uses the small-grid kernels.
 template <typename T>
 bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
-                      hipStream_t s);
+                      hipStream_t s, bool zero_guess = false);
 // zero-guess red half sweep followed by a black half sweep, in one pass (needs dinv);
 // false (nothing done) when the level uses the small-grid kernels
 template <typename T>

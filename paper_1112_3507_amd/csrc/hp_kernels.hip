@@ -761,8 +761,10 @@ __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
 // t (the pair partner) and t-1 or t+1, y neighbours at t in rows j-1 and j+1, z neighbours at t
 // in the planes below and above; the other colour's z and rho at t of three consecutive planes
 // stay in registers. DOT also reduces <r, z> over both colours; RESID instead writes
-// t = r - A z on the cells of colour c only.
-template <typename T, bool DOT, bool RESID>
+// t = r - A z on the cells of colour c only. ZG (with RESID, colour red): z holds the zero-guess
+// pre-smoothing, whose red values are r dinv, so r - (m + sum w) z vanishes on red cells and
+// t = sum_f w_f z_nb (r and m are not read).
+template <typename T, bool DOT, bool RESID, bool ZG = false>
 __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
                                                     const T* __restrict__ m,
@@ -791,7 +793,8 @@ __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
         // this plane's cell of colour c and its in-plane neighbours
         int e = ((j + k) & 1) ^ colour;  // 0: the cell is 2t (extra x neighbour at t-1), 1: 2t+1
         int tx = e ? sc.tp : sc.tm;
-        T ra = rho[rb + ch + t], rr = r[rb + ch + t], mm = m[rb + ch + t];
+        constexpr bool RM = !(RESID && ZG);  // r and m are read
+        T ra = rho[rb + ch + t], rr = RM ? r[rb + ch + t] : T(0), mm = RM ? m[rb + ch + t] : T(0);
         T zx = z[rb + oh + tx], rx = rho[rb + oh + tx];
         T zy0 = z[srow(sc.jm, k, nx, ny) + oh + t], ry0 = rho[srow(sc.jm, k, nx, ny) + oh + t];
         T zy1 = z[srow(sc.jp, k, nx, ny) + oh + t], ry1 = rho[srow(sc.jp, k, nx, ny) + oh + t];
@@ -803,7 +806,8 @@ __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
             const int txn = en ? sc.tp : sc.tm;
             const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
             // prefetch plane k+1 and the other colour two planes up
-            const T ran = rho[rbn + ch + t], rrn = r[rbn + ch + t], mmn = m[rbn + ch + t];
+            const T ran = rho[rbn + ch + t];
+            const T rrn = RM ? r[rbn + ch + t] : T(0), mmn = RM ? m[rbn + ch + t] : T(0);
             const T zxn = z[rbn + oh + txn], rxn = rho[rbn + oh + txn];
             const int rby0 = srow(sc.jm, kn, nx, ny), rby1 = srow(sc.jp, kn, nx, ny);
             const T zy0n = z[rby0 + oh + t], ry0n = rho[rby0 + oh + t];
@@ -828,7 +832,9 @@ __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
             const T wzm = czm * face_kappa(ra, rom), wzp = czp * face_kappa(ra, ron);
             sw += wzm + wzp;
             swz += wzm * zom + wzp * zon;
-            if (RESID) {
+            if (RESID && ZG) {
+                tout[rb + ch + t] = swz;
+            } else if (RESID) {
                 const T zs = z[rb + ch + t];
                 tout[rb + ch + t] = rr + swz - (mm + sw) * zs;
             } else {
@@ -1257,11 +1263,15 @@ __global__ __launch_bounds__(kBlock) void k_presmooth_zm(Geo<T> g, ZTiles zt,
 // residual after a black half sweep: t = r - A z on red cells, 0 on black cells
 template <typename T>
 bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
-                      hipStream_t s) {
+                      hipStream_t s, bool zero_guess) {
     if (g.split) {
         ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
-        hipLaunchKernelGGL((k_rbgs_zs<T, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s,
-                           g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
+        if (zero_guess)
+            hipLaunchKernelGGL((k_rbgs_zs<T, false, true, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS),
+                               0, s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
+        else
+            hipLaunchKernelGGL((k_rbgs_zs<T, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0,
+                               s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
         return true;
     }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
@@ -1348,31 +1358,38 @@ void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* 
 
 // Fine taps of coarse index I along one axis for R = P^T / 2 (P: weights 3/4 parent, 1/4 the
 // second-nearest coarse cell; mirrored at a Neumann end, wrapped on a periodic axis).
-__device__ __forceinline__ int restrict_taps(int I, int nf, int coarsened, int periodic,
-                                             int* idx, float* w) {
+// Fine taps of coarse index I along one axis for R = P^T / 2: always four (index, weight)
+// pairs; missing taps (Neumann ends, an uncoarsened axis) get weight 0 and an in-range index, so
+// the restriction is straight-line code with all its loads independent.
+__device__ __forceinline__ void restrict_taps(int I, int nf, int coarsened, int periodic, int* idx,
+                                              float* w) {
     if (!coarsened) {
-        idx[0] = I;
-        w[0] = 1.0f;
-        return 1;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            idx[s] = I;
+            w[s] = s == 0 ? 1.0f : 0.0f;
+        }
+        return;
     }
     const int nc = nf >> 1;
-    int cnt = 0;
 #pragma unroll
-    for (int s = -1; s <= 2; ++s) {
-        int i = 2 * I + s;
+    for (int s = 0; s < 4; ++s) {
+        int i = 2 * I - 1 + s;
         if (i < 0 || i >= nf) {
-            if (!periodic) continue;
+            if (!periodic) {
+                idx[s] = 2 * I;
+                w[s] = 0.0f;
+                continue;
+            }
             i = (i + nf) % nf;
         }
         int parent = i >> 1;
         int other = (i & 1) ? parent + 1 : parent - 1;
         if (other < 0 || other >= nc) other = periodic ? (other + nc) % nc : parent;
         float p = (parent == I ? 0.75f : 0.0f) + (other == I ? 0.25f : 0.0f);
-        idx[cnt] = i;
-        w[cnt] = 0.5f * p;
-        ++cnt;
+        idx[s] = i;
+        w[s] = 0.5f * p;
     }
-    return cnt;
 }
 
 template <typename T>
@@ -1384,16 +1401,19 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Transfer t, const T* __rest
     if (I >= t.ncx || J >= t.ncy || K >= t.ncz) return;
     int ix[4], iy[4], iz[4];
     float wx[4], wy[4], wz[4];
-    int nxs = restrict_taps(I, t.nfx, t.fx, t.perx, ix, wx);
-    int nys = restrict_taps(J, t.nfy, t.fy, t.pery, iy, wy);
-    int nzs = restrict_taps(K, t.nfz, t.fz, t.perz, iz, wz);
+    restrict_taps(I, t.nfx, t.fx, t.perx, ix, wx);
+    restrict_taps(J, t.nfy, t.fy, t.pery, iy, wy);
+    restrict_taps(K, t.nfz, t.fz, t.perz, iz, wz);
     T acc = T(0);
-    for (int c = 0; c < nzs; ++c) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
         T accy = T(0);
-        for (int b = 0; b < nys; ++b) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
             const T* row = fine + (int64_t)t.nfx * (iy[b] + (int64_t)t.nfy * iz[c]);
             T accx = T(0);
-            for (int q = 0; q < nxs; ++q) accx += (T)wx[q] * row[ix[q]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) accx += (T)wx[q] * row[ix[q]];
             accy += (T)wy[b] * accx;
         }
         acc += (T)wz[c] * accy;
@@ -1927,7 +1947,7 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
     template bool launch_presmooth<T>(const Geo<T>&, const T*, const T*, const T*, T*,          \
                                       hipStream_t);                                             \
     template bool launch_resid_red<T>(const Geo<T>&, const T*, const T*, const T*, const T*, T*, \
-                                      hipStream_t);                                             \
+                                      hipStream_t, bool);                                       \
     template void launch_restrict<T>(const Transfer&, const T*, T*, hipStream_t, bool);         \
     template void launch_relayout<T>(const T*, T*, int, int, int, int, hipStream_t);            \
     template void launch_prolong_add<T>(const Transfer&, const T*, T*, hipStream_t);            \

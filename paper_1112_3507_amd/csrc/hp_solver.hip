@@ -381,7 +381,8 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
     Geo<T> g = geo<T>(H, L);
     const T* rho = lvl_rho<T>(L);
     const T* m = lvl_m<T>(L);
-    if (!launch_presmooth<T>(g, rho, lvl_dinv<T>(L), r, z, s)) {
+    const bool fused_pre = launch_presmooth<T>(g, rho, lvl_dinv<T>(L), r, z, s);
+    if (!fused_pre) {
         launch_rbgs_zero<T>(g, rho, m, r, z, s);
         launch_rbgs<T>(g, rho, m, r, z, 1, s);
     }
@@ -391,7 +392,7 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
     }
     T* t = lvl_t<T>(L);
     // after the black half sweep the residual vanishes on black cells
-    const bool red_res = launch_resid_red<T>(g, rho, m, r, z, t, s);
+    const bool red_res = launch_resid_red<T>(g, rho, m, r, z, t, s, fused_pre && H->nu_pre == 1);
     if (!red_res) launch_apply<T>(g, rho, m, z, r, t, 2, red(H, OP_NONE), s);
     LevelData& C = H->lv[l + 1];
     Transfer tr = transfer(H, l);
