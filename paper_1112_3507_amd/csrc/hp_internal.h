@@ -106,8 +106,11 @@ void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* 
 template <typename T>
 void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s,
                      bool red_only = false);
+// fine += P coarse. red_only: in the split layout only red cells are corrected (valid when a
+// black half sweep follows, which overwrites every black cell without reading it)
 template <typename T>
-void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s);
+void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s,
+                        bool red_only = false);
 // natural <-> red-black split layout of one finest-level vector (src and dst differ)
 template <typename T>
 void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split, hipStream_t s);

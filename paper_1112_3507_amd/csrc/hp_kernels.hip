@@ -1596,7 +1596,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Transfer t, const T* __r
 // per wave, a chunk of fine planes (even start) per workgroup. Both cells have parent column I;
 // the second-nearest column is I-1 for 2I and I+1 for 2I+1 (taken from the neighbour lanes).
 // The x-y interpolation v(K) of coarse planes K-1, K, K+1 is kept in registers while marching.
-template <typename T, bool SPLIT>
+// RED_ONLY (split layout): only the red cells are corrected, for a black half sweep that follows
+// and overwrites every black cell without reading it.
+template <typename T, bool SPLIT, bool RED_ONLY = false>
 __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
                                                        const T* __restrict__ coarse,
                                                        T* __restrict__ fine) {
@@ -1653,8 +1655,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
                 // cell 2I has the colour of the row's parity
                 const int p = (jc + k) & 1, hf = t.nfx >> 1;
                 T* q = fine + ((int64_t)k * t.nfy + jc) * t.nfx + Ic;
-                q[p * hf] += dlo;
-                q[(1 - p) * hf] += dhi;
+                if (RED_ONLY) {
+                    q[0] += p ? dhi : dlo;
+                } else {
+                    q[p * hf] += dlo;
+                    q[(1 - p) * hf] += dhi;
+                }
             } else {
                 T* q = fp + k * sf;
                 q[0] += dlo;
@@ -1665,12 +1671,15 @@ __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
 }
 
 template <typename T>
-void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s) {
+void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
         ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64, 2);
         zt.kz += zt.kz & 1;  // chunks start on even fine planes
         zt.tz = (t.nfz + zt.kz - 1) / zt.kz;
-        if (t.fsplit)
+        if (t.fsplit && red_only)
+            hipLaunchKernelGGL((k_prolong_zm<T, true, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
+                               t, zt, coarse, fine);
+        else if (t.fsplit)
             hipLaunchKernelGGL((k_prolong_zm<T, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t,
                                zt, coarse, fine);
         else
@@ -1950,7 +1959,7 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
                                       hipStream_t, bool);                                       \
     template void launch_restrict<T>(const Transfer&, const T*, T*, hipStream_t, bool);         \
     template void launch_relayout<T>(const T*, T*, int, int, int, int, hipStream_t);            \
-    template void launch_prolong_add<T>(const Transfer&, const T*, T*, hipStream_t);            \
+    template void launch_prolong_add<T>(const Transfer&, const T*, T*, hipStream_t, bool);      \
     template void launch_coarse_solve<T>(const double*, int, const T*, T*, hipStream_t);        \
     template void launch_dot<T>(const T*, const T*, int64_t, const RedCtl&, hipStream_t);       \
     template void launch_axpy2_norm<T>(T*, const T*, T*, const T*, int64_t, const RedCtl&,      \

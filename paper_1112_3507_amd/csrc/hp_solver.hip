@@ -398,7 +398,8 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
     Transfer tr = transfer(H, l);
     launch_restrict<T>(tr, t, lvl_r<T>(C), s, red_res);
     vcycle<T>(H, l + 1, lvl_r<T>(C), lvl_z<T>(C));
-    launch_prolong_add<T>(tr, lvl_z<T>(C), z, s);
+    // the post-smoothing starts with a black half sweep, which overwrites the black cells
+    launch_prolong_add<T>(tr, lvl_z<T>(C), z, s, true);
     for (int it = 0; it < H->nu_post; ++it) {
         const bool timed = (l == 0 && sizeof(T) == 8);
         if (timed) time_begin(H, TIME_SWEEP);
