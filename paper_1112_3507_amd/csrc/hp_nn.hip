@@ -42,6 +42,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int BX = 16, BY = 4, BZ = 4;                 // output brick
 constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;  // input brick with halo
 constexpr int HV = HX * HY * HZ;                       // 648 halo voxels
+#ifndef HP_CONV_SPW2
+#define HP_CONV_SPW2 1
+#endif
 constexpr int NCONV = 10;
 constexpr int CIN[NCONV] = {4, 16, 16, 32, 32, 64, 96, 32, 48, 16};
 constexpr int COUT[NCONV] = {16, 16, 32, 32, 64, 64, 32, 32, 16, 16};
@@ -81,84 +84,141 @@ struct ConvArgs {
     int relu;
 };
 
-template <int CT, bool OUT_F32>
+// SPW z-slices per wave: the output brick is 16 x 4 x (4 SPW) voxels.
+template <int CT, int G, int SPW, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
-    __shared__ uint4 lds[HV * 32 / 8];  // one chunk of up to 32 channels of the halo brick
+    constexpr int CC = 8 * G;                  // channels per LDS chunk
+    constexpr int FZ = 4 * SPW, FHZ = FZ + 2, FHV = HX * HY * FHZ;
+    constexpr int NU = (FHV * G + 255) / 256;  // 16-byte staging loads per thread and chunk
+    constexpr int NSTEPS = (27 * CC + 31) / 32;
+    // one output tile (16 channels): its weights of the chunk are staged in LDS too
+    constexpr bool WL = (CT == 1);
+    constexpr int NWL = WL ? 16 * 27 * G : 0;  // 16-byte weight groups of the chunk
+    constexpr int NUW = (NWL + 255) / 256;
+    __shared__ uint4 lds[FHV * G + NWL];  // one chunk of CC channels of the halo brick [+ weights]
     const int cin = p.ca + p.cb;
-    const int CC = (cin % 32 == 0) ? 32 : ((cin % 16 == 0) ? 16 : 8);
-    const int G = CC / 8;  // 16-byte channel groups per voxel in LDS
     const int bxn = (p.nx + BX - 1) / BX, byn = (p.ny + BY - 1) / BY;
     const int bid = blockIdx.x;
     const int x0 = (bid % bxn) * BX;
     const int y0 = ((bid / bxn) % byn) * BY;
-    const int z0 = (bid / (bxn * byn)) * BZ;
+    const int z0 = (bid / (bxn * byn)) * FZ;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, grp = lane >> 4;
     const int anx = p.a_up ? p.nx >> 1 : p.nx, any = p.a_up ? p.ny >> 1 : p.ny;
     const int Ktot = 27 * cin;
-    f32x4 acc[4][CT];
+    f32x4 acc[4 * SPW][CT];  // row r of slice sl at 4 sl + r
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4 * SPW; ++r)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[r][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // weight fragment of K step s: 8 consecutive k of output row ct*16 + li
+    auto wload = [&](int c0, int s, uint4* w) {
+        const int kk = s * 32 + grp * 8;
+        const int tap = kk / CC, c = kk - tap * CC;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+            w[ct] = tap < 27 ? *(const uint4*)(p.w + (int64_t)(ct * 16 + li) * Ktot + tap * cin + c0 + c)
+                             : uint4{0u, 0u, 0u, 0u};
+    };
 
     for (int c0 = 0; c0 < cin; c0 += CC) {
-        __syncthreads();
-        for (int u = tid; u < HV * G; u += 256) {
-            const int hv = u / G, cg = u - hv * G;
-            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-            int gx = x0 + hx - 1, gy = y0 + hy - 1;
-            const int gz = z0 + hz - 1;
-            gx = gx < 0 ? gx + p.nx : (gx >= p.nx ? gx - p.nx : gx);
-            gy = gy < 0 ? gy + p.ny : (gy >= p.ny ? gy - p.ny : gy);
-            const int ch = c0 + cg * 8;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (gz >= 0 && gz < p.nz) {
-                if (ch < p.ca) {
-                    int ax = gx, ay = gy, az = gz;
-                    if (p.a_up) { ax >>= 1; ay >>= 1; az >>= 1; }
-                    const int64_t vox = ((int64_t)az * any + ay) * anx + ax;
-                    v = *(const uint4*)(p.a + vox * p.ca + ch);
-                } else {
-                    const int64_t vox = ((int64_t)gz * p.ny + gy) * p.nx + gx;
-                    v = *(const uint4*)(p.b + vox * p.cb + (ch - p.ca));
+        // stage the chunk: all loads of a thread in flight before its LDS stores
+        uint4 v[NU];
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            const int u = tid + 256 * i;
+            v[i] = uint4{0u, 0u, 0u, 0u};
+            if (u < FHV * G) {
+                const int hv = u / G, cg = u - hv * G;
+                const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+                int gx = x0 + hx - 1, gy = y0 + hy - 1;
+                const int gz = z0 + hz - 1;
+                gx = gx < 0 ? gx + p.nx : (gx >= p.nx ? gx - p.nx : gx);
+                gy = gy < 0 ? gy + p.ny : (gy >= p.ny ? gy - p.ny : gy);
+                const int ch = c0 + cg * 8;
+                if (gz >= 0 && gz < p.nz) {
+                    if (ch < p.ca) {
+                        int ax = gx, ay = gy, az = gz;
+                        if (p.a_up) { ax >>= 1; ay >>= 1; az >>= 1; }
+                        const int64_t vox = ((int64_t)az * any + ay) * anx + ax;
+                        v[i] = *(const uint4*)(p.a + vox * p.ca + ch);
+                    } else {
+                        const int64_t vox = ((int64_t)gz * p.ny + gy) * p.nx + gx;
+                        v[i] = *(const uint4*)(p.b + vox * p.cb + (ch - p.ca));
+                    }
                 }
             }
-            lds[u] = v;
+        }
+        uint4 wcur[CT], wnext[CT];
+        uint4 wv[NUW > 0 ? NUW : 1];
+        if (WL) {
+            // weight row o, tap, 8-channel group of the chunk -> lds[FHV G + o 27 G + tap G + group]
+#pragma unroll
+            for (int i = 0; i < NUW; ++i) {
+                const int u = tid + 256 * i;
+                wv[i] = uint4{0u, 0u, 0u, 0u};
+                if (u < NWL) {
+                    const int o = u / (27 * G), kq = u - o * (27 * G);
+                    const int tap = kq / G, c8 = kq - tap * G;
+                    wv[i] = *(const uint4*)(p.w + (int64_t)o * Ktot + tap * cin + c0 + c8 * 8);
+                }
+            }
+        } else {
+            wload(c0, 0, wcur);
+        }
+        __syncthreads();  // the previous chunk's reads of lds are done
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            const int u = tid + 256 * i;
+            if (u < FHV * G) lds[u] = v[i];
+        }
+        if (WL) {
+#pragma unroll
+            for (int i = 0; i < NUW; ++i) {
+                const int u = tid + 256 * i;
+                if (u < NWL) lds[FHV * G + u] = wv[i];
+            }
         }
         __syncthreads();
-        const int nsteps = (27 * CC + 31) / 32;
-        for (int s = 0; s < nsteps; ++s) {
+#pragma unroll 1
+        for (int s = 0; s < NSTEPS; ++s) {
+            // next step's weights in flight while this step's products run
+            if (!WL && s + 1 < NSTEPS) wload(c0, s + 1, wnext);
             const int kk = s * 32 + grp * 8;
             const int tap = kk / CC, c = kk - tap * CC;
             const bool kv = tap < 27;
             const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
             bf16x8 af[CT];
+            if (WL) {
+                af[0] = as_bf8(kv ? lds[FHV * G + li * (27 * G) + (kk >> 3)] : uint4{0u, 0u, 0u, 0u});
+            } else {
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                uint4 wv = {0u, 0u, 0u, 0u};
-                if (kv) wv = *(const uint4*)(p.w + (int64_t)(ct * 16 + li) * Ktot + tap * cin + c0 + c);
-                af[ct] = as_bf8(wv);
+                for (int ct = 0; ct < CT; ++ct) af[ct] = as_bf8(wcur[ct]);
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int sr = 0; sr < 4 * SPW; ++sr) {
+                const int sl = sr >> 2, r = sr & 3;
                 uint4 xv = {0u, 0u, 0u, 0u};
                 if (kv) {
-                    const int hv = ((wave + dz) * HY + (r + dy)) * HX + (li + dx);
+                    const int hv = ((wave * SPW + sl + dz) * HY + (r + dy)) * HX + (li + dx);
                     xv = lds[hv * G + (c >> 3)];
                 }
                 const bf16x8 bf = as_bf8(xv);
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct)
-                    acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bf, acc[r][ct], 0, 0, 0);
+                    acc[sr][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bf, acc[sr][ct], 0, 0, 0);
+            }
+            if (!WL) {
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) wcur[ct] = wnext[ct];
             }
         }
     }
-    // epilogue: this lane holds D[o = ct*16 + 4*grp + e][voxel li of row r]
-    const int gz = z0 + wave, gx = x0 + li;
+    // epilogue: this lane holds D[o = ct*16 + 4*grp + e][voxel li of row r of slice sl]
+    const int gx = x0 + li;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int gy = y0 + r;
+    for (int sr = 0; sr < 4 * SPW; ++sr) {
+        const int gz = z0 + wave * SPW + (sr >> 2), gy = y0 + (sr & 3);
         if (gx >= p.nx || gy >= p.ny || gz >= p.nz) continue;
         const int64_t vox = ((int64_t)gz * p.ny + gy) * p.nx + gx;
 #pragma unroll
@@ -167,7 +227,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
             float v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                v[e] = acc[r][ct][e] + (p.bias ? p.bias[o + e] : 0.f);
+                v[e] = acc[sr][ct][e] + (p.bias ? p.bias[o + e] : 0.f);
                 if (p.relu) v[e] = fmaxf(v[e], 0.f);
             }
             if (OUT_F32) {
@@ -466,12 +526,20 @@ __global__ void k_relu_bwd(const float* __restrict__ g, const bf16_t* __restrict
     }
 }
 
-__global__ void k_reduce_cols(const float* __restrict__ partial, int nrows, int c, float* __restrict__ out) {
-    const int ch = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ch >= c) return;
+// column sums of partial[nrows][c]: one workgroup per column, fixed-order tree
+__global__ __launch_bounds__(256) void k_reduce_cols(const float* __restrict__ partial, int nrows, int c,
+                                                     float* __restrict__ out) {
+    __shared__ double sm[256];
+    const int ch = blockIdx.x, tid = threadIdx.x;
     double s = 0.0;
-    for (int q = 0; q < nrows; ++q) s += partial[(int64_t)q * c + ch];
-    out[ch] = (float)s;
+    for (int q = tid; q < nrows; q += 256) s += partial[(int64_t)q * c + ch];
+    sm[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) sm[tid] += sm[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[ch] = (float)sm[0];
 }
 
 // head: y[v] = sum_c d1[v][c] w[c] + b
@@ -672,14 +740,25 @@ void conv_launch(hp_net* N, int l, const bf16_t* a, int ca, int a_up, const bf16
                  const bf16_t* w, const float* bias, void* out, int cout, int relu, bool out_f32) {
     const Level& L = N->lv[level_of_conv(l)];
     ConvArgs p{a, ca, a_up, b, cb, w, bias, out, cout, L.nx, L.ny, L.nz, relu};
-    const unsigned blocks = (unsigned)(((L.nx + BX - 1) / BX) * ((L.ny + BY - 1) / BY) * ((L.nz + BZ - 1) / BZ));
     const int ct = cout / 16;
+    const int cin = ca + cb;
+    // two z-slices per wave for the 16-channel outputs (more products per staged brick)
+    const int g = (cin % 32 == 0) ? 4 : ((cin % 16 == 0) ? 2 : 1);  // 16-byte groups per chunk voxel
+    const int spw = (ct == 1 && g <= 2 && HP_CONV_SPW2) ? 2 : 1;
+    const unsigned blocks = (unsigned)(((L.nx + BX - 1) / BX) * ((L.ny + BY - 1) / BY) *
+                                       ((L.nz + 4 * spw - 1) / (4 * spw)));
+#define CONV_LAUNCH2(CTV, GV, SV)                                                                    \
+    if (out_f32)                                                                                     \
+        hipLaunchKernelGGL((k_conv_fwd<CTV, GV, SV, true>), dim3(blocks), dim3(256), 0, N->stream, p); \
+    else                                                                                             \
+        hipLaunchKernelGGL((k_conv_fwd<CTV, GV, SV, false>), dim3(blocks), dim3(256), 0, N->stream, p);
+#define CONV_LAUNCH(CTV, GV)                                                                         \
+    if (CTV == 1 && GV <= 2 && spw == 2) { CONV_LAUNCH2(CTV, GV, 2) } else { CONV_LAUNCH2(CTV, GV, 1) }
 #define CONV_CASE(CTV)                                                                           \
     case CTV:                                                                                    \
-        if (out_f32)                                                                             \
-            hipLaunchKernelGGL((k_conv_fwd<CTV, true>), dim3(blocks), dim3(256), 0, N->stream, p); \
-        else                                                                                     \
-            hipLaunchKernelGGL((k_conv_fwd<CTV, false>), dim3(blocks), dim3(256), 0, N->stream, p); \
+        if (g == 4) { CONV_LAUNCH(CTV, 4) }                                                      \
+        else if (g == 2) { CONV_LAUNCH(CTV, 2) }                                                 \
+        else { CONV_LAUNCH(CTV, 1) }                                                             \
         break;
     switch (ct) {
         CONV_CASE(1)
@@ -690,6 +769,8 @@ void conv_launch(hp_net* N, int l, const bf16_t* a, int ca, int a_up, const bf16
         default: break;
     }
 #undef CONV_CASE
+#undef CONV_LAUNCH
+#undef CONV_LAUNCH2
 }
 
 // conv input tensors of layer l in the forward pass
@@ -764,7 +845,7 @@ int backward_conv(hp_net* N, int l) {
     const int64_t rows = (L.nv + 63) / 64;
     hipLaunchKernelGGL(k_relu_bwd, dim3((unsigned)rows), dim3(256), 0, N->stream, N->gact[l], N->act[l],
                        N->gpre, L.nv, co, N->cpart);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(64), 0, N->stream, N->cpart, (int)rows, co,
+    hipLaunchKernelGGL(k_reduce_cols, dim3(co), dim3(256), 0, N->stream, N->cpart, (int)rows, co,
                        N->grad + N->boff[l]);
     // weight gradient
     ConvIn in = conv_inputs(N, l);
@@ -931,7 +1012,7 @@ int backward_net(hp_net* N) {
     const int64_t hrows = (V + 255) / 256;
     hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)hrows), dim3(64), 0, N->stream, N->gy, N->act[9],
                        N->theta + N->hoff, N->gact[9], V, N->cpart);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(64), 0, N->stream, N->cpart, (int)hrows, 17,
+    hipLaunchKernelGGL(k_reduce_cols, dim3(17), dim3(256), 0, N->stream, N->cpart, (int)hrows, 17,
                        N->grad + N->hoff);
     // decoder and encoder in reverse
     const Level& L1 = N->lv[1];
