@@ -38,6 +38,13 @@ ALG_BYTES = {
     "rbgs_half_sweep": 24.0,
 }
 
+# Algorithmic FP64 bytes per finest-level cell and MG-PCG iteration (every pass of the
+# iteration with the arrays it must touch once): apply 32, pre-smooth 32, red residual 16,
+# red-only restriction 5, red-only prolongation 9, black sweep 24, red sweep with <r, z> 28,
+# r -= alpha q 24, x += alpha p with p = z + beta p 40; plus the coarser levels (1/7 of the
+# V-cycle's finest-level 114 bytes: 16).
+ITER_BYTES_PER_CELL = 32 + 32 + 16 + 5 + 9 + 24 + 28 + 24 + 40 + 16
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -270,6 +277,12 @@ def main():
     }
     log("bench: %.2f solves/s, %.1f iterations/solve" % (value, result["iterations_mean"]))
 
+    per_iter_bytes = ITER_BYTES_PER_CELL * p.ncells
+    eff = per_iter_bytes * result["iterations_mean"] / (secs / K) / 1e9
+    result["mgpcg_effective"] = {
+        "bytes_per_cell_iteration": ITER_BYTES_PER_CELL, "GBs": round(eff, 1),
+        "frac_of_peak": round(eff / HBM_PEAK_GBS, 4),
+        "note": "whole-solve algorithmic bytes (model) / wall time per solve"}
     if not args.no_roofline:
         result["roofline"] = roofline(solver, rhs, x, p.ncells, dev, W)
         log("bench: roofline %s" % json.dumps(result["roofline"]))
