@@ -194,7 +194,36 @@ def learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base):
                      "speedup_vs_fp64_mgpcg": round(v / base, 3)}
     s.close()
     net.close()
+    out["training"] = training_leg(dev)
     return out
+
+
+def training_leg(dev, steps=10):
+    """One step of the A-norm training (network forward, loss through the solver's operator,
+    backward, Adam) on a 128^3 polytrope sample, as the training driver runs it."""
+    import torch
+    import paper_1112_3507_amd as hp
+    from paper_1112_3507_amd import train as tr
+    from paper_1112_3507_amd import workloads as wl
+    p = wl.polytrope((128, 128, 128), 0.001, seed=12345, contrast=12.0, index=1.4)
+    rho, c2 = torch.from_numpy(p.rho).to(dev), torch.from_numpy(p.c2).to(dev)
+    b = torch.from_numpy(wl.rhs_white(p.n, 12346)).to(dev)
+    x = torch.zeros_like(b)
+    net = hp.Net(p.n, training=True)
+    net.set_params(torch.from_numpy(tr.he_uniform(0)).to(dev))
+    with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as s:
+        s.solve(b, x, tol=TOL)
+        net.set_output_scale(float(x.norm() / b.norm()))
+        for _ in range(2):
+            s.train_step_anorm(net, b, x, 1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.train_step_anorm(net, b, x, 1e-4)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+    net.close()
+    return {"grid": [128, 128, 128], "ms_per_step": round(ms, 3), "steps_timed": steps}
 
 
 def cpu_baseline(p, b, n, mach, budget_s=15.0):
@@ -258,8 +287,17 @@ def main():
     rho, c2 = torch.from_numpy(p.rho).to(dev), torch.from_numpy(p.c2).to(dev)
 
     log("bench: FP64 MG-PCG, Ma=0.01, %d warmup + %d timed solves" % (W, K))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     solver = hp.setup(p.n, p.h, p.bc, rho, c2, p.dt, hp.MODE_FP64_MGPCG)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t0)
     secs, stats = run_solves(solver, rhs, x, W, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.update_coefficients(rho, c2, p.dt)
+    torch.cuda.synchronize()
+    update_ms = 1e3 * (time.perf_counter() - t0)
     value = K / secs
     its = [s["iterations"] for s in stats]
     result = {
@@ -272,6 +310,9 @@ def main():
                                % (args.n, args.n, args.n, seeds[W], seeds[-1]),
                    "grid": list(n), "mach": 0.01, "tol": TOL, "mode": "fp64_mgpcg"},
         "iterations_mean": sum(its) / len(its),
+        "solve_ms_median": round(sorted(s["time_ms"] for s in stats)[len(stats) // 2], 4),
+        "solve_ms_min": round(min(s["time_ms"] for s in stats), 4),
+        "setup_ms": round(setup_ms, 2), "update_coefficients_ms": round(update_ms, 2),
         "max_rel_residual": max(s["rel_residual"] for s in stats),
         "all_converged": all(s["converged"] for s in stats),
     }
@@ -313,6 +354,7 @@ def main():
         if lv is not None:
             var["learned_warm_start"] = lv["warm_start"]
             var["learned_fcg"] = lv["fcg"]
+            result["learned_training"] = lv["training"]
         del rho3, c23
 
     if not args.no_cpu_baseline:

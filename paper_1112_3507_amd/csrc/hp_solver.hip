@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -240,21 +241,41 @@ int build_coarse_inverse(hp_handle* H) {
             A[(size_t)i * n + j] = s / ljj;
         }
     }
-    // inverse: solve L L^T X = I column by column
+    // inverse: solve L L^T x = e_col for every column (independent, split over host threads);
+    // L y = e_col has y = 0 above row col; x goes to row col of X (the inverse is symmetric).
+    std::vector<double> U((size_t)n * n, 0.0);  // L^T, row-major, for contiguous back substitution
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k <= i; ++k) U[(size_t)k * n + i] = A[(size_t)i * n + k];
     std::vector<double>& X = H->host_ainv;
     X.assign((size_t)n * n, 0.0);
-    std::vector<double> y(n);
-    for (int col = 0; col < n; ++col) {
-        for (int i = 0; i < n; ++i) {
-            double s = (i == col) ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) s -= A[(size_t)i * n + k] * y[k];
-            y[i] = s / A[(size_t)i * n + i];
+    auto solve_columns = [&](int c0, int c1) {
+        std::vector<double> y(n);
+        for (int col = c0; col < c1; ++col) {
+            for (int i = 0; i < col; ++i) y[i] = 0.0;
+            for (int i = col; i < n; ++i) {
+                const double* Li = &A[(size_t)i * n];
+                double sum = (i == col) ? 1.0 : 0.0;
+                for (int k = col; k < i; ++k) sum -= Li[k] * y[k];
+                y[i] = sum / Li[i];
+            }
+            double* x = &X[(size_t)col * n];
+            for (int i = n - 1; i >= 0; --i) {
+                const double* Ui = &U[(size_t)i * n];
+                double sum = y[i];
+                for (int k = i + 1; k < n; ++k) sum -= Ui[k] * x[k];
+                x[i] = sum / Ui[i];
+            }
         }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int k = i + 1; k < n; ++k) s -= A[(size_t)k * n + i] * X[(size_t)k * n + col];
-            X[(size_t)i * n + col] = s / A[(size_t)i * n + i];
-        }
+    };
+    const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+    if (nthreads == 1 || n < 64) {
+        solve_columns(0, n);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t)
+            pool.emplace_back(solve_columns, (int)((int64_t)n * t / nthreads),
+                              (int)((int64_t)n * (t + 1) / nthreads));
+        for (auto& th : pool) th.join();
     }
     for (int i = 0; i < n; ++i)  // exact symmetry keeps the V-cycle a symmetric operator
         for (int j = i + 1; j < n; ++j) {
