@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
             }
         }
         __syncthreads();
-#pragma unroll 1
+#pragma unroll 2
         for (int s = 0; s < NSTEPS; ++s) {
             // next step's weights in flight while this step's products run
             if (!WL && s + 1 < NSTEPS) wload(c0, s + 1, wnext);
