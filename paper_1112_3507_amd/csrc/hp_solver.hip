@@ -89,6 +89,7 @@ struct hp_handle {
     double* host_scal = nullptr;  // pinned mirror of scal
     int* host_flag = nullptr;     // pinned
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_scal = nullptr;  // marks the copy of scal into host_scal
     std::vector<void*> allocs;
     // options
     int mode = HP_MODE_FP64_MGPCG;
@@ -440,6 +441,30 @@ int read_scalars(hp_handle* H) {
     return HP_OK;
 }
 
+// Split form of read_scalars: post_scalars enqueues the copy of the device scalars as they stand
+// at this point of the stream, later work may be enqueued behind it, and wait_scalars blocks
+// only until the copy itself has landed.
+int post_scalars(hp_handle* H) {
+    HIPCHK(hipMemcpyAsync(H->host_scal, H->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                          H->stream));
+    HIPCHK(hipEventRecord(H->ev_scal, H->stream));
+    return HP_OK;
+}
+
+int wait_scalars(hp_handle* H) {
+    HIPCHK(hipEventSynchronize(H->ev_scal));
+    return HP_OK;
+}
+
+// Whether a CG loop should enqueue the next direction before it has seen the residual norm of
+// the current iteration.  Doing so keeps the GPU busy across the host's convergence check; the
+// price is one unused preconditioner application when the iteration turns out to be the last,
+// so the look-ahead stops once the norm predicted from the last observed contraction lies within
+// a factor of ten of the target.
+bool look_ahead(double rr_prev, double ratio, double target) {
+    return !(std::sqrt(rr_prev * ratio) <= 10.0 * target);
+}
+
 // Preconditioner z = M r with <r, z> reduced under `op` (OP_RZINIT or OP_BETA).
 void precond64(hp_handle* H, const double* r, double* z, int op) {
     int64_t N = H->lv[0].N;
@@ -463,6 +488,18 @@ int true_residual(hp_handle* H, const double* b, const double* x, double* out, d
     return HP_OK;
 }
 
+// Next direction of the FP64 PCG: z = M r (beta from <r, z>), x += alpha p (the deferred update
+// of the previous step), p = z + beta p, q = A p (alpha from <p, q>).
+void next_direction64(hp_handle* H, double* x) {
+    LevelData& F = H->lv[0];
+    hipStream_t s = H->stream;
+    precond64(H, H->r, H->z, OP_BETA);
+    launch_xpby_x<double>(H->z, H->p, x, F.N, H->scal, s);
+    time_begin(H, TIME_APPLY);
+    launch_apply<double>(geo<double>(H, F), F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
+    time_end(H);
+}
+
 // FP64 PCG (Jacobi or MG preconditioner) from the current x; r holds b - A x and
 // host_scal[S_RR] its squared norm on entry.
 int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
@@ -471,6 +508,8 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
     Geo<double> g = geo<double>(H, F);
     hipStream_t s = H->stream;
     hp_stats& st = H->stats;
+    const double target = tol * bnorm;
+    double rr_prev = H->host_scal[S_RR], ratio = 1.0;
     bool restart = true;
     while (true) {
         if (restart) {
@@ -482,14 +521,23 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         // r -= alpha q now; x += alpha p is deferred to the next direction update (or the exit)
         launch_axpy_norm<double>(H->r, H->q, N, red(H, OP_STORE, S_RR), s);
         CHK(check_launch());
-        CHK(read_scalars(H));
+        CHK(post_scalars(H));
+        // the next direction only reads r and the scalars, so it may run ahead of the check
+        const bool ahead = st.iterations + 1 < H->max_iter && look_ahead(rr_prev, ratio, target);
+        if (ahead) next_direction64(H, x);
+        CHK(check_launch());
+        CHK(wait_scalars(H));
         st.iterations++;
         if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
         double rr = H->host_scal[S_RR];
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite residual in iteration %d", st.iterations);
-        if (std::sqrt(rr) <= tol * bnorm || st.iterations >= H->max_iter)
+        ratio = rr_prev > 0.0 ? rr / rr_prev : 1.0;
+        rr_prev = rr;
+        const bool conv = std::sqrt(rr) <= target;
+        // with the look-ahead the deferred x update has already been applied
+        if ((conv || st.iterations >= H->max_iter) && !ahead)
             launch_axpy_alpha<double>(x, H->p, N, H->scal, s);
-        if (std::sqrt(rr) <= tol * bnorm) {
+        if (conv) {
             double rel;
             CHK(true_residual(H, b, x, H->z, bnorm, &rel));
             st.rel_residual = rel;
@@ -500,21 +548,30 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
             launch_copy<double>(H->z, H->r, N, s);   // continue from the true residual
             st.restarts++;
             restart = true;
+            rr_prev = rel * bnorm * rel * bnorm;
+            ratio = 1.0;
             if (st.iterations >= H->max_iter) break;
             continue;
         }
         if (st.iterations >= H->max_iter) break;
-        precond64(H, H->r, H->z, OP_BETA);
-        launch_xpby_x<double>(H->z, H->p, x, N, H->scal, s);
-        time_begin(H, TIME_APPLY);
-        launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
-        time_end(H);
+        if (!ahead) next_direction64(H, x);
     }
     double rel;
     CHK(true_residual(H, b, x, H->z, bnorm, &rel));
     st.rel_residual = rel;
     return fail(HP_ENOCONV, "no convergence in %d iterations (relative residual %.3e)",
                 st.iterations, rel);
+}
+
+// Next direction of the inner FP32 PCG (the same steps as next_direction64 on the FP32 vectors).
+void next_direction32(hp_handle* H) {
+    LevelData& F = H->lv[0];
+    hipStream_t s = H->stream;
+    RedCtl rc = red(H, OP_BETA);
+    if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, F.N, rc, s);
+    launch_xpby_x<float>(H->z32, H->p32, H->x32, F.N, H->scal, s);
+    launch_apply<float>(geo<float>(H, F), F.rho32, F.m32, H->p32, nullptr, H->q32, 1,
+                        red(H, OP_ALPHA), s);
 }
 
 // FP32 MG-PCG on A32 d = r32 (unit-norm r32), d = x32 starts at 0; returns inner iterations.
@@ -531,22 +588,27 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
     launch_copy<float>(H->z32, H->p32, N, s);
     launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
     *its = 0;
+    double rr_prev = 1.0, ratio = 1.0;
+    bool ahead = false;
     while (*its < budget) {
         // r -= alpha q; x += alpha p is deferred to the next direction update (or the end)
         launch_axpy_norm<float>(H->r32, H->q32, N, red(H, OP_STORE, S_RR), s);
         CHK(check_launch());
-        CHK(read_scalars(H));
+        CHK(post_scalars(H));
+        ahead = *its + 1 < budget && look_ahead(rr_prev, ratio, eta);
+        if (ahead) next_direction32(H);
+        CHK(check_launch());
+        CHK(wait_scalars(H));
         (*its)++;
         if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "inner CG breakdown");
         double rr = H->host_scal[S_RR];
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite inner residual");
+        ratio = rr_prev > 0.0 ? rr / rr_prev : 1.0;
+        rr_prev = rr;
         if (std::sqrt(rr) <= eta || *its >= budget) break;
-        RedCtl rc = red(H, OP_BETA);
-        if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, N, rc, s);
-        launch_xpby_x<float>(H->z32, H->p32, H->x32, N, H->scal, s);
-        launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
+        if (!ahead) next_direction32(H);
     }
-    if (*its > 0) launch_axpy_alpha<float>(H->x32, H->p32, N, H->scal, s);
+    if (*its > 0 && !ahead) launch_axpy_alpha<float>(H->x32, H->p32, N, H->scal, s);
     return HP_OK;
 }
 
@@ -920,7 +982,8 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
     if (hipHostMalloc((void**)&H->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&H->host_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(HP_ENOMEM, "pinned host allocation failed"));
-    if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess)
+    if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&H->ev_scal, hipEventDisableTiming) != hipSuccess)
         return bail(fail(HP_EHIP, "hipEventCreate failed"));
     if (hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), H->stream) != hipSuccess)
         return bail(fail(HP_EHIP, "hipMemsetAsync failed"));
@@ -940,6 +1003,7 @@ void hp_free(hp_handle* H) {
     if (H->host_flag) (void)hipHostFree(H->host_flag);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
+    if (H->ev_scal) (void)hipEventDestroy(H->ev_scal);
     for (hipEvent_t e : H->tev) (void)hipEventDestroy(e);
     delete H;
 }
