@@ -649,8 +649,40 @@ struct SplitCol {
     }
 };
 
+// Neighbour exchange of the split kernels: each wave owns one row of its workgroup's kRowsS rows,
+// and per plane every wave stores the values of its row that neighbours need into LDS, the first
+// and the last wave also the rows just below and above the workgroup (the y- row of its first row
+// and the y+ row of its last row). After one barrier the y neighbours are read from the rows
+// beside a wave's own and the outer x neighbour from the adjacent lane; only a lane at the edge
+// of its tile (lane 0 for the x- side, the last lane in the tile for the x+ side) reads that
+// neighbour from memory, one plane ahead like everything else. Two plane slots make one barrier
+// per plane enough: a slot is rewritten two planes later, after every wave has passed the barrier
+// of the plane in between. The grid covers whole rows (ny a multiple of kRowsS); lanes beyond the
+// row (t >= nx/2) work on a clamped copy of the last half position and store nothing.
+static_assert(kRowsS >= 2, "the split kernels need separate first and last waves");
+
+struct SplitLane {
+    int lane, w, tl, t, j, hs;
+    bool act, gl, gr, hw;
+    __device__ __forceinline__ SplitLane(int bx, int by, int hx) {
+        lane = threadIdx.x & 63;
+        w = threadIdx.x >> 6;
+        tl = bx * 64 + lane;
+        act = tl < hx;
+        t = act ? tl : hx - 1;
+        j = by * kRowsS + w;
+        gl = lane == 0;
+        gr = !(lane < 63 && tl + 1 < hx);
+        hw = w == 0 || w == kRowsS - 1;
+        hs = w == 0 ? 0 : kRowsS + 1;
+    }
+    // neighbour lanes in LDS (own lane where memory supplies the value)
+    __device__ __forceinline__ int lm() const { return gl ? lane : lane - 1; }
+    __device__ __forceinline__ int lp() const { return gr ? lane : lane + 1; }
+};
+
 // Operator apply in the split layout: the pair march of k_apply_zp with each pair read from the
-// two halves of its row.
+// two halves of its row; pairs of x and rho of the current plane are exchanged through LDS.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
@@ -658,100 +690,131 @@ __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ x,
                                                      const T* __restrict__ b, T* __restrict__ y,
                                                      double* __restrict__ partials) {
+    __shared__ T sx[2][2][kRowsS + 2][2][64];  // [plane slot][x, rho][row][cell of the pair][lane]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
-    const int hx = g.nx >> 1;
-    const int t = bx * 64 + (threadIdx.x & 63);
-    const int j = by * kRowsS + (threadIdx.x >> 6);
+    const int nx = g.nx, ny = g.ny, hx = nx >> 1;
+    const SplitLane L(bx, by, hx);
+    const int t = L.t, j = L.j, lane = L.lane, w = L.w;
+    const SplitCol<T> sc(g, t, j);
+    const int jh = w == 0 ? sc.jm : sc.jp;
+    const int lm = L.lm(), lp = L.lp();
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
     double part = 0.0;
-    if (t < hx && j < g.ny) {
-        const int nx = g.nx, ny = g.ny;
-        const SplitCol<T> sc(g, t, j);
-        int k = k0;
-        int p = (j + k) & 1;
-        int rb = srow(j, k, nx, ny);
-        Pair<T> xc = lds(x, rb, hx, t, p), rc = lds(rho, rb, hx, t, p);
-        const int km = kbelow(k, g.nz, g.pz), kp = kabove(k, g.nz, g.pz);
-        const Pair<T> xm0 = lds(x, srow(j, km, nx, ny), hx, t, p ^ 1);
-        const Pair<T> rm0 = lds(rho, srow(j, km, nx, ny), hx, t, p ^ 1);
-        Pair<T> xm = xm0;
-        const T czm0 = (k > 0 || g.pz) ? g.cz : T(0);
-        T wzm0 = czm0 * face_kappa(rc.v0, rm0.v0);
-        T wzm1 = czm0 * face_kappa(rc.v1, rm0.v1);
-        Pair<T> xn = lds(x, srow(j, kp, nx, ny), hx, t, p ^ 1);
-        Pair<T> rn = lds(rho, srow(j, kp, nx, ny), hx, t, p ^ 1);
-        T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
-        T xl = x[rb + (1 - p) * hx + sc.tm], xr = x[rb + p * hx + sc.tp];
-        T rl = rho[rb + (1 - p) * hx + sc.tm], rr = rho[rb + p * hx + sc.tp];
-        Pair<T> xym = lds(x, srow(sc.jm, k, nx, ny), hx, t, p ^ 1);
-        Pair<T> xyp = lds(x, srow(sc.jp, k, nx, ny), hx, t, p ^ 1);
-        Pair<T> rym = lds(rho, srow(sc.jm, k, nx, ny), hx, t, p ^ 1);
-        Pair<T> ryp = lds(rho, srow(sc.jp, k, nx, ny), hx, t, p ^ 1);
-        Pair<T> mv = lds(m, rb, hx, t, p);
-        Pair<T> bv = {T(0), T(0)};
-        if (MODE >= 2) bv = lds(b, rb, hx, t, p);
-        for (; k < k1; ++k) {
-            // prefetch plane k+1 (clamped to the chunk) and the pair two planes up
-            const int kn = min(k + 1, k1 - 1);
-            const int pn = (j + kn) & 1;
-            const int rbn = srow(j, kn, nx, ny);
-            const int knn = kabove(kn, g.nz, g.pz);
-            const T czpn = (kn < g.nz - 1 || g.pz) ? g.cz : T(0);
-            const T xln = x[rbn + (1 - pn) * hx + sc.tm], xrn = x[rbn + pn * hx + sc.tp];
-            const T rln = rho[rbn + (1 - pn) * hx + sc.tm], rrn = rho[rbn + pn * hx + sc.tp];
-            const Pair<T> xymn = lds(x, srow(sc.jm, kn, nx, ny), hx, t, pn ^ 1);
-            const Pair<T> xypn = lds(x, srow(sc.jp, kn, nx, ny), hx, t, pn ^ 1);
-            const Pair<T> rymn = lds(rho, srow(sc.jm, kn, nx, ny), hx, t, pn ^ 1);
-            const Pair<T> rypn = lds(rho, srow(sc.jp, kn, nx, ny), hx, t, pn ^ 1);
-            const Pair<T> mvn = lds(m, rbn, hx, t, pn);
-            Pair<T> bvn = {T(0), T(0)};
-            if (MODE >= 2) bvn = lds(b, rbn, hx, t, pn);
-            const Pair<T> xnn = lds(x, srow(j, knn, nx, ny), hx, t, pn ^ 1);
-            const Pair<T> rnn = lds(rho, srow(j, knn, nx, ny), hx, t, pn ^ 1);
-            // plane k
-            const T wx = g.cx * face_kappa(rc.v0, rc.v1);
-            const T wzp0 = czp * face_kappa(rc.v0, rn.v0);
-            const T wzp1 = czp * face_kappa(rc.v1, rn.v1);
-            T acc0 = mv.v0 * xc.v0;
-            acc0 += sc.cxl * face_kappa(rc.v0, rl) * (xc.v0 - xl);
-            acc0 += wx * (xc.v0 - xc.v1);
-            acc0 += sc.cym * face_kappa(rc.v0, rym.v0) * (xc.v0 - xym.v0);
-            acc0 += sc.cyp * face_kappa(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
-            acc0 += wzm0 * (xc.v0 - xm.v0);
-            acc0 += wzp0 * (xc.v0 - xn.v0);
-            T acc1 = mv.v1 * xc.v1;
-            acc1 += wx * (xc.v1 - xc.v0);
-            acc1 += sc.cxr * face_kappa(rc.v1, rr) * (xc.v1 - xr);
-            acc1 += sc.cym * face_kappa(rc.v1, rym.v1) * (xc.v1 - xym.v1);
-            acc1 += sc.cyp * face_kappa(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
-            acc1 += wzm1 * (xc.v1 - xm.v1);
-            acc1 += wzp1 * (xc.v1 - xn.v1);
-            if (MODE >= 2) {
-                acc0 = bv.v0 - acc0;
-                acc1 = bv.v1 - acc1;
-            }
+    int k = k0;
+    int p = (j + k) & 1;
+    int rb = srow(j, k, nx, ny);
+    Pair<T> xc = lds(x, rb, hx, t, p), rc = lds(rho, rb, hx, t, p);
+    const int km = kbelow(k, g.nz, g.pz), kp = kabove(k, g.nz, g.pz);
+    const Pair<T> xm0 = lds(x, srow(j, km, nx, ny), hx, t, p ^ 1);
+    const Pair<T> rm0 = lds(rho, srow(j, km, nx, ny), hx, t, p ^ 1);
+    Pair<T> xm = xm0;
+    const T czm0 = (k > 0 || g.pz) ? g.cz : T(0);
+    T wzm0 = czm0 * face_kappa(rc.v0, rm0.v0);
+    T wzm1 = czm0 * face_kappa(rc.v1, rm0.v1);
+    Pair<T> xn = lds(x, srow(j, kp, nx, ny), hx, t, p ^ 1);
+    Pair<T> rn = lds(rho, srow(j, kp, nx, ny), hx, t, p ^ 1);
+    T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
+    T xl = L.gl ? x[rb + (1 - p) * hx + sc.tm] : T(0), xr = L.gr ? x[rb + p * hx + sc.tp] : T(0);
+    T rl = L.gl ? rho[rb + (1 - p) * hx + sc.tm] : T(0), rr = L.gr ? rho[rb + p * hx + sc.tp] : T(0);
+    Pair<T> xh = {T(0), T(0)}, rh = {T(0), T(0)};
+    if (L.hw) {
+        xh = lds(x, srow(jh, k, nx, ny), hx, t, p ^ 1);
+        rh = lds(rho, srow(jh, k, nx, ny), hx, t, p ^ 1);
+    }
+    Pair<T> mv = lds(m, rb, hx, t, p);
+    Pair<T> bv = {T(0), T(0)};
+    if (MODE >= 2) bv = lds(b, rb, hx, t, p);
+    for (; k < k1; ++k) {
+        // prefetch plane k+1 (clamped to the chunk) and the pair two planes up
+        const int kn = min(k + 1, k1 - 1);
+        const int pn = (j + kn) & 1;
+        const int rbn = srow(j, kn, nx, ny);
+        const int knn = kabove(kn, g.nz, g.pz);
+        const T czpn = (kn < g.nz - 1 || g.pz) ? g.cz : T(0);
+        const T xln = L.gl ? x[rbn + (1 - pn) * hx + sc.tm] : T(0);
+        const T xrn = L.gr ? x[rbn + pn * hx + sc.tp] : T(0);
+        const T rln = L.gl ? rho[rbn + (1 - pn) * hx + sc.tm] : T(0);
+        const T rrn = L.gr ? rho[rbn + pn * hx + sc.tp] : T(0);
+        Pair<T> xhn = {T(0), T(0)}, rhn = {T(0), T(0)};
+        if (L.hw) {
+            xhn = lds(x, srow(jh, kn, nx, ny), hx, t, pn ^ 1);
+            rhn = lds(rho, srow(jh, kn, nx, ny), hx, t, pn ^ 1);
+        }
+        const Pair<T> mvn = lds(m, rbn, hx, t, pn);
+        Pair<T> bvn = {T(0), T(0)};
+        if (MODE >= 2) bvn = lds(b, rbn, hx, t, pn);
+        const Pair<T> xnn = lds(x, srow(j, knn, nx, ny), hx, t, pn ^ 1);
+        const Pair<T> rnn = lds(rho, srow(j, knn, nx, ny), hx, t, pn ^ 1);
+        // exchange plane k
+        const int sl = k & 1;
+        sx[sl][0][w + 1][0][lane] = xc.v0;
+        sx[sl][0][w + 1][1][lane] = xc.v1;
+        sx[sl][1][w + 1][0][lane] = rc.v0;
+        sx[sl][1][w + 1][1][lane] = rc.v1;
+        if (L.hw) {
+            sx[sl][0][L.hs][0][lane] = xh.v0;
+            sx[sl][0][L.hs][1][lane] = xh.v1;
+            sx[sl][1][L.hs][0][lane] = rh.v0;
+            sx[sl][1][L.hs][1][lane] = rh.v1;
+        }
+        __syncthreads();
+        if (!L.gl) {
+            xl = sx[sl][0][w + 1][1][lm];
+            rl = sx[sl][1][w + 1][1][lm];
+        }
+        if (!L.gr) {
+            xr = sx[sl][0][w + 1][0][lp];
+            rr = sx[sl][1][w + 1][0][lp];
+        }
+        const Pair<T> xym = {sx[sl][0][w][0][lane], sx[sl][0][w][1][lane]};
+        const Pair<T> xyp = {sx[sl][0][w + 2][0][lane], sx[sl][0][w + 2][1][lane]};
+        const Pair<T> rym = {sx[sl][1][w][0][lane], sx[sl][1][w][1][lane]};
+        const Pair<T> ryp = {sx[sl][1][w + 2][0][lane], sx[sl][1][w + 2][1][lane]};
+        // plane k
+        const T wx = g.cx * face_kappa(rc.v0, rc.v1);
+        const T wzp0 = czp * face_kappa(rc.v0, rn.v0);
+        const T wzp1 = czp * face_kappa(rc.v1, rn.v1);
+        T acc0 = mv.v0 * xc.v0;
+        acc0 += sc.cxl * face_kappa(rc.v0, rl) * (xc.v0 - xl);
+        acc0 += wx * (xc.v0 - xc.v1);
+        acc0 += sc.cym * face_kappa(rc.v0, rym.v0) * (xc.v0 - xym.v0);
+        acc0 += sc.cyp * face_kappa(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
+        acc0 += wzm0 * (xc.v0 - xm.v0);
+        acc0 += wzp0 * (xc.v0 - xn.v0);
+        T acc1 = mv.v1 * xc.v1;
+        acc1 += wx * (xc.v1 - xc.v0);
+        acc1 += sc.cxr * face_kappa(rc.v1, rr) * (xc.v1 - xr);
+        acc1 += sc.cym * face_kappa(rc.v1, rym.v1) * (xc.v1 - xym.v1);
+        acc1 += sc.cyp * face_kappa(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
+        acc1 += wzm1 * (xc.v1 - xm.v1);
+        acc1 += wzp1 * (xc.v1 - xn.v1);
+        if (MODE >= 2) {
+            acc0 = bv.v0 - acc0;
+            acc1 = bv.v1 - acc1;
+        }
+        if (L.act) {
             y[rb + p * hx + t] = acc0;
             y[rb + (1 - p) * hx + t] = acc1;
             if (MODE == 1) part += (double)xc.v0 * (double)acc0 + (double)xc.v1 * (double)acc1;
             if (MODE == 3) part += (double)acc0 * (double)acc0 + (double)acc1 * (double)acc1;
-            // advance: the z+ faces of plane k are the z- faces of plane k+1
-            wzm0 = wzp0;
-            wzm1 = wzp1;
-            xm = xc;
-            xc = xn;
-            rc = rn;
-            xn = xnn;
-            rn = rnn;
-            czp = czpn;
-            xl = xln; xr = xrn; rl = rln; rr = rrn;
-            xym = xymn; xyp = xypn; rym = rymn; ryp = rypn;
-            mv = mvn;
-            bv = bvn;
-            p = pn;
-            rb = rbn;
         }
+        // advance: the z+ faces of plane k are the z- faces of plane k+1
+        wzm0 = wzp0;
+        wzm1 = wzp1;
+        xm = xc;
+        xc = xn;
+        rc = rn;
+        xn = xnn;
+        rn = rnn;
+        czp = czpn;
+        xl = xln; xr = xrn; rl = rln; rr = rrn;
+        xh = xhn; rh = rhn;
+        mv = mvn;
+        bv = bvn;
+        p = pn;
+        rb = rbn;
     }
     if (MODE == 1 || MODE == 3) block_partial(part, partials);
 }
@@ -760,10 +823,11 @@ __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
 // of row j), marching in z. Every neighbour has the other colour: x neighbours at half positions
 // t (the pair partner) and t-1 or t+1, y neighbours at t in rows j-1 and j+1, z neighbours at t
 // in the planes below and above; the other colour's z and rho at t of three consecutive planes
-// stay in registers. DOT also reduces <r, z> over both colours; RESID instead writes
-// t = r - A z on the cells of colour c only. ZG (with RESID, colour red): z holds the zero-guess
-// pre-smoothing, whose red values are r dinv, so r - (m + sum w) z vanishes on red cells and
-// t = sum_f w_f z_nb (r and m are not read).
+// stay in registers, and those of the current plane are exchanged through LDS for the x and y
+// neighbours. DOT also reduces <r, z> over both colours; RESID instead writes t = r - A z on the
+// cells of colour c only. ZG (with RESID, colour red): z holds the zero-guess pre-smoothing,
+// whose red values are r dinv, so r - (m + sum w) z vanishes on red cells and t = sum_f w_f z_nb
+// (r and m are not read).
 template <typename T, bool DOT, bool RESID, bool ZG = false>
 __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
@@ -771,67 +835,86 @@ __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ r, T* __restrict__ z,
                                                     int colour, double* __restrict__ partials,
                                                     T* __restrict__ tout) {
+    __shared__ T sx[2][2][kRowsS + 2][64];  // [plane slot][z, rho of the other colour][row][lane]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
-    const int hx = g.nx >> 1;
-    const int t = bx * 64 + (threadIdx.x & 63);
-    const int j = by * kRowsS + (threadIdx.x >> 6);
+    const int nx = g.nx, ny = g.ny, hx = nx >> 1;
+    const SplitLane L(bx, by, hx);
+    const int t = L.t, j = L.j, lane = L.lane, w = L.w;
+    const int ch = colour * hx, oh = (colour ^ 1) * hx;
+    const SplitCol<T> sc(g, t, j);
+    const int jh = w == 0 ? sc.jm : sc.jp;
+    const int lm = L.lm(), lp = L.lp();
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
     double dsum = 0.0;
-    if (t < hx && j < g.ny) {
-        const int nx = g.nx, ny = g.ny;
-        const int ch = colour * hx, oh = (colour ^ 1) * hx;
-        const SplitCol<T> sc(g, t, j);
-        const int k0 = bz * zt.kz;
-        const int k1 = min(k0 + zt.kz, g.nz);
-        int k = k0;
-        int rb = srow(j, k, nx, ny);
-        // other colour at t: planes k-1, k, k+1
-        const int rbm = srow(j, kbelow(k, g.nz, g.pz), nx, ny);
-        const int rbp = srow(j, kabove(k, g.nz, g.pz), nx, ny);
-        T zom = z[rbm + oh + t], zoc = z[rb + oh + t], zon = z[rbp + oh + t];
-        T rom = rho[rbm + oh + t], roc = rho[rb + oh + t], ron = rho[rbp + oh + t];
-        // this plane's cell of colour c and its in-plane neighbours
-        int e = ((j + k) & 1) ^ colour;  // 0: the cell is 2t (extra x neighbour at t-1), 1: 2t+1
-        int tx = e ? sc.tp : sc.tm;
-        constexpr bool RM = !(RESID && ZG);  // r and m are read
-        T ra = rho[rb + ch + t], rr = RM ? r[rb + ch + t] : T(0), mm = RM ? m[rb + ch + t] : T(0);
-        T zx = z[rb + oh + tx], rx = rho[rb + oh + tx];
-        T zy0 = z[srow(sc.jm, k, nx, ny) + oh + t], ry0 = rho[srow(sc.jm, k, nx, ny) + oh + t];
-        T zy1 = z[srow(sc.jp, k, nx, ny) + oh + t], ry1 = rho[srow(sc.jp, k, nx, ny) + oh + t];
-        T ro_r = DOT ? r[rb + oh + t] : T(0);
-        for (; k < k1; ++k) {
-            const int kn = min(k + 1, k1 - 1);
-            const int rbn = srow(j, kn, nx, ny);
-            const int en = ((j + kn) & 1) ^ colour;
-            const int txn = en ? sc.tp : sc.tm;
-            const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
-            // prefetch plane k+1 and the other colour two planes up
-            const T ran = rho[rbn + ch + t];
-            const T rrn = RM ? r[rbn + ch + t] : T(0), mmn = RM ? m[rbn + ch + t] : T(0);
-            const T zxn = z[rbn + oh + txn], rxn = rho[rbn + oh + txn];
-            const int rby0 = srow(sc.jm, kn, nx, ny), rby1 = srow(sc.jp, kn, nx, ny);
-            const T zy0n = z[rby0 + oh + t], ry0n = rho[rby0 + oh + t];
-            const T zy1n = z[rby1 + oh + t], ry1n = rho[rby1 + oh + t];
-            const T zonn = z[rbnn + oh + t], ronn = rho[rbnn + oh + t];
-            const T ro_rn = DOT ? r[rbn + oh + t] : T(0);
-            // plane k; faces in the order x-, x+, y-, y+, z-, z+
-            const T czm = (k > 0 || g.pz) ? g.cz : T(0);
-            const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
-            const T wp = g.cx * face_kappa(ra, roc);                    // pair partner
-            const T we = (e ? sc.cxr : sc.cxl) * face_kappa(ra, rx);    // outer x neighbour
-            const T w0 = e ? wp : we, v0 = e ? zoc : zx;
-            const T w1 = e ? we : wp, v1 = e ? zx : zoc;
-            T sw = w0, swz = w0 * v0;
-            sw += w1;
-            swz += w1 * v1;
-            const T wy0 = sc.cym * face_kappa(ra, ry0), wy1 = sc.cyp * face_kappa(ra, ry1);
-            sw += wy0;
-            swz += wy0 * zy0;
-            sw += wy1;
-            swz += wy1 * zy1;
-            const T wzm = czm * face_kappa(ra, rom), wzp = czp * face_kappa(ra, ron);
-            sw += wzm + wzp;
-            swz += wzm * zom + wzp * zon;
+    int k = k0;
+    int rb = srow(j, k, nx, ny);
+    // other colour at t: planes k-1, k, k+1
+    const int rbm = srow(j, kbelow(k, g.nz, g.pz), nx, ny);
+    const int rbp = srow(j, kabove(k, g.nz, g.pz), nx, ny);
+    T zom = z[rbm + oh + t], zoc = z[rb + oh + t], zon = z[rbp + oh + t];
+    T rom = rho[rbm + oh + t], roc = rho[rb + oh + t], ron = rho[rbp + oh + t];
+    // this plane's cell of colour c; its outer x neighbour from memory at a tile edge
+    int e = ((j + k) & 1) ^ colour;  // 0: the cell is 2t (extra x neighbour at t-1), 1: 2t+1
+    bool gx = e ? L.gr : L.gl;
+    constexpr bool RM = !(RESID && ZG);  // r and m are read
+    T ra = rho[rb + ch + t], rr = RM ? r[rb + ch + t] : T(0), mm = RM ? m[rb + ch + t] : T(0);
+    T zx = gx ? z[rb + oh + (e ? sc.tp : sc.tm)] : T(0);
+    T rx = gx ? rho[rb + oh + (e ? sc.tp : sc.tm)] : T(0);
+    T zh = L.hw ? z[srow(jh, k, nx, ny) + oh + t] : T(0);
+    T rh = L.hw ? rho[srow(jh, k, nx, ny) + oh + t] : T(0);
+    T ro_r = DOT ? r[rb + oh + t] : T(0);
+    for (; k < k1; ++k) {
+        const int kn = min(k + 1, k1 - 1);
+        const int rbn = srow(j, kn, nx, ny);
+        const int en = ((j + kn) & 1) ^ colour;
+        const bool gxn = en ? L.gr : L.gl;
+        const int txn = en ? sc.tp : sc.tm;
+        const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
+        // prefetch plane k+1 and the other colour two planes up
+        const T ran = rho[rbn + ch + t];
+        const T rrn = RM ? r[rbn + ch + t] : T(0), mmn = RM ? m[rbn + ch + t] : T(0);
+        const T zxn = gxn ? z[rbn + oh + txn] : T(0), rxn = gxn ? rho[rbn + oh + txn] : T(0);
+        const T zhn = L.hw ? z[srow(jh, kn, nx, ny) + oh + t] : T(0);
+        const T rhn = L.hw ? rho[srow(jh, kn, nx, ny) + oh + t] : T(0);
+        const T zonn = z[rbnn + oh + t], ronn = rho[rbnn + oh + t];
+        const T ro_rn = DOT ? r[rbn + oh + t] : T(0);
+        // exchange the other colour of plane k
+        const int sl = k & 1;
+        sx[sl][0][w + 1][lane] = zoc;
+        sx[sl][1][w + 1][lane] = roc;
+        if (L.hw) {
+            sx[sl][0][L.hs][lane] = zh;
+            sx[sl][1][L.hs][lane] = rh;
+        }
+        __syncthreads();
+        if (!gx) {
+            const int ln = e ? lp : lm;
+            zx = sx[sl][0][w + 1][ln];
+            rx = sx[sl][1][w + 1][ln];
+        }
+        const T zy0 = sx[sl][0][w][lane], ry0 = sx[sl][1][w][lane];
+        const T zy1 = sx[sl][0][w + 2][lane], ry1 = sx[sl][1][w + 2][lane];
+        // plane k; faces in the order x-, x+, y-, y+, z-, z+
+        const T czm = (k > 0 || g.pz) ? g.cz : T(0);
+        const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
+        const T wp = g.cx * face_kappa(ra, roc);                    // pair partner
+        const T we = (e ? sc.cxr : sc.cxl) * face_kappa(ra, rx);    // outer x neighbour
+        const T w0 = e ? wp : we, v0 = e ? zoc : zx;
+        const T w1 = e ? we : wp, v1 = e ? zx : zoc;
+        T sw = w0, swz = w0 * v0;
+        sw += w1;
+        swz += w1 * v1;
+        const T wy0 = sc.cym * face_kappa(ra, ry0), wy1 = sc.cyp * face_kappa(ra, ry1);
+        sw += wy0;
+        swz += wy0 * zy0;
+        sw += wy1;
+        swz += wy1 * zy1;
+        const T wzm = czm * face_kappa(ra, rom), wzp = czp * face_kappa(ra, ron);
+        sw += wzm + wzp;
+        swz += wzm * zom + wzp * zon;
+        if (L.act) {
             if (RESID && ZG) {
                 tout[rb + ch + t] = swz;
             } else if (RESID) {
@@ -842,36 +925,38 @@ __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                 z[rb + ch + t] = znew;
                 if (DOT) dsum += (double)rr * (double)znew + (double)ro_r * (double)zoc;
             }
-            // advance one plane (the other colour is not written by this sweep)
-            zom = zoc; zoc = zon; zon = zonn;
-            rom = roc; roc = ron; ron = ronn;
-            ra = ran; rr = rrn; mm = mmn;
-            zx = zxn; rx = rxn;
-            zy0 = zy0n; ry0 = ry0n; zy1 = zy1n; ry1 = ry1n;
-            ro_r = ro_rn;
-            e = en;
-            rb = rbn;
         }
+        // advance one plane (the other colour is not written by this sweep)
+        zom = zoc; zoc = zon; zon = zonn;
+        rom = roc; roc = ron; ron = ronn;
+        ra = ran; rr = rrn; mm = mmn;
+        zx = zxn; rx = rxn; gx = gxn;
+        zh = zhn; rh = rhn;
+        ro_r = ro_rn;
+        e = en;
+        rb = rbn;
     }
     if (DOT) block_partial(dsum, partials);
 }
 
 // Zero-guess pre-smoothing in the split layout, one pass: z_red = r dinv on red cells and
 // z_black = dinv_b (r_b + sum_f w_f (r dinv)_nb) on black cells, whose neighbours are all red.
+// The red q = r dinv and rho of the current plane are exchanged through LDS.
 template <typename T>
 __global__ __launch_bounds__(kBlockS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
                                                          const T* __restrict__ rho,
                                                          const T* __restrict__ dinv,
                                                          const T* __restrict__ r,
                                                          T* __restrict__ z) {
+    __shared__ T sx[2][2][kRowsS + 2][64];  // [plane slot][red q, red rho][row][lane]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
-    const int hx = g.nx >> 1;
-    const int t = bx * 64 + (threadIdx.x & 63);
-    const int j = by * kRowsS + (threadIdx.x >> 6);
-    if (t >= hx || j >= g.ny) return;
-    const int nx = g.nx, ny = g.ny;
+    const int nx = g.nx, ny = g.ny, hx = nx >> 1;
+    const SplitLane L(bx, by, hx);
+    const int t = L.t, j = L.j, lane = L.lane, w = L.w;
     const SplitCol<T> sc(g, t, j);
+    const int jh = w == 0 ? sc.jm : sc.jp;
+    const int lm = L.lm(), lp = L.lp();
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
     int k = k0;
@@ -881,28 +966,59 @@ __global__ __launch_bounds__(kBlockS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
     const int rbp = srow(j, kabove(k, g.nz, g.pz), nx, ny);
     T qm = r[rbm + t] * dinv[rbm + t], qc = r[rb + t] * dinv[rb + t], qn = r[rbp + t] * dinv[rbp + t];
     T rom = rho[rbm + t], roc = rho[rb + t], ron = rho[rbp + t];
-    // black cell of this plane and its in-plane red neighbours
+    // black cell of this plane; its outer x neighbour from memory at a tile edge
     int e = ((j + k) & 1) ^ 1;
-    int tx = e ? sc.tp : sc.tm;
+    bool gx = e ? L.gr : L.gl;
     T rb_rho = rho[rb + hx + t], rb_r = r[rb + hx + t], rb_d = dinv[rb + hx + t];
-    T qx = r[rb + tx] * dinv[rb + tx], rx = rho[rb + tx];
-    int rby0 = srow(sc.jm, k, nx, ny), rby1 = srow(sc.jp, k, nx, ny);
-    T qy0 = r[rby0 + t] * dinv[rby0 + t], ry0 = rho[rby0 + t];
-    T qy1 = r[rby1 + t] * dinv[rby1 + t], ry1 = rho[rby1 + t];
+    T qx = T(0), rx = T(0);
+    if (gx) {
+        const int tx = e ? sc.tp : sc.tm;
+        qx = r[rb + tx] * dinv[rb + tx];
+        rx = rho[rb + tx];
+    }
+    T qh = T(0), rh = T(0);
+    if (L.hw) {
+        const int rbh = srow(jh, k, nx, ny);
+        qh = r[rbh + t] * dinv[rbh + t];
+        rh = rho[rbh + t];
+    }
     for (; k < k1; ++k) {
         const int kn = min(k + 1, k1 - 1);
         const int rbn = srow(j, kn, nx, ny);
         const int en = ((j + kn) & 1) ^ 1;
+        const bool gxn = en ? L.gr : L.gl;
         const int txn = en ? sc.tp : sc.tm;
         const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
         // prefetch plane k+1 and the red cell two planes up
         const T rb_rhon = rho[rbn + hx + t], rb_rn = r[rbn + hx + t], rb_dn = dinv[rbn + hx + t];
-        const T qxn = r[rbn + txn] * dinv[rbn + txn], rxn = rho[rbn + txn];
-        rby0 = srow(sc.jm, kn, nx, ny);
-        rby1 = srow(sc.jp, kn, nx, ny);
-        const T qy0n = r[rby0 + t] * dinv[rby0 + t], ry0n = rho[rby0 + t];
-        const T qy1n = r[rby1 + t] * dinv[rby1 + t], ry1n = rho[rby1 + t];
+        T qxn = T(0), rxn = T(0);
+        if (gxn) {
+            qxn = r[rbn + txn] * dinv[rbn + txn];
+            rxn = rho[rbn + txn];
+        }
+        T qhn = T(0), rhn = T(0);
+        if (L.hw) {
+            const int rbh = srow(jh, kn, nx, ny);
+            qhn = r[rbh + t] * dinv[rbh + t];
+            rhn = rho[rbh + t];
+        }
         const T qnn = r[rbnn + t] * dinv[rbnn + t], ronn = rho[rbnn + t];
+        // exchange the red cells of plane k
+        const int sl = k & 1;
+        sx[sl][0][w + 1][lane] = qc;
+        sx[sl][1][w + 1][lane] = roc;
+        if (L.hw) {
+            sx[sl][0][L.hs][lane] = qh;
+            sx[sl][1][L.hs][lane] = rh;
+        }
+        __syncthreads();
+        if (!gx) {
+            const int ln = e ? lp : lm;
+            qx = sx[sl][0][w + 1][ln];
+            rx = sx[sl][1][w + 1][ln];
+        }
+        const T qy0 = sx[sl][0][w][lane], ry0 = sx[sl][1][w][lane];
+        const T qy1 = sx[sl][0][w + 2][lane], ry1 = sx[sl][1][w + 2][lane];
         // plane k; faces of the black cell in the order x-, x+, y-, y+, z-, z+
         const T czm = (k > 0 || g.pz) ? g.cz : T(0);
         const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
@@ -914,14 +1030,16 @@ __global__ __launch_bounds__(kBlockS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
         swq += sc.cyp * face_kappa(rb_rho, ry1) * qy1;
         const T wzm = czm * face_kappa(rb_rho, rom), wzp = czp * face_kappa(rb_rho, ron);
         swq += wzm * qm + wzp * qn;
-        z[rb + t] = qc;
-        z[rb + hx + t] = (rb_r + swq) * rb_d;
+        if (L.act) {
+            z[rb + t] = qc;
+            z[rb + hx + t] = (rb_r + swq) * rb_d;
+        }
         // advance one plane
         qm = qc; qc = qn; qn = qnn;
         rom = roc; roc = ron; ron = ronn;
         rb_rho = rb_rhon; rb_r = rb_rn; rb_d = rb_dn;
-        qx = qxn; rx = rxn;
-        qy0 = qy0n; ry0 = ry0n; qy1 = qy1n; ry1 = ry1n;
+        qx = qxn; rx = rxn; gx = gxn;
+        qh = qhn; rh = rhn;
         e = en;
         rb = rbn;
     }
@@ -1700,7 +1818,7 @@ void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split,
 }
 
 bool split_layout_ok(int nx, int ny, int nz, const Transfer* t) {
-    return use_zm(nx, ny, nz) && (nx % 2 == 0) && t && transfer_zm(*t);
+    return use_zm(nx, ny, nz) && (nx % 2 == 0) && (ny % kRowsS == 0) && t && transfer_zm(*t);
 }
 
 // ------------------------------------------------------------------------------------------

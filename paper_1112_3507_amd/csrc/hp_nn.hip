@@ -136,7 +136,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
                 gx = gx < 0 ? gx + p.nx : (gx >= p.nx ? gx - p.nx : gx);
                 gy = gy < 0 ? gy + p.ny : (gy >= p.ny ? gy - p.ny : gy);
                 const int ch = c0 + cg * 8;
-                if (gz >= 0 && gz < p.nz) {
+                // a brick wider than the grid reaches past the periodic image: those voxels only
+                // feed outputs outside the grid and stay zero
+                if (gz >= 0 && gz < p.nz && gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny) {
                     if (ch < p.ca) {
                         int ax = gx, ay = gy, az = gz;
                         if (p.a_up) { ax >>= 1; ay >>= 1; az >>= 1; }
@@ -302,7 +304,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(BwdWArgs p) {
             gy = gy < 0 ? gy + p.ny : (gy >= p.ny ? gy - p.ny : gy);
             const int ch = c0 + cg * 8;
             uint4 val = {0u, 0u, 0u, 0u};
-            if (gz >= 0 && gz < p.nz && ch < cin) {
+            // past the periodic image (a brick wider than the grid): zero, as its gradient is
+            if (gz >= 0 && gz < p.nz && gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny && ch < cin) {
                 if (ch < p.ca) {
                     int ax = gx, ay = gy, az = gz;
                     if (p.a_up) { ax >>= 1; ay >>= 1; az >>= 1; }
