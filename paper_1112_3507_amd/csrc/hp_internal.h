@@ -48,6 +48,7 @@ struct Geo {
     int px, py, pz;        // 1 if the axis has a periodic wrap face (periodic and n >= 2)
     T cx, cy, cz;          // dt^2 / h_d^2
     int split;             // 1: arrays of this level use the red-black split layout
+    int rev = 0;           // 1: z-march tiles in reverse order (see ztile)
 };
 
 // Red-black split layout (finest level, nx even): each x row of nx cells holds its nx/2 red
@@ -61,6 +62,7 @@ struct Transfer {
     int fx, fy, fz;        // 1 if the axis is coarsened
     int perx, pery, perz;  // 1 if the axis is periodic
     int fsplit;            // 1 if the fine level uses the red-black split layout
+    int rev = 0;           // 1: z-march tiles in reverse order
 };
 
 // ---- launchers (hp_kernels.hip); all asynchronous on `s` ----
@@ -131,10 +133,13 @@ template <typename T>
 void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s);
 // deferred iterate update: r -= alpha q with ||r||^2 under rc; then x += alpha p and
 // p = z + beta p in one pass; x += alpha p alone where the iteration ends (alpha = scal[S_ALPHA])
+// (with g of a split finest level: in the tile order and direction of the split kernels)
 template <typename T>
-void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s);
+void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s,
+                      const Geo<T>* g = nullptr);
 template <typename T>
-void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s);
+void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s,
+                   const Geo<T>* g = nullptr);
 template <typename T>
 void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s);
 // z = dinv * r with <r, z> reduced

@@ -297,13 +297,18 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo<T> g, const T* __restrict_
 struct ZTiles {
     int tx, ty, tz;  // tiles along x, y and z chunks
     int kz;          // planes per z chunk
+    int rev = 0;     // tiles in reverse order
 };
 
-// Tile of this workgroup, XCD-contiguous: hardware dispatches workgroup L to XCD L % 8.
+// Tile of this workgroup, XCD-contiguous: hardware dispatches workgroup L to XCD L % 8. In
+// reverse order the workgroups dispatched first take the tiles that the forward order reaches
+// last, so a pass over the finest grid that follows a forward pass over the same arrays starts
+// on the data still held by the memory-side cache; consecutive finest-level passes alternate.
 __device__ __forceinline__ void ztile(const ZTiles& t, int& bx, int& by, int& bz) {
     unsigned total = (unsigned)t.tx * t.ty * t.tz;
     unsigned L = blockIdx.x;
     if ((total & 7u) == 0) L = (L & 7u) * (total >> 3) + (L >> 3);
+    if (t.rev) L = total - 1u - L;
     bx = (int)(L % (unsigned)t.tx);
     by = (int)((L / (unsigned)t.tx) % (unsigned)t.ty);
     bz = (int)(L / ((unsigned)t.tx * t.ty));
@@ -588,8 +593,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
 #ifndef HP_ZS_ROWS
 #define HP_ZS_ROWS 4
 #endif
-constexpr int kRowsS = HP_ZS_ROWS;     // x rows (waves) per workgroup of the split-layout kernels
-constexpr int kBlockS = 64 * kRowsS;
+#ifndef HP_ZS_XW
+#define HP_ZS_XW 2
+#endif
+constexpr int kRowsS = HP_ZS_ROWS;     // x rows per workgroup of the split-layout kernels
+constexpr int kXW = HP_ZS_XW;          // waves per row: a row tile spans kTW half positions
+constexpr int kTW = 64 * kXW;
+constexpr int kBlockS = kTW * kRowsS;
 // Thread (t, j) owns the cell pair (2t, 2t+1) of row j: half position t of the red and of the
 // black half of the row. Cell 2t has the colour of the row parity p = (j + k) & 1; cell 2t-1
 // (half position t-1) the other colour and cell 2t+2 (half position t+1) the same colour. The
@@ -649,135 +659,210 @@ struct SplitCol {
     }
 };
 
-// Neighbour exchange of the split kernels: each wave owns one row of its workgroup's kRowsS rows,
-// and per plane every wave stores the values of its row that neighbours need into LDS, the first
-// and the last wave also the rows just below and above the workgroup (the y- row of its first row
-// and the y+ row of its last row). After one barrier the y neighbours are read from the rows
-// beside a wave's own and the outer x neighbour from the adjacent lane; only a lane at the edge
-// of its tile (lane 0 for the x- side, the last lane in the tile for the x+ side) reads that
-// neighbour from memory, one plane ahead like everything else. Two plane slots make one barrier
-// per plane enough: a slot is rewritten two planes later, after every wave has passed the barrier
-// of the plane in between. The grid covers whole rows (ny a multiple of kRowsS); lanes beyond the
-// row (t >= nx/2) work on a clamped copy of the last half position and store nothing.
-static_assert(kRowsS >= 2, "the split kernels need separate first and last waves");
+// Neighbour exchange of the split kernels: a workgroup covers kRowsS rows of one row tile (kTW
+// half positions, kXW waves per row), and per plane every thread stores the values of its cells
+// that neighbours need into LDS, together with the rows just below and above the workgroup
+// (loaded by all threads of the workgroup, a few entries each). After one barrier the y
+// neighbours are read from the rows beside a thread's own and the outer x neighbour from the
+// adjacent position. Where a row tile covers the whole row (FULL: nx/2 <= kTW) the periodic x
+// wrap is in LDS too; otherwise the thread at the edge of a tile reads that neighbour from
+// memory. Two plane slots make one barrier per plane enough: a slot is rewritten two planes
+// later, after every wave has passed the barrier of the plane in between. The grid covers whole
+// rows (ny a multiple of kRowsS); positions beyond the row (t >= nx/2) work on a clamped copy of
+// the last one and store nothing.
+//
+// The z march keeps the column of the cell (planes k-1 .. k+2) in a ring of registers and the
+// values of the next plane in the second of two records, and is unrolled by four so that both
+// rotate by renaming: a register move at the loop end would wait for loads still in flight.
+static_assert(kRowsS >= 2, "the split kernels need separate first and last rows");
 
+#ifndef HP_ZS_WG
+#define HP_ZS_WG 0
+#endif
+// Tiles of the split kernels over hx = nx/2 half positions: kTW per tile, kRowsS rows, z chunks
+// of at least HP_ZMIN planes, about 8192 waves in all.
+static ZTiles split_tiles(int hx, int ny, int nz) {
+    ZTiles t;
+    t.tx = (hx + kTW - 1) / kTW;
+    t.ty = (ny + kRowsS - 1) / kRowsS;
+    const int cols = t.tx * t.ty;
+    const int target = HP_ZS_WG > 0 ? HP_ZS_WG : 8192 / (kXW * kRowsS);
+    t.kz = nz;
+    if (HP_ZS_WG > 0) {
+        const int want = std::max(1, std::min(nz, (target + cols / 2) / cols));
+        t.kz = (nz + want - 1) / want;
+    } else {
+        while (t.kz > HP_ZMIN && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < target) t.kz = (t.kz + 1) / 2;
+    }
+    t.tz = (nz + t.kz - 1) / t.kz;
+    return t;
+}
+
+template <bool FULL>
 struct SplitLane {
-    int lane, w, tl, t, j, hs;
-    bool act, gl, gr, hw;
+    int lane;    // position in the row tile, 0 .. kTW-1 (the LDS column)
+    int w;       // row of the workgroup
+    int tl, t, j, j0;
+    int lm, lp;  // LDS columns of the half positions t-1 and t+1 (own column where memory supplies)
+    bool act, gl, gr;
     __device__ __forceinline__ SplitLane(int bx, int by, int hx) {
-        lane = threadIdx.x & 63;
-        w = threadIdx.x >> 6;
-        tl = bx * 64 + lane;
+        lane = threadIdx.x % kTW;
+        // a row is a whole number of waves, so the row index is uniform across the wave: kept in a
+        // scalar register, and with it every row base address
+        w = __builtin_amdgcn_readfirstlane(threadIdx.x / kTW);
+        tl = bx * kTW + lane;
         act = tl < hx;
         t = act ? tl : hx - 1;
-        j = by * kRowsS + w;
-        gl = lane == 0;
-        gr = !(lane < 63 && tl + 1 < hx);
-        hw = w == 0 || w == kRowsS - 1;
-        hs = w == 0 ? 0 : kRowsS + 1;
+        j0 = by * kRowsS;
+        j = j0 + w;
+        if (FULL) {  // the tile is the whole row: wrap in LDS
+            gl = gr = false;
+            lm = t > 0 ? t - 1 : hx - 1;
+            lp = t < hx - 1 ? t + 1 : 0;
+        } else {
+            gl = lane == 0;
+            gr = !(lane < kTW - 1 && tl + 1 < hx);
+            lm = gl ? lane : lane - 1;
+            lp = gr ? lane : lane + 1;
+        }
     }
-    // neighbour lanes in LDS (own lane where memory supplies the value)
-    __device__ __forceinline__ int lm() const { return gl ? lane : lane - 1; }
-    __device__ __forceinline__ int lp() const { return gr ? lane : lane + 1; }
 };
 
+// Rows just below (side 0) and above (side 1) the workgroup's rows j0 .. j0+kRowsS-1; the edge
+// row itself where a Neumann end has no such row.
+__device__ __forceinline__ int halo_row(int side, int j0, int ny, int py) {
+    if (side == 0) return j0 > 0 ? j0 - 1 : (py ? ny - 1 : j0);
+    return j0 + kRowsS < ny ? j0 + kRowsS : (py ? 0 : j0 + kRowsS - 1);
+}
+
+// Entries at half position t of the red and of the black half of a row, as loaded; the cells
+// (2t, 2t+1) of a row of parity par are pos(h, par). Loaded values stay in this form and cells
+// are selected only where they are used, so that no select waits for a load still in flight.
+template <typename T>
+struct HalfPair {
+    T r, b;
+};
+template <typename T>
+__device__ __forceinline__ HalfPair<T> ldh(const T* __restrict__ a, int rb, int hx, int t) {
+    return {a[rb + t], a[rb + hx + t]};
+}
+template <typename T>
+__device__ __forceinline__ Pair<T> pos(const HalfPair<T>& h, int par) {
+    return par ? Pair<T>{h.b, h.r} : Pair<T>{h.r, h.b};
+}
+
 // Operator apply in the split layout: the pair march of k_apply_zp with each pair read from the
-// two halves of its row; pairs of x and rho of the current plane are exchanged through LDS.
-template <typename T, int MODE>
+// two halves of its row; pairs of x and rho of the current plane are exchanged through LDS. The
+// column pairs of x (planes k-1 .. k+2) and rho (k .. k+2) form the register rings.
+template <typename T, int MODE, bool FULL>
 __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
                                                      const T* __restrict__ m,
                                                      const T* __restrict__ x,
                                                      const T* __restrict__ b, T* __restrict__ y,
                                                      double* __restrict__ partials) {
-    __shared__ T sx[2][2][kRowsS + 2][2][64];  // [plane slot][x, rho][row][cell of the pair][lane]
+    __shared__ T sx[2][2][kRowsS + 2][2][kTW];  // [plane slot][x, rho][row][cell of the pair][column]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int nx = g.nx, ny = g.ny, hx = nx >> 1;
-    const SplitLane L(bx, by, hx);
+    const SplitLane<FULL> L(bx, by, hx);
     const int t = L.t, j = L.j, lane = L.lane, w = L.w;
     const SplitCol<T> sc(g, t, j);
-    const int jh = w == 0 ? sc.jm : sc.jp;
-    const int lm = L.lm(), lp = L.lp();
+    const int lm = L.lm, lp = L.lp;
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
     double part = 0.0;
-    int k = k0;
-    int p = (j + k) & 1;
-    int rb = srow(j, k, nx, ny);
-    Pair<T> xc = lds(x, rb, hx, t, p), rc = lds(rho, rb, hx, t, p);
-    const int km = kbelow(k, g.nz, g.pz), kp = kabove(k, g.nz, g.pz);
-    const Pair<T> xm0 = lds(x, srow(j, km, nx, ny), hx, t, p ^ 1);
-    const Pair<T> rm0 = lds(rho, srow(j, km, nx, ny), hx, t, p ^ 1);
-    Pair<T> xm = xm0;
-    const T czm0 = (k > 0 || g.pz) ? g.cz : T(0);
-    T wzm0 = czm0 * face_kappa(rc.v0, rm0.v0);
-    T wzm1 = czm0 * face_kappa(rc.v1, rm0.v1);
-    Pair<T> xn = lds(x, srow(j, kp, nx, ny), hx, t, p ^ 1);
-    Pair<T> rn = lds(rho, srow(j, kp, nx, ny), hx, t, p ^ 1);
-    T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
-    T xl = L.gl ? x[rb + (1 - p) * hx + sc.tm] : T(0), xr = L.gr ? x[rb + p * hx + sc.tp] : T(0);
-    T rl = L.gl ? rho[rb + (1 - p) * hx + sc.tm] : T(0), rr = L.gr ? rho[rb + p * hx + sc.tp] : T(0);
-    Pair<T> xh = {T(0), T(0)}, rh = {T(0), T(0)};
-    if (L.hw) {
-        xh = lds(x, srow(jh, k, nx, ny), hx, t, p ^ 1);
-        rh = lds(rho, srow(jh, k, nx, ny), hx, t, p ^ 1);
-    }
-    Pair<T> mv = lds(m, rb, hx, t, p);
-    Pair<T> bv = {T(0), T(0)};
-    if (MODE >= 2) bv = lds(b, rb, hx, t, p);
-    for (; k < k1; ++k) {
-        // prefetch plane k+1 (clamped to the chunk) and the pair two planes up
-        const int kn = min(k + 1, k1 - 1);
-        const int pn = (j + kn) & 1;
-        const int rbn = srow(j, kn, nx, ny);
-        const int knn = kabove(kn, g.nz, g.pz);
-        const T czpn = (kn < g.nz - 1 || g.pz) ? g.cz : T(0);
-        const T xln = L.gl ? x[rbn + (1 - pn) * hx + sc.tm] : T(0);
-        const T xrn = L.gr ? x[rbn + pn * hx + sc.tp] : T(0);
-        const T rln = L.gl ? rho[rbn + (1 - pn) * hx + sc.tm] : T(0);
-        const T rrn = L.gr ? rho[rbn + pn * hx + sc.tp] : T(0);
-        Pair<T> xhn = {T(0), T(0)}, rhn = {T(0), T(0)};
-        if (L.hw) {
-            xhn = lds(x, srow(jh, kn, nx, ny), hx, t, pn ^ 1);
-            rhn = lds(rho, srow(jh, kn, nx, ny), hx, t, pn ^ 1);
+    // halo items: 2 rows x (x, rho) x (red, black half) x kTW columns, a few per thread
+    constexpr int HI = 8 * kTW, NH = (HI + kBlockS - 1) / kBlockS;
+    // what a plane contributes besides the column: m and b, the outer x neighbours where memory
+    // supplies them, this thread's halo entries
+    struct Own {
+        HalfPair<T> mh, bh;
+        T xl, xr, rl, rr;
+        T h[NH];
+    };
+    auto load_own = [&](int kp, Own& o) {
+        const int pp = (j + kp) & 1;
+        const int rbp = srow(j, kp, nx, ny);
+        o.mh = ldh(m, rbp, hx, t);
+        o.bh = MODE >= 2 ? ldh(b, rbp, hx, t) : HalfPair<T>{T(0), T(0)};
+        if (!FULL) {
+            o.xl = L.gl ? x[rbp + (1 - pp) * hx + sc.tm] : T(0);
+            o.rl = L.gl ? rho[rbp + (1 - pp) * hx + sc.tm] : T(0);
+            o.xr = L.gr ? x[rbp + pp * hx + sc.tp] : T(0);
+            o.rr = L.gr ? rho[rbp + pp * hx + sc.tp] : T(0);
         }
-        const Pair<T> mvn = lds(m, rbn, hx, t, pn);
-        Pair<T> bvn = {T(0), T(0)};
-        if (MODE >= 2) bvn = lds(b, rbn, hx, t, pn);
-        const Pair<T> xnn = lds(x, srow(j, knn, nx, ny), hx, t, pn ^ 1);
-        const Pair<T> rnn = lds(rho, srow(j, knn, nx, ny), hx, t, pn ^ 1);
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+            const int i = threadIdx.x + n * kBlockS;
+            T v = T(0);
+            if (i < HI) {
+                const int col = i % kTW, rest = i / kTW;
+                const int half = rest & 1, arr = (rest >> 1) & 1, side = rest >> 2;
+                const int tp = min(bx * kTW + col, hx - 1);
+                const int jr = halo_row(side, L.j0, ny, g.py);
+                v = (arr ? rho : x)[srow(jr, kp, nx, ny) + half * hx + tp];
+            }
+            o.h[n] = v;
+        }
+    };
+    auto store_halo = [&](int k, int sl, const Own& o) {
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+            const int i = threadIdx.x + n * kBlockS;
+            if (i < HI) {
+                const int col = i % kTW, rest = i / kTW;
+                const int half = rest & 1, arr = (rest >> 1) & 1, side = rest >> 2;
+                const int jr = halo_row(side, L.j0, ny, g.py);
+                sx[sl][arr][side ? kRowsS + 1 : 0][half ^ ((jr + k) & 1)][col] = o.h[n];
+            }
+        }
+    };
+    auto step = [&](int k, const HalfPair<T>& Xm, const HalfPair<T>& Xc, const HalfPair<T>& Xn,
+                    HalfPair<T>& Xnn, const HalfPair<T>& Rc, const HalfPair<T>& Rn, HalfPair<T>& Rnn,
+                    T& wzm0, T& wzm1, const Own& c, Own& nxt) {
+        // prefetch plane k+1 (clamped to the chunk) and the column two planes up
+        const int kn = min(k + 1, k1 - 1);
+        load_own(kn, nxt);
+        const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
+        Xnn = ldh(x, rbnn, hx, t);
+        Rnn = ldh(rho, rbnn, hx, t);
+        const int p = (j + k) & 1;
+        const int rb = srow(j, k, nx, ny);
+        const Pair<T> xc = pos(Xc, p), rc = pos(Rc, p);
         // exchange plane k
         const int sl = k & 1;
         sx[sl][0][w + 1][0][lane] = xc.v0;
         sx[sl][0][w + 1][1][lane] = xc.v1;
         sx[sl][1][w + 1][0][lane] = rc.v0;
         sx[sl][1][w + 1][1][lane] = rc.v1;
-        if (L.hw) {
-            sx[sl][0][L.hs][0][lane] = xh.v0;
-            sx[sl][0][L.hs][1][lane] = xh.v1;
-            sx[sl][1][L.hs][0][lane] = rh.v0;
-            sx[sl][1][L.hs][1][lane] = rh.v1;
-        }
+        store_halo(k, sl, c);
         __syncthreads();
-        if (!L.gl) {
-            xl = sx[sl][0][w + 1][1][lm];
-            rl = sx[sl][1][w + 1][1][lm];
-        }
-        if (!L.gr) {
-            xr = sx[sl][0][w + 1][0][lp];
-            rr = sx[sl][1][w + 1][0][lp];
+        T xl = sx[sl][0][w + 1][1][lm], rl = sx[sl][1][w + 1][1][lm];
+        T xr = sx[sl][0][w + 1][0][lp], rr = sx[sl][1][w + 1][0][lp];
+        if (!FULL) {
+            if (L.gl) {
+                xl = c.xl;
+                rl = c.rl;
+            }
+            if (L.gr) {
+                xr = c.xr;
+                rr = c.rr;
+            }
         }
         const Pair<T> xym = {sx[sl][0][w][0][lane], sx[sl][0][w][1][lane]};
         const Pair<T> xyp = {sx[sl][0][w + 2][0][lane], sx[sl][0][w + 2][1][lane]};
         const Pair<T> rym = {sx[sl][1][w][0][lane], sx[sl][1][w][1][lane]};
         const Pair<T> ryp = {sx[sl][1][w + 2][0][lane], sx[sl][1][w + 2][1][lane]};
+        const Pair<T> xm = pos(Xm, p ^ 1), xn = pos(Xn, p ^ 1), rn = pos(Rn, p ^ 1);
+        const Pair<T> mv = pos(c.mh, p);
         // plane k
+        const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
         const T wx = g.cx * face_kappa(rc.v0, rc.v1);
         const T wzp0 = czp * face_kappa(rc.v0, rn.v0);
         const T wzp1 = czp * face_kappa(rc.v1, rn.v1);
         T acc0 = mv.v0 * xc.v0;
-        acc0 += sc.cxl * face_kappa(rc.v0, rl) * (xc.v0 - xl);
+        acc0 += ((t > 0 || g.px) ? g.cx : T(0)) * face_kappa(rc.v0, rl) * (xc.v0 - xl);
         acc0 += wx * (xc.v0 - xc.v1);
         acc0 += sc.cym * face_kappa(rc.v0, rym.v0) * (xc.v0 - xym.v0);
         acc0 += sc.cyp * face_kappa(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
@@ -785,12 +870,13 @@ __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
         acc0 += wzp0 * (xc.v0 - xn.v0);
         T acc1 = mv.v1 * xc.v1;
         acc1 += wx * (xc.v1 - xc.v0);
-        acc1 += sc.cxr * face_kappa(rc.v1, rr) * (xc.v1 - xr);
+        acc1 += ((t < hx - 1 || g.px) ? g.cx : T(0)) * face_kappa(rc.v1, rr) * (xc.v1 - xr);
         acc1 += sc.cym * face_kappa(rc.v1, rym.v1) * (xc.v1 - xym.v1);
         acc1 += sc.cyp * face_kappa(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
         acc1 += wzm1 * (xc.v1 - xm.v1);
         acc1 += wzp1 * (xc.v1 - xn.v1);
         if (MODE >= 2) {
+            const Pair<T> bv = pos(c.bh, p);
             acc0 = bv.v0 - acc0;
             acc1 = bv.v1 - acc1;
         }
@@ -800,107 +886,142 @@ __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
             if (MODE == 1) part += (double)xc.v0 * (double)acc0 + (double)xc.v1 * (double)acc1;
             if (MODE == 3) part += (double)acc0 * (double)acc0 + (double)acc1 * (double)acc1;
         }
-        // advance: the z+ faces of plane k are the z- faces of plane k+1
+        // the z+ faces of plane k are the z- faces of plane k+1
         wzm0 = wzp0;
         wzm1 = wzp1;
-        xm = xc;
-        xc = xn;
-        rc = rn;
-        xn = xnn;
-        rn = rnn;
-        czp = czpn;
-        xl = xln; xr = xrn; rl = rln; rr = rrn;
-        xh = xhn; rh = rhn;
-        mv = mvn;
-        bv = bvn;
-        p = pn;
-        rb = rbn;
+    };
+    HalfPair<T> X0, X1, X2, X3 = {T(0), T(0)}, R0, R1, R2, R3 = {T(0), T(0)};
+    T wzm0, wzm1;
+    {
+        const int p0 = (j + k0) & 1;
+        const int rbm = srow(j, kbelow(k0, g.nz, g.pz), nx, ny), rb = srow(j, k0, nx, ny);
+        const int rbp = srow(j, kabove(k0, g.nz, g.pz), nx, ny);
+        X0 = ldh(x, rbm, hx, t);
+        X1 = ldh(x, rb, hx, t);
+        X2 = ldh(x, rbp, hx, t);
+        R0 = ldh(rho, rbm, hx, t);
+        R1 = ldh(rho, rb, hx, t);
+        R2 = ldh(rho, rbp, hx, t);
+        const Pair<T> rc = pos(R1, p0), rm = pos(R0, p0 ^ 1);
+        const T czm0 = (k0 > 0 || g.pz) ? g.cz : T(0);
+        wzm0 = czm0 * face_kappa(rc.v0, rm.v0);
+        wzm1 = czm0 * face_kappa(rc.v1, rm.v1);
     }
+    Own A, B;
+    load_own(k0, A);
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+        step(k, X0, X1, X2, X3, R1, R2, R3, wzm0, wzm1, A, B);
+        step(k + 1, X1, X2, X3, X0, R2, R3, R0, wzm0, wzm1, B, A);
+        step(k + 2, X2, X3, X0, X1, R3, R0, R1, wzm0, wzm1, A, B);
+        step(k + 3, X3, X0, X1, X2, R0, R1, R2, wzm0, wzm1, B, A);
+    }
+    if (k < k1) step(k, X0, X1, X2, X3, R1, R2, R3, wzm0, wzm1, A, B);
+    if (k + 1 < k1) step(k + 1, X1, X2, X3, X0, R2, R3, R0, wzm0, wzm1, B, A);
+    if (k + 2 < k1) step(k + 2, X2, X3, X0, X1, R3, R0, R1, wzm0, wzm1, A, B);
     if (MODE == 1 || MODE == 3) block_partial(part, partials);
 }
 
 // Half sweep of colour c in the split layout: one thread per cell of colour c (half position t
 // of row j), marching in z. Every neighbour has the other colour: x neighbours at half positions
 // t (the pair partner) and t-1 or t+1, y neighbours at t in rows j-1 and j+1, z neighbours at t
-// in the planes below and above; the other colour's z and rho at t of three consecutive planes
-// stay in registers, and those of the current plane are exchanged through LDS for the x and y
+// in the planes below and above; the other colour's z and rho at t of planes k-1 .. k+2 form the
+// register ring, and those of the current plane are exchanged through LDS for the x and y
 // neighbours. DOT also reduces <r, z> over both colours; RESID instead writes t = r - A z on the
 // cells of colour c only. ZG (with RESID, colour red): z holds the zero-guess pre-smoothing,
 // whose red values are r dinv, so r - (m + sum w) z vanishes on red cells and t = sum_f w_f z_nb
 // (r and m are not read).
-template <typename T, bool DOT, bool RESID, bool ZG = false>
+template <typename T, bool DOT, bool RESID, bool ZG, bool FULL>
 __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
                                                     const T* __restrict__ m,
                                                     const T* __restrict__ r, T* __restrict__ z,
                                                     int colour, double* __restrict__ partials,
                                                     T* __restrict__ tout) {
-    __shared__ T sx[2][2][kRowsS + 2][64];  // [plane slot][z, rho of the other colour][row][lane]
+    __shared__ T sx[2][2][kRowsS + 2][kTW];  // [plane slot][z, rho of the other colour][row][column]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int nx = g.nx, ny = g.ny, hx = nx >> 1;
-    const SplitLane L(bx, by, hx);
+    const SplitLane<FULL> L(bx, by, hx);
     const int t = L.t, j = L.j, lane = L.lane, w = L.w;
     const int ch = colour * hx, oh = (colour ^ 1) * hx;
     const SplitCol<T> sc(g, t, j);
-    const int jh = w == 0 ? sc.jm : sc.jp;
-    const int lm = L.lm(), lp = L.lp();
+    const int lm = L.lm, lp = L.lp;
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
-    double dsum = 0.0;
-    int k = k0;
-    int rb = srow(j, k, nx, ny);
-    // other colour at t: planes k-1, k, k+1
-    const int rbm = srow(j, kbelow(k, g.nz, g.pz), nx, ny);
-    const int rbp = srow(j, kabove(k, g.nz, g.pz), nx, ny);
-    T zom = z[rbm + oh + t], zoc = z[rb + oh + t], zon = z[rbp + oh + t];
-    T rom = rho[rbm + oh + t], roc = rho[rb + oh + t], ron = rho[rbp + oh + t];
-    // this plane's cell of colour c; its outer x neighbour from memory at a tile edge
-    int e = ((j + k) & 1) ^ colour;  // 0: the cell is 2t (extra x neighbour at t-1), 1: 2t+1
-    bool gx = e ? L.gr : L.gl;
     constexpr bool RM = !(RESID && ZG);  // r and m are read
-    T ra = rho[rb + ch + t], rr = RM ? r[rb + ch + t] : T(0), mm = RM ? m[rb + ch + t] : T(0);
-    T zx = gx ? z[rb + oh + (e ? sc.tp : sc.tm)] : T(0);
-    T rx = gx ? rho[rb + oh + (e ? sc.tp : sc.tm)] : T(0);
-    T zh = L.hw ? z[srow(jh, k, nx, ny) + oh + t] : T(0);
-    T rh = L.hw ? rho[srow(jh, k, nx, ny) + oh + t] : T(0);
-    T ro_r = DOT ? r[rb + oh + t] : T(0);
-    for (; k < k1; ++k) {
+    double dsum = 0.0;
+    // halo items: 2 rows x (z, rho) x kTW columns of the other colour
+    constexpr int HI = 4 * kTW, NH = (HI + kBlockS - 1) / kBlockS;
+    // what a plane contributes besides the other colour's column: this colour's rho, r and m,
+    // the outer x neighbour where memory supplies it, r of the other colour (DOT), halo entries
+    struct Own {
+        T ra, rr, mm, zx, rx, ror;
+        T h[NH];
+    };
+    auto load_own = [&](int kp, Own& o) {
+        const int rbp = srow(j, kp, nx, ny);
+        o.ra = rho[rbp + ch + t];
+        o.rr = RM ? r[rbp + ch + t] : T(0);
+        o.mm = RM ? m[rbp + ch + t] : T(0);
+        if (!FULL) {
+            const int ep = ((j + kp) & 1) ^ colour;
+            const bool gxp = ep ? L.gr : L.gl;
+            const int txp = ep ? sc.tp : sc.tm;
+            o.zx = gxp ? z[rbp + oh + txp] : T(0);
+            o.rx = gxp ? rho[rbp + oh + txp] : T(0);
+        }
+        o.ror = DOT ? r[rbp + oh + t] : T(0);
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+            const int i = threadIdx.x + n * kBlockS;
+            T v = T(0);
+            if (i < HI) {
+                const int col = i % kTW, rest = i / kTW;
+                const int arr = rest & 1, side = rest >> 1;
+                const int tp = min(bx * kTW + col, hx - 1);
+                v = (arr ? rho : z)[srow(halo_row(side, L.j0, ny, g.py), kp, nx, ny) + oh + tp];
+            }
+            o.h[n] = v;
+        }
+    };
+    auto step = [&](int k, const T& zom, const T& zoc, const T& zon, T& zonn, const T& rom, const T& roc,
+                    const T& ron, T& ronn, const Own& c, Own& nxt) {
         const int kn = min(k + 1, k1 - 1);
-        const int rbn = srow(j, kn, nx, ny);
-        const int en = ((j + kn) & 1) ^ colour;
-        const bool gxn = en ? L.gr : L.gl;
-        const int txn = en ? sc.tp : sc.tm;
+        load_own(kn, nxt);
         const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
-        // prefetch plane k+1 and the other colour two planes up
-        const T ran = rho[rbn + ch + t];
-        const T rrn = RM ? r[rbn + ch + t] : T(0), mmn = RM ? m[rbn + ch + t] : T(0);
-        const T zxn = gxn ? z[rbn + oh + txn] : T(0), rxn = gxn ? rho[rbn + oh + txn] : T(0);
-        const T zhn = L.hw ? z[srow(jh, kn, nx, ny) + oh + t] : T(0);
-        const T rhn = L.hw ? rho[srow(jh, kn, nx, ny) + oh + t] : T(0);
-        const T zonn = z[rbnn + oh + t], ronn = rho[rbnn + oh + t];
-        const T ro_rn = DOT ? r[rbn + oh + t] : T(0);
+        zonn = z[rbnn + oh + t];
+        ronn = rho[rbnn + oh + t];
+        const int rb = srow(j, k, nx, ny);
+        const int e = ((j + k) & 1) ^ colour;  // 0: the cell is 2t (extra x neighbour at t-1), 1: 2t+1
         // exchange the other colour of plane k
         const int sl = k & 1;
         sx[sl][0][w + 1][lane] = zoc;
         sx[sl][1][w + 1][lane] = roc;
-        if (L.hw) {
-            sx[sl][0][L.hs][lane] = zh;
-            sx[sl][1][L.hs][lane] = rh;
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+            const int i = threadIdx.x + n * kBlockS;
+            if (i < HI) {
+                const int col = i % kTW, rest = i / kTW;
+                sx[sl][rest & 1][(rest >> 1) ? kRowsS + 1 : 0][col] = c.h[n];
+            }
         }
         __syncthreads();
-        if (!gx) {
-            const int ln = e ? lp : lm;
-            zx = sx[sl][0][w + 1][ln];
-            rx = sx[sl][1][w + 1][ln];
+        const int ln = e ? lp : lm;
+        T zx = sx[sl][0][w + 1][ln], rx = sx[sl][1][w + 1][ln];
+        if (!FULL && (e ? L.gr : L.gl)) {
+            zx = c.zx;
+            rx = c.rx;
         }
         const T zy0 = sx[sl][0][w][lane], ry0 = sx[sl][1][w][lane];
         const T zy1 = sx[sl][0][w + 2][lane], ry1 = sx[sl][1][w + 2][lane];
-        // plane k; faces in the order x-, x+, y-, y+, z-, z+
+        // faces in the order x-, x+, y-, y+, z-, z+
+        const T ra = c.ra;
         const T czm = (k > 0 || g.pz) ? g.cz : T(0);
         const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
         const T wp = g.cx * face_kappa(ra, roc);                    // pair partner
-        const T we = (e ? sc.cxr : sc.cxl) * face_kappa(ra, rx);    // outer x neighbour
+        const T cxo = ((e ? t < hx - 1 : t > 0) || g.px) ? g.cx : T(0);  // outer x face factor
+        const T we = cxo * face_kappa(ra, rx);                      // outer x neighbour
         const T w0 = e ? wp : we, v0 = e ? zoc : zx;
         const T w1 = e ? we : wp, v1 = e ? zx : zoc;
         T sw = w0, swz = w0 * v0;
@@ -919,130 +1040,199 @@ __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                 tout[rb + ch + t] = swz;
             } else if (RESID) {
                 const T zs = z[rb + ch + t];
-                tout[rb + ch + t] = rr + swz - (mm + sw) * zs;
+                tout[rb + ch + t] = c.rr + swz - (c.mm + sw) * zs;
             } else {
-                const T znew = (rr + swz) / (mm + sw);
+                const T znew = (c.rr + swz) / (c.mm + sw);
                 z[rb + ch + t] = znew;
-                if (DOT) dsum += (double)rr * (double)znew + (double)ro_r * (double)zoc;
+                if (DOT) dsum += (double)c.rr * (double)znew + (double)c.ror * (double)zoc;
             }
         }
-        // advance one plane (the other colour is not written by this sweep)
-        zom = zoc; zoc = zon; zon = zonn;
-        rom = roc; roc = ron; ron = ronn;
-        ra = ran; rr = rrn; mm = mmn;
-        zx = zxn; rx = rxn; gx = gxn;
-        zh = zhn; rh = rhn;
-        ro_r = ro_rn;
-        e = en;
-        rb = rbn;
+    };
+    // other colour at t: planes k0-1, k0, k0+1
+    T z0, z1, z2, z3 = T(0), q0, q1, q2, q3 = T(0);
+    {
+        const int rbm = srow(j, kbelow(k0, g.nz, g.pz), nx, ny), rb = srow(j, k0, nx, ny);
+        const int rbp = srow(j, kabove(k0, g.nz, g.pz), nx, ny);
+        z0 = z[rbm + oh + t]; z1 = z[rb + oh + t]; z2 = z[rbp + oh + t];
+        q0 = rho[rbm + oh + t]; q1 = rho[rb + oh + t]; q2 = rho[rbp + oh + t];
     }
+    Own A, B;
+    load_own(k0, A);
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+        step(k, z0, z1, z2, z3, q0, q1, q2, q3, A, B);
+        step(k + 1, z1, z2, z3, z0, q1, q2, q3, q0, B, A);
+        step(k + 2, z2, z3, z0, z1, q2, q3, q0, q1, A, B);
+        step(k + 3, z3, z0, z1, z2, q3, q0, q1, q2, B, A);
+    }
+    if (k < k1) step(k, z0, z1, z2, z3, q0, q1, q2, q3, A, B);
+    if (k + 1 < k1) step(k + 1, z1, z2, z3, z0, q1, q2, q3, q0, B, A);
+    if (k + 2 < k1) step(k + 2, z2, z3, z0, z1, q2, q3, q0, q1, A, B);
     if (DOT) block_partial(dsum, partials);
 }
 
 // Zero-guess pre-smoothing in the split layout, one pass: z_red = r dinv on red cells and
 // z_black = dinv_b (r_b + sum_f w_f (r dinv)_nb) on black cells, whose neighbours are all red.
-// The red q = r dinv and rho of the current plane are exchanged through LDS.
-template <typename T>
+// The red q = r dinv and rho of the current plane are exchanged through LDS; the red column
+// (r, dinv and rho at t, planes k-1 .. k+2) forms the register ring.
+template <typename T, bool FULL>
 __global__ __launch_bounds__(kBlockS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
                                                          const T* __restrict__ rho,
                                                          const T* __restrict__ dinv,
                                                          const T* __restrict__ r,
                                                          T* __restrict__ z) {
-    __shared__ T sx[2][2][kRowsS + 2][64];  // [plane slot][red q, red rho][row][lane]
+    __shared__ T sx[2][2][kRowsS + 2][kTW];  // [plane slot][red q, red rho][row][column]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int nx = g.nx, ny = g.ny, hx = nx >> 1;
-    const SplitLane L(bx, by, hx);
+    const SplitLane<FULL> L(bx, by, hx);
     const int t = L.t, j = L.j, lane = L.lane, w = L.w;
     const SplitCol<T> sc(g, t, j);
-    const int jh = w == 0 ? sc.jm : sc.jp;
-    const int lm = L.lm(), lp = L.lp();
+    const int lm = L.lm, lp = L.lp;
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
-    int k = k0;
-    int rb = srow(j, k, nx, ny);
-    // red cells at t: q = r dinv and rho for planes k-1, k, k+1
-    const int rbm = srow(j, kbelow(k, g.nz, g.pz), nx, ny);
-    const int rbp = srow(j, kabove(k, g.nz, g.pz), nx, ny);
-    T qm = r[rbm + t] * dinv[rbm + t], qc = r[rb + t] * dinv[rb + t], qn = r[rbp + t] * dinv[rbp + t];
-    T rom = rho[rbm + t], roc = rho[rb + t], ron = rho[rbp + t];
-    // black cell of this plane; its outer x neighbour from memory at a tile edge
-    int e = ((j + k) & 1) ^ 1;
-    bool gx = e ? L.gr : L.gl;
-    T rb_rho = rho[rb + hx + t], rb_r = r[rb + hx + t], rb_d = dinv[rb + hx + t];
-    T qx = T(0), rx = T(0);
-    if (gx) {
-        const int tx = e ? sc.tp : sc.tm;
-        qx = r[rb + tx] * dinv[rb + tx];
-        rx = rho[rb + tx];
-    }
-    T qh = T(0), rh = T(0);
-    if (L.hw) {
-        const int rbh = srow(jh, k, nx, ny);
-        qh = r[rbh + t] * dinv[rbh + t];
-        rh = rho[rbh + t];
-    }
-    for (; k < k1; ++k) {
+    // red entries at t of one plane: r, dinv and rho
+    struct Red {
+        T r, d, rho;
+    };
+    auto ldred = [&](int rbp, Red& o) {
+        o.r = r[rbp + t];
+        o.d = dinv[rbp + t];
+        o.rho = rho[rbp + t];
+    };
+    // halo items: 2 rows x (q from r and dinv, rho) x kTW columns of the red half
+    constexpr int HI = 4 * kTW, NH = (HI + kBlockS - 1) / kBlockS;
+    // the black cell of a plane, its outer x neighbour where memory supplies it, halo entries
+    struct Own {
+        T rho, r, d, xr, xd, xrho;
+        T h0[NH], h1[NH];
+    };
+    auto load_own = [&](int kp, Own& o) {
+        const int rbp = srow(j, kp, nx, ny);
+        o.rho = rho[rbp + hx + t];
+        o.r = r[rbp + hx + t];
+        o.d = dinv[rbp + hx + t];
+        if (!FULL) {
+            const int ep = ((j + kp) & 1) ^ 1;
+            const bool gxp = ep ? L.gr : L.gl;
+            const int txp = ep ? sc.tp : sc.tm;
+            o.xr = gxp ? r[rbp + txp] : T(0);
+            o.xd = gxp ? dinv[rbp + txp] : T(0);
+            o.xrho = gxp ? rho[rbp + txp] : T(0);
+        }
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+            const int i = threadIdx.x + n * kBlockS;
+            T v0 = T(0), v1 = T(1);
+            if (i < HI) {
+                const int col = i % kTW, rest = i / kTW;
+                const int arr = rest & 1, side = rest >> 1;
+                const int tp = min(bx * kTW + col, hx - 1);
+                const int a = srow(halo_row(side, L.j0, ny, g.py), kp, nx, ny) + tp;
+                if (arr) {
+                    v0 = rho[a];
+                } else {
+                    v0 = r[a];
+                    v1 = dinv[a];
+                }
+            }
+            o.h0[n] = v0;
+            o.h1[n] = v1;
+        }
+    };
+    auto step = [&](int k, const Red& cm, const Red& cc, const Red& cn, Red& cnn, const Own& c, Own& nxt) {
         const int kn = min(k + 1, k1 - 1);
-        const int rbn = srow(j, kn, nx, ny);
-        const int en = ((j + kn) & 1) ^ 1;
-        const bool gxn = en ? L.gr : L.gl;
-        const int txn = en ? sc.tp : sc.tm;
-        const int rbnn = srow(j, kabove(kn, g.nz, g.pz), nx, ny);
-        // prefetch plane k+1 and the red cell two planes up
-        const T rb_rhon = rho[rbn + hx + t], rb_rn = r[rbn + hx + t], rb_dn = dinv[rbn + hx + t];
-        T qxn = T(0), rxn = T(0);
-        if (gxn) {
-            qxn = r[rbn + txn] * dinv[rbn + txn];
-            rxn = rho[rbn + txn];
-        }
-        T qhn = T(0), rhn = T(0);
-        if (L.hw) {
-            const int rbh = srow(jh, kn, nx, ny);
-            qhn = r[rbh + t] * dinv[rbh + t];
-            rhn = rho[rbh + t];
-        }
-        const T qnn = r[rbnn + t] * dinv[rbnn + t], ronn = rho[rbnn + t];
+        load_own(kn, nxt);
+        ldred(srow(j, kabove(kn, g.nz, g.pz), nx, ny), cnn);
+        const int rb = srow(j, k, nx, ny);
+        const int e = ((j + k) & 1) ^ 1;
+        const T qm = cm.r * cm.d, qc = cc.r * cc.d, qn = cn.r * cn.d;
         // exchange the red cells of plane k
         const int sl = k & 1;
         sx[sl][0][w + 1][lane] = qc;
-        sx[sl][1][w + 1][lane] = roc;
-        if (L.hw) {
-            sx[sl][0][L.hs][lane] = qh;
-            sx[sl][1][L.hs][lane] = rh;
+        sx[sl][1][w + 1][lane] = cc.rho;
+#pragma unroll
+        for (int n = 0; n < NH; ++n) {
+            const int i = threadIdx.x + n * kBlockS;
+            if (i < HI) {
+                const int col = i % kTW, rest = i / kTW;
+                sx[sl][rest & 1][(rest >> 1) ? kRowsS + 1 : 0][col] = c.h0[n] * c.h1[n];
+            }
         }
         __syncthreads();
-        if (!gx) {
-            const int ln = e ? lp : lm;
-            qx = sx[sl][0][w + 1][ln];
-            rx = sx[sl][1][w + 1][ln];
+        const int ln = e ? lp : lm;
+        T qx = sx[sl][0][w + 1][ln], rx = sx[sl][1][w + 1][ln];
+        if (!FULL && (e ? L.gr : L.gl)) {
+            qx = c.xr * c.xd;
+            rx = c.xrho;
         }
         const T qy0 = sx[sl][0][w][lane], ry0 = sx[sl][1][w][lane];
         const T qy1 = sx[sl][0][w + 2][lane], ry1 = sx[sl][1][w + 2][lane];
-        // plane k; faces of the black cell in the order x-, x+, y-, y+, z-, z+
+        // faces of the black cell in the order x-, x+, y-, y+, z-, z+
+        const T rbr = c.rho;
         const T czm = (k > 0 || g.pz) ? g.cz : T(0);
         const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
-        const T wp = g.cx * face_kappa(rb_rho, roc);
-        const T we = (e ? sc.cxr : sc.cxl) * face_kappa(rb_rho, rx);
+        const T wp = g.cx * face_kappa(rbr, cc.rho);
+        const T cxo = ((e ? t < hx - 1 : t > 0) || g.px) ? g.cx : T(0);
+        const T we = cxo * face_kappa(rbr, rx);
         T swq = (e ? wp : we) * (e ? qc : qx);
         swq += (e ? we : wp) * (e ? qx : qc);
-        swq += sc.cym * face_kappa(rb_rho, ry0) * qy0;
-        swq += sc.cyp * face_kappa(rb_rho, ry1) * qy1;
-        const T wzm = czm * face_kappa(rb_rho, rom), wzp = czp * face_kappa(rb_rho, ron);
+        swq += sc.cym * face_kappa(rbr, ry0) * qy0;
+        swq += sc.cyp * face_kappa(rbr, ry1) * qy1;
+        const T wzm = czm * face_kappa(rbr, cm.rho), wzp = czp * face_kappa(rbr, cn.rho);
         swq += wzm * qm + wzp * qn;
         if (L.act) {
             z[rb + t] = qc;
-            z[rb + hx + t] = (rb_r + swq) * rb_d;
+            z[rb + hx + t] = (c.r + swq) * c.d;
         }
-        // advance one plane
-        qm = qc; qc = qn; qn = qnn;
-        rom = roc; roc = ron; ron = ronn;
-        rb_rho = rb_rhon; rb_r = rb_rn; rb_d = rb_dn;
-        qx = qxn; rx = rxn; gx = gxn;
-        qh = qhn; rh = rhn;
-        e = en;
-        rb = rbn;
+    };
+    Red C0, C1, C2, C3 = {T(0), T(0), T(0)};
+    ldred(srow(j, kbelow(k0, g.nz, g.pz), nx, ny), C0);
+    ldred(srow(j, k0, nx, ny), C1);
+    ldred(srow(j, kabove(k0, g.nz, g.pz), nx, ny), C2);
+    Own A, B;
+    load_own(k0, A);
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+        step(k, C0, C1, C2, C3, A, B);
+        step(k + 1, C1, C2, C3, C0, B, A);
+        step(k + 2, C2, C3, C0, C1, A, B);
+        step(k + 3, C3, C0, C1, C2, B, A);
     }
+    if (k < k1) step(k, C0, C1, C2, C3, A, B);
+    if (k + 1 < k1) step(k + 1, C1, C2, C3, C0, B, A);
+    if (k + 2 < k1) step(k + 2, C2, C3, C0, C1, A, B);
+}
+
+// Launch one split kernel over its tiles, with FULL where a row tile spans the whole row.
+template <typename T, int MODE>
+static void launch_apply_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, const T* m, const T* x,
+                            const T* b, T* y, double* partials, hipStream_t s) {
+    const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlockS);
+    if ((g.nx >> 1) <= kTW)
+        hipLaunchKernelGGL((k_apply_zs<T, MODE, true>), grid, block, 0, s, g, zt, rho, m, x, b, y, partials);
+    else
+        hipLaunchKernelGGL((k_apply_zs<T, MODE, false>), grid, block, 0, s, g, zt, rho, m, x, b, y, partials);
+}
+template <typename T, bool DOT, bool RESID, bool ZG>
+static void launch_rbgs_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, const T* m, const T* r, T* z,
+                           int colour, double* partials, T* tout, hipStream_t s) {
+    const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlockS);
+    if ((g.nx >> 1) <= kTW)
+        hipLaunchKernelGGL((k_rbgs_zs<T, DOT, RESID, ZG, true>), grid, block, 0, s, g, zt, rho, m, r, z,
+                           colour, partials, tout);
+    else
+        hipLaunchKernelGGL((k_rbgs_zs<T, DOT, RESID, ZG, false>), grid, block, 0, s, g, zt, rho, m, r, z,
+                           colour, partials, tout);
+}
+template <typename T>
+static void launch_presmooth_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, const T* dinv, const T* r,
+                                T* z, hipStream_t s) {
+    const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlockS);
+    if ((g.nx >> 1) <= kTW)
+        hipLaunchKernelGGL((k_presmooth_zs<T, true>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+    else
+        hipLaunchKernelGGL((k_presmooth_zs<T, false>), grid, block, 0, s, g, zt, rho, dinv, r, z);
 }
 
 static bool use_zm(int nx, int ny, int nz) { return nx >= 64 && ny >= 4 && nz >= 8; }
@@ -1052,7 +1242,7 @@ static int64_t zm_blocks(int nx, int ny, int nz) {
     int64_t nb = 0;
     for (int v = 0; v < 3; ++v) {
         ZTiles t = v == 0 ? ztiles(nx, ny, nz, 64) : v == 1 ? ztiles(nx, ny, nz, 128)
-                                                             : ztiles(std::max(nx >> 1, 1), ny, nz, 64, HP_ZMIN, kRowsS);
+                                                             : split_tiles(std::max(nx >> 1, 1), ny, nz);
         nb = std::max<int64_t>(nb, (int64_t)t.tx * t.ty * t.tz);
     }
     return nb;
@@ -1072,17 +1262,18 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
                   int mode, const RedCtl& rc, hipStream_t s) {
     int nb;
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
+        ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
+        zt.rev = g.rev;
         nb = zt.tx * zt.ty * zt.tz;
-        dim3 grid(nb), block(kBlockS);
         switch (mode) {
-            case 0: hipLaunchKernelGGL((k_apply_zs<T, 0>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            case 1: hipLaunchKernelGGL((k_apply_zs<T, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            case 2: hipLaunchKernelGGL((k_apply_zs<T, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            default: hipLaunchKernelGGL((k_apply_zs<T, 3>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 0: launch_apply_zs<T, 0>(g, zt, rho, m, x, b, y, rc.partials, s); break;
+            case 1: launch_apply_zs<T, 1>(g, zt, rho, m, x, b, y, rc.partials, s); break;
+            case 2: launch_apply_zs<T, 2>(g, zt, rho, m, x, b, y, rc.partials, s); break;
+            default: launch_apply_zs<T, 3>(g, zt, rho, m, x, b, y, rc.partials, s); break;
         }
     } else if (use_zp(g, {rho, m, x, b, y})) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+        zt.rev = g.rev;
         nb = zt.tx * zt.ty * zt.tz;
         dim3 grid(nb), block(kBlock);
         switch (mode) {
@@ -1093,6 +1284,7 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
         }
     } else if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 64);
+        zt.rev = g.rev;
         nb = zt.tx * zt.ty * zt.tz;
         dim3 grid(nb), block(kBlock);
         switch (mode) {
@@ -1383,17 +1575,17 @@ template <typename T>
 bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, const T* z, T* t,
                       hipStream_t s, bool zero_guess) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
+        ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
+        zt.rev = g.rev;
         if (zero_guess)
-            hipLaunchKernelGGL((k_rbgs_zs<T, false, true, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS),
-                               0, s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
+            launch_rbgs_zs<T, false, true, true>(g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t, s);
         else
-            hipLaunchKernelGGL((k_rbgs_zs<T, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0,
-                               s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
+            launch_rbgs_zs<T, false, true, false>(g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t, s);
         return true;
     }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+    zt.rev = g.rev;
     hipLaunchKernelGGL((k_rbgs_zm<T, false, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
                        s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
     return true;
@@ -1402,13 +1594,14 @@ bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, con
 template <typename T>
 bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
-        hipLaunchKernelGGL((k_presmooth_zs<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s, g, zt,
-                           rho, dinv, r, z);
+        ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
+        zt.rev = g.rev;
+        launch_presmooth_zs<T>(g, zt, rho, dinv, r, z, s);
         return true;
     }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+    zt.rev = g.rev;
     hipLaunchKernelGGL((k_presmooth_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt, rho,
                        dinv, r, z);
     return true;
@@ -1418,13 +1611,14 @@ template <typename T>
 void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                  hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
-        hipLaunchKernelGGL((k_rbgs_zs<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s,
-                           g, zt, rho, m, r, z, colour, nullptr, nullptr);
+        ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
+        zt.rev = g.rev;
+        launch_rbgs_zs<T, false, false, false>(g, zt, rho, m, r, z, colour, nullptr, nullptr, s);
         return;
     }
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+        zt.rev = g.rev;
         hipLaunchKernelGGL((k_rbgs_zm<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
                            s, g, zt, rho, m, r, z, colour, nullptr);
         return;
@@ -1437,15 +1631,16 @@ template <typename T>
 bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                      const RedCtl& rc, hipStream_t s) {
     if (g.split) {
-        ZTiles zt = ztiles(g.nx >> 1, g.ny, g.nz, 64, HP_ZMIN, kRowsS);
+        ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
+        zt.rev = g.rev;
         const int nb = zt.tx * zt.ty * zt.tz;
-        hipLaunchKernelGGL((k_rbgs_zs<T, true, false>), dim3(nb), dim3(kBlockS), 0, s, g, zt, rho, m, r, z,
-                           colour, rc.partials, nullptr);
+        launch_rbgs_zs<T, true, false, false>(g, zt, rho, m, r, z, colour, rc.partials, nullptr, s);
         finalize(rc, nb, s);
         return true;
     }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+    zt.rev = g.rev;
     const int nb = zt.tx * zt.ty * zt.tz;
     hipLaunchKernelGGL((k_rbgs_zm<T, false, true>), dim3(nb), dim3(kBlock), 0, s, g, zt, rho, m, r, z,
                        colour, rc.partials);
@@ -1463,6 +1658,7 @@ void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* 
     }
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
+        zt.rev = g.rev;
         hipLaunchKernelGGL((k_rbgs_zm<T, true, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
                            s, g, zt, rho, m, r, z, 0, nullptr);
         return;
@@ -1653,6 +1849,7 @@ template <typename T>
 void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
         ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64, 2);
+        zt.rev = t.rev;
         const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlock);
         if (!t.fsplit)
             hipLaunchKernelGGL((k_restrict_zm<T, false, false>), grid, block, 0, s, t, zt, fine, coarse);
@@ -1792,6 +1989,7 @@ template <typename T>
 void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
         ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64, 2);
+        zt.rev = t.rev;
         zt.kz += zt.kz & 1;  // chunks start on even fine planes
         zt.tz = (t.nfz + zt.kz - 1) / zt.kz;
         if (t.fsplit && red_only)
@@ -1919,8 +2117,92 @@ __global__ __launch_bounds__(kBlock) void k_axpy_norm(T* __restrict__ r, const T
     block_partial(acc, rc.partials);
 }
 
+// The same two updates over a split finest level in the tile order of the split kernels (and in
+// their direction), so that they start on what the previous pass left in the memory-side cache.
+// Four planes of loads are in flight per thread.
 template <typename T>
-void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s) {
+__global__ __launch_bounds__(kBlockS) void k_axpy_norm_zs(ZTiles zt, int nx, int ny, int nz,
+                                                          T* __restrict__ r, const T* __restrict__ q,
+                                                          RedCtl rc) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int hx = nx >> 1;
+    const int t = bx * kTW + (int)(threadIdx.x % kTW), j = by * kRowsS + (int)(threadIdx.x / kTW);
+    const int k0 = bz * zt.kz, k1 = min(k0 + zt.kz, nz);
+    const T alpha = (T)rc.scal[S_ALPHA];
+    double acc = 0.0;
+    if (t < hx) {
+        for (int k = k0; k < k1; k += 4) {
+            T rv[8], qv[8];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int a = srow(j, min(k + u, k1 - 1), nx, ny) + t;
+                rv[2 * u] = r[a];
+                rv[2 * u + 1] = r[a + hx];
+                qv[2 * u] = q[a];
+                qv[2 * u + 1] = q[a + hx];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (k + u < k1) {
+                    const int a = srow(j, k + u, nx, ny) + t;
+                    const T r0 = rv[2 * u] - alpha * qv[2 * u], r1 = rv[2 * u + 1] - alpha * qv[2 * u + 1];
+                    r[a] = r0;
+                    r[a + hx] = r1;
+                    acc += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+                }
+            }
+        }
+    }
+    block_partial(acc, rc.partials);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlockS) void k_xpby_x_zs(ZTiles zt, int nx, int ny, int nz,
+                                                       const T* __restrict__ z, T* __restrict__ p,
+                                                       T* __restrict__ x, const double* __restrict__ scal) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int hx = nx >> 1;
+    const int t = bx * kTW + (int)(threadIdx.x % kTW), j = by * kRowsS + (int)(threadIdx.x / kTW);
+    const int k0 = bz * zt.kz, k1 = min(k0 + zt.kz, nz);
+    if (t >= hx) return;
+    const T alpha = (T)scal[S_ALPHA], beta = (T)scal[S_BETA];
+    for (int k = k0; k < k1; k += 4) {
+        T zv[8], pv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int a = srow(j, min(k + u, k1 - 1), nx, ny) + t;
+            zv[2 * u] = z[a];
+            zv[2 * u + 1] = z[a + hx];
+            pv[2 * u] = p[a];
+            pv[2 * u + 1] = p[a + hx];
+            xv[2 * u] = x[a];
+            xv[2 * u + 1] = x[a + hx];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (k + u < k1) {
+                const int a = srow(j, k + u, nx, ny) + t;
+                x[a] = xv[2 * u] + alpha * pv[2 * u];
+                x[a + hx] = xv[2 * u + 1] + alpha * pv[2 * u + 1];
+                p[a] = zv[2 * u] + beta * pv[2 * u];
+                p[a + hx] = zv[2 * u + 1] + beta * pv[2 * u + 1];
+            }
+        }
+    }
+}
+
+template <typename T>
+void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s, const Geo<T>* g) {
+    if (g && g->split) {
+        ZTiles zt = split_tiles(g->nx >> 1, g->ny, g->nz);
+        zt.rev = g->rev;
+        const int nb = zt.tx * zt.ty * zt.tz;
+        hipLaunchKernelGGL((k_axpy_norm_zs<T>), dim3(nb), dim3(kBlockS), 0, s, zt, g->nx, g->ny, g->nz, r, q, rc);
+        finalize(rc, nb, s);
+        return;
+    }
     hipLaunchKernelGGL((k_axpy_norm<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, r, q, n, rc);
     finalize(rc, vec_blocks(n), s);
 }
@@ -1939,7 +2221,14 @@ __global__ __launch_bounds__(kBlock) void k_xpby_x(const T* __restrict__ z, T* _
 }
 
 template <typename T>
-void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s) {
+void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s, const Geo<T>* g) {
+    if (g && g->split) {
+        ZTiles zt = split_tiles(g->nx >> 1, g->ny, g->nz);
+        zt.rev = g->rev;
+        hipLaunchKernelGGL((k_xpby_x_zs<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s, zt, g->nx, g->ny,
+                           g->nz, z, p, x, scal);
+        return;
+    }
     hipLaunchKernelGGL((k_xpby_x<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        s, z, p, x, n, scal);
 }
@@ -2082,8 +2371,10 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
     template void launch_dot<T>(const T*, const T*, int64_t, const RedCtl&, hipStream_t);       \
     template void launch_axpy2_norm<T>(T*, const T*, T*, const T*, int64_t, const RedCtl&,      \
                                        hipStream_t);                                            \
-    template void launch_axpy_norm<T>(T*, const T*, int64_t, const RedCtl&, hipStream_t);       \
-    template void launch_xpby_x<T>(const T*, T*, T*, int64_t, const double*, hipStream_t);      \
+    template void launch_axpy_norm<T>(T*, const T*, int64_t, const RedCtl&, hipStream_t,        \
+                                      const Geo<T>*);                                             \
+    template void launch_xpby_x<T>(const T*, T*, T*, int64_t, const double*, hipStream_t,       \
+                                   const Geo<T>*);                                                \
     template void launch_axpy_alpha<T>(T*, const T*, int64_t, const double*, hipStream_t);      \
     template void launch_xpby<T>(const T*, T*, int64_t, const double*, hipStream_t);            \
     template void launch_fill<T>(T*, T, int64_t, hipStream_t);                                  \

@@ -90,6 +90,7 @@ struct hp_handle {
     int* host_flag = nullptr;     // pinned
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_scal = nullptr;  // marks the copy of scal into host_scal
+    unsigned dir = 0;              // traversal direction of the last finest-level pass
     std::vector<void*> allocs;
     // options
     int mode = HP_MODE_FP64_MGPCG;
@@ -137,6 +138,17 @@ Geo<T> geo(const hp_handle* H, const LevelData& L) {
     g.cz = (T)(dt2 / (L.h[2] * L.h[2]));
     g.split = L.split;
     return g;
+}
+
+// Direction of the next z-march pass over level l: passes over the finest level alternate (the
+// memory-side cache keeps what the previous pass touched last), coarser levels stay forward.
+int flip(hp_handle* H, int l) { return l == 0 ? (int)(H->dir ^= 1u) : 0; }
+
+template <typename T>
+Geo<T> geo_pass(hp_handle* H, const Geo<T>& g, int l) {
+    Geo<T> c = g;
+    c.rev = flip(H, l);
+    return c;
 }
 
 Transfer transfer(const hp_handle* H, int l) {
@@ -403,33 +415,39 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
     Geo<T> g = geo<T>(H, L);
     const T* rho = lvl_rho<T>(L);
     const T* m = lvl_m<T>(L);
-    const bool fused_pre = launch_presmooth<T>(g, rho, lvl_dinv<T>(L), r, z, s);
+    const bool fused_pre = launch_presmooth<T>(geo_pass(H, g, l), rho, lvl_dinv<T>(L), r, z, s);
     if (!fused_pre) {
-        launch_rbgs_zero<T>(g, rho, m, r, z, s);
-        launch_rbgs<T>(g, rho, m, r, z, 1, s);
+        launch_rbgs_zero<T>(geo_pass(H, g, l), rho, m, r, z, s);
+        launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 1, s);
     }
     for (int it = 1; it < H->nu_pre; ++it) {
-        launch_rbgs<T>(g, rho, m, r, z, 0, s);
-        launch_rbgs<T>(g, rho, m, r, z, 1, s);
+        launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 0, s);
+        launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 1, s);
     }
     T* t = lvl_t<T>(L);
     // after the black half sweep the residual vanishes on black cells
-    const bool red_res = launch_resid_red<T>(g, rho, m, r, z, t, s, fused_pre && H->nu_pre == 1);
-    if (!red_res) launch_apply<T>(g, rho, m, z, r, t, 2, red(H, OP_NONE), s);
+    const bool red_res = launch_resid_red<T>(geo_pass(H, g, l), rho, m, r, z, t, s,
+                                             fused_pre && H->nu_pre == 1);
+    if (!red_res) launch_apply<T>(geo_pass(H, g, l), rho, m, z, r, t, 2, red(H, OP_NONE), s);
     LevelData& C = H->lv[l + 1];
     Transfer tr = transfer(H, l);
+    tr.rev = flip(H, l);
     launch_restrict<T>(tr, t, lvl_r<T>(C), s, red_res);
     vcycle<T>(H, l + 1, lvl_r<T>(C), lvl_z<T>(C));
     // the post-smoothing starts with a black half sweep, which overwrites the black cells
+    tr.rev = flip(H, l);
     launch_prolong_add<T>(tr, lvl_z<T>(C), z, s, true);
     for (int it = 0; it < H->nu_post; ++it) {
         const bool timed = (l == 0 && sizeof(T) == 8);
         if (timed) time_begin(H, TIME_SWEEP);
-        launch_rbgs<T>(g, rho, m, r, z, 1, s);
+        launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 1, s);
         if (timed) time_end(H);
-        if (dot && it == H->nu_post - 1) return launch_rbgs_dot<T>(g, rho, m, r, z, 0, *dot, s) ||
-                                                (launch_rbgs<T>(g, rho, m, r, z, 0, s), false);
-        launch_rbgs<T>(g, rho, m, r, z, 0, s);
+        if (dot && it == H->nu_post - 1) {
+            const Geo<T> gd = geo_pass(H, g, l);
+            return launch_rbgs_dot<T>(gd, rho, m, r, z, 0, *dot, s) ||
+                   (launch_rbgs<T>(gd, rho, m, r, z, 0, s), false);
+        }
+        launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 0, s);
     }
     return false;
 }
@@ -496,7 +514,8 @@ void next_direction64(hp_handle* H, double* x) {
     precond64(H, H->r, H->z, OP_BETA);
     launch_xpby_x<double>(H->z, H->p, x, F.N, H->scal, s);
     time_begin(H, TIME_APPLY);
-    launch_apply<double>(geo<double>(H, F), F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
+    launch_apply<double>(geo_pass(H, geo<double>(H, F), 0), F.rho, F.m, H->p, nullptr, H->q, 1,
+                         red(H, OP_ALPHA), s);
     time_end(H);
 }
 
@@ -515,11 +534,12 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         if (restart) {
             precond64(H, H->r, H->z, OP_RZINIT);
             launch_copy<double>(H->z, H->p, N, s);
-            launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
+            launch_apply<double>(geo_pass(H, g, 0), F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
             restart = false;
         }
         // r -= alpha q now; x += alpha p is deferred to the next direction update (or the exit)
-        launch_axpy_norm<double>(H->r, H->q, N, red(H, OP_STORE, S_RR), s);
+        const Geo<double> gn = geo_pass(H, g, 0);
+        launch_axpy_norm<double>(H->r, H->q, N, red(H, OP_STORE, S_RR), s, &gn);
         CHK(check_launch());
         CHK(post_scalars(H));
         // the next direction only reads r and the scalars, so it may run ahead of the check
@@ -570,7 +590,7 @@ void next_direction32(hp_handle* H) {
     RedCtl rc = red(H, OP_BETA);
     if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, F.N, rc, s);
     launch_xpby_x<float>(H->z32, H->p32, H->x32, F.N, H->scal, s);
-    launch_apply<float>(geo<float>(H, F), F.rho32, F.m32, H->p32, nullptr, H->q32, 1,
+    launch_apply<float>(geo_pass(H, geo<float>(H, F), 0), F.rho32, F.m32, H->p32, nullptr, H->q32, 1,
                         red(H, OP_ALPHA), s);
 }
 
@@ -586,13 +606,14 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
         if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, N, rc, s);
     }
     launch_copy<float>(H->z32, H->p32, N, s);
-    launch_apply<float>(g, F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
+    launch_apply<float>(geo_pass(H, g, 0), F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
     *its = 0;
     double rr_prev = 1.0, ratio = 1.0;
     bool ahead = false;
     while (*its < budget) {
         // r -= alpha q; x += alpha p is deferred to the next direction update (or the end)
-        launch_axpy_norm<float>(H->r32, H->q32, N, red(H, OP_STORE, S_RR), s);
+        const Geo<float> gn = geo_pass(H, g, 0);
+        launch_axpy_norm<float>(H->r32, H->q32, N, red(H, OP_STORE, S_RR), s, &gn);
         CHK(check_launch());
         CHK(post_scalars(H));
         ahead = *its + 1 < budget && look_ahead(rr_prev, ratio, eta);
@@ -1093,6 +1114,7 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     int levels = st.levels;
     st = hp_stats{};
     st.levels = levels;
+    H->dir = 0;  // the same sequence of pass directions (and so of reduction orders) every solve
     LevelData& F = H->lv[0];
     const int64_t N = F.N;
     hipStream_t s = H->stream;
