@@ -62,6 +62,7 @@ struct Transfer {
     int fx, fy, fz;        // 1 if the axis is coarsened
     int perx, pery, perz;  // 1 if the axis is periodic
     int fsplit;            // 1 if the fine level uses the red-black split layout
+    int csplit = 0;        // 1 if the coarse level does
     int rev = 0;           // 1: z-march tiles in reverse order
 };
 

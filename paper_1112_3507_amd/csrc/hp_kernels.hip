@@ -593,13 +593,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
 #ifndef HP_ZS_ROWS
 #define HP_ZS_ROWS 4
 #endif
-#ifndef HP_ZS_XW
-#define HP_ZS_XW 2
-#endif
 constexpr int kRowsS = HP_ZS_ROWS;     // x rows per workgroup of the split-layout kernels
-constexpr int kXW = HP_ZS_XW;          // waves per row: a row tile spans kTW half positions
-constexpr int kTW = 64 * kXW;
-constexpr int kBlockS = kTW * kRowsS;
+// Waves per row of the split kernels: a row tile spans 64 XW half positions, two waves where
+// rows have more than 64 half positions (up to 256 cells: the whole row), else one.
+static inline int split_xw(int hx) { return hx > 64 ? 2 : 1; }
 // Thread (t, j) owns the cell pair (2t, 2t+1) of row j: half position t of the red and of the
 // black half of the row. Cell 2t has the colour of the row parity p = (j + k) & 1; cell 2t-1
 // (half position t-1) the other colour and cell 2t+2 (half position t+1) the same colour. The
@@ -679,14 +676,15 @@ static_assert(kRowsS >= 2, "the split kernels need separate first and last rows"
 #ifndef HP_ZS_WG
 #define HP_ZS_WG 0
 #endif
-// Tiles of the split kernels over hx = nx/2 half positions: kTW per tile, kRowsS rows, z chunks
+// Tiles of the split kernels over hx = nx/2 half positions: 64 XW per tile, kRowsS rows, z chunks
 // of at least HP_ZMIN planes, about 8192 waves in all.
 static ZTiles split_tiles(int hx, int ny, int nz) {
+    const int xw = split_xw(hx), tw = 64 * xw;
     ZTiles t;
-    t.tx = (hx + kTW - 1) / kTW;
+    t.tx = (hx + tw - 1) / tw;
     t.ty = (ny + kRowsS - 1) / kRowsS;
     const int cols = t.tx * t.ty;
-    const int target = HP_ZS_WG > 0 ? HP_ZS_WG : 8192 / (kXW * kRowsS);
+    const int target = HP_ZS_WG > 0 ? HP_ZS_WG : 8192 / (xw * kRowsS);
     t.kz = nz;
     if (HP_ZS_WG > 0) {
         const int want = std::max(1, std::min(nz, (target + cols / 2) / cols));
@@ -698,8 +696,9 @@ static ZTiles split_tiles(int hx, int ny, int nz) {
     return t;
 }
 
-template <bool FULL>
+template <bool FULL, int XW>
 struct SplitLane {
+    static constexpr int kTW = 64 * XW;
     int lane;    // position in the row tile, 0 .. kTW-1 (the LDS column)
     int w;       // row of the workgroup
     int tl, t, j, j0;
@@ -754,18 +753,19 @@ __device__ __forceinline__ Pair<T> pos(const HalfPair<T>& h, int par) {
 // Operator apply in the split layout: the pair march of k_apply_zp with each pair read from the
 // two halves of its row; pairs of x and rho of the current plane are exchanged through LDS. The
 // column pairs of x (planes k-1 .. k+2) and rho (k .. k+2) form the register rings.
-template <typename T, int MODE, bool FULL>
-__global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
+template <typename T, int MODE, bool FULL, int XW>
+__global__ __launch_bounds__(64 * XW * kRowsS) void k_apply_zs(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
                                                      const T* __restrict__ m,
                                                      const T* __restrict__ x,
                                                      const T* __restrict__ b, T* __restrict__ y,
                                                      double* __restrict__ partials) {
+    constexpr int kTW = 64 * XW, kBlockS = kTW * kRowsS;
     __shared__ T sx[2][2][kRowsS + 2][2][kTW];  // [plane slot][x, rho][row][cell of the pair][column]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int nx = g.nx, ny = g.ny, hx = nx >> 1;
-    const SplitLane<FULL> L(bx, by, hx);
+    const SplitLane<FULL, XW> L(bx, by, hx);
     const int t = L.t, j = L.j, lane = L.lane, w = L.w;
     const SplitCol<T> sc(g, t, j);
     const int lm = L.lm, lp = L.lp;
@@ -931,18 +931,19 @@ __global__ __launch_bounds__(kBlockS) void k_apply_zs(Geo<T> g, ZTiles zt,
 // cells of colour c only. ZG (with RESID, colour red): z holds the zero-guess pre-smoothing,
 // whose red values are r dinv, so r - (m + sum w) z vanishes on red cells and t = sum_f w_f z_nb
 // (r and m are not read).
-template <typename T, bool DOT, bool RESID, bool ZG, bool FULL>
-__global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
+template <typename T, bool DOT, bool RESID, bool ZG, bool FULL, int XW>
+__global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
                                                     const T* __restrict__ m,
                                                     const T* __restrict__ r, T* __restrict__ z,
                                                     int colour, double* __restrict__ partials,
                                                     T* __restrict__ tout) {
+    constexpr int kTW = 64 * XW, kBlockS = kTW * kRowsS;
     __shared__ T sx[2][2][kRowsS + 2][kTW];  // [plane slot][z, rho of the other colour][row][column]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int nx = g.nx, ny = g.ny, hx = nx >> 1;
-    const SplitLane<FULL> L(bx, by, hx);
+    const SplitLane<FULL, XW> L(bx, by, hx);
     const int t = L.t, j = L.j, lane = L.lane, w = L.w;
     const int ch = colour * hx, oh = (colour ^ 1) * hx;
     const SplitCol<T> sc(g, t, j);
@@ -1075,17 +1076,18 @@ __global__ __launch_bounds__(kBlockS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
 // z_black = dinv_b (r_b + sum_f w_f (r dinv)_nb) on black cells, whose neighbours are all red.
 // The red q = r dinv and rho of the current plane are exchanged through LDS; the red column
 // (r, dinv and rho at t, planes k-1 .. k+2) forms the register ring.
-template <typename T, bool FULL>
-__global__ __launch_bounds__(kBlockS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
+template <typename T, bool FULL, int XW>
+__global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
                                                          const T* __restrict__ rho,
                                                          const T* __restrict__ dinv,
                                                          const T* __restrict__ r,
                                                          T* __restrict__ z) {
+    constexpr int kTW = 64 * XW, kBlockS = kTW * kRowsS;
     __shared__ T sx[2][2][kRowsS + 2][kTW];  // [plane slot][red q, red rho][row][column]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int nx = g.nx, ny = g.ny, hx = nx >> 1;
-    const SplitLane<FULL> L(bx, by, hx);
+    const SplitLane<FULL, XW> L(bx, by, hx);
     const int t = L.t, j = L.j, lane = L.lane, w = L.w;
     const SplitCol<T> sc(g, t, j);
     const int lm = L.lm, lp = L.lp;
@@ -1204,35 +1206,67 @@ __global__ __launch_bounds__(kBlockS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
     if (k + 2 < k1) step(k + 2, C2, C3, C0, C1, A, B);
 }
 
-// Launch one split kernel over its tiles, with FULL where a row tile spans the whole row.
+// Launch one split kernel over its tiles: one wave per row for rows of up to 64 half positions,
+// else two; FULL where the row tile spans the whole row. F(full, xw) names the instance.
+enum SplitShape { SPLIT_FULL1, SPLIT_FULL2, SPLIT_TILED2 };
+static inline SplitShape split_shape(int hx) {
+    return hx <= 64 ? SPLIT_FULL1 : (hx <= 128 ? SPLIT_FULL2 : SPLIT_TILED2);
+}
+static inline dim3 split_block(int hx) { return dim3(64 * split_xw(hx) * kRowsS); }
+
 template <typename T, int MODE>
 static void launch_apply_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, const T* m, const T* x,
                             const T* b, T* y, double* partials, hipStream_t s) {
-    const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlockS);
-    if ((g.nx >> 1) <= kTW)
-        hipLaunchKernelGGL((k_apply_zs<T, MODE, true>), grid, block, 0, s, g, zt, rho, m, x, b, y, partials);
-    else
-        hipLaunchKernelGGL((k_apply_zs<T, MODE, false>), grid, block, 0, s, g, zt, rho, m, x, b, y, partials);
+    const int hx = g.nx >> 1;
+    const dim3 grid(zt.tx * zt.ty * zt.tz), block = split_block(hx);
+    switch (split_shape(hx)) {
+        case SPLIT_FULL1:
+            hipLaunchKernelGGL((k_apply_zs<T, MODE, true, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, partials);
+            break;
+        case SPLIT_FULL2:
+            hipLaunchKernelGGL((k_apply_zs<T, MODE, true, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, partials);
+            break;
+        default:
+            hipLaunchKernelGGL((k_apply_zs<T, MODE, false, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, partials);
+            break;
+    }
 }
 template <typename T, bool DOT, bool RESID, bool ZG>
 static void launch_rbgs_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, const T* m, const T* r, T* z,
                            int colour, double* partials, T* tout, hipStream_t s) {
-    const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlockS);
-    if ((g.nx >> 1) <= kTW)
-        hipLaunchKernelGGL((k_rbgs_zs<T, DOT, RESID, ZG, true>), grid, block, 0, s, g, zt, rho, m, r, z,
-                           colour, partials, tout);
-    else
-        hipLaunchKernelGGL((k_rbgs_zs<T, DOT, RESID, ZG, false>), grid, block, 0, s, g, zt, rho, m, r, z,
-                           colour, partials, tout);
+    const int hx = g.nx >> 1;
+    const dim3 grid(zt.tx * zt.ty * zt.tz), block = split_block(hx);
+    switch (split_shape(hx)) {
+        case SPLIT_FULL1:
+            hipLaunchKernelGGL((k_rbgs_zs<T, DOT, RESID, ZG, true, 1>), grid, block, 0, s, g, zt, rho, m, r, z,
+                               colour, partials, tout);
+            break;
+        case SPLIT_FULL2:
+            hipLaunchKernelGGL((k_rbgs_zs<T, DOT, RESID, ZG, true, 2>), grid, block, 0, s, g, zt, rho, m, r, z,
+                               colour, partials, tout);
+            break;
+        default:
+            hipLaunchKernelGGL((k_rbgs_zs<T, DOT, RESID, ZG, false, 2>), grid, block, 0, s, g, zt, rho, m, r, z,
+                               colour, partials, tout);
+            break;
+    }
 }
 template <typename T>
 static void launch_presmooth_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, const T* dinv, const T* r,
                                 T* z, hipStream_t s) {
-    const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlockS);
-    if ((g.nx >> 1) <= kTW)
-        hipLaunchKernelGGL((k_presmooth_zs<T, true>), grid, block, 0, s, g, zt, rho, dinv, r, z);
-    else
-        hipLaunchKernelGGL((k_presmooth_zs<T, false>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+    const int hx = g.nx >> 1;
+    const dim3 grid(zt.tx * zt.ty * zt.tz), block = split_block(hx);
+    switch (split_shape(hx)) {
+        case SPLIT_FULL1:
+            hipLaunchKernelGGL((k_presmooth_zs<T, true, 1>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+            break;
+        case SPLIT_FULL2:
+            hipLaunchKernelGGL((k_presmooth_zs<T, true, 2>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+            break;
+        default:
+            hipLaunchKernelGGL((k_presmooth_zs<T, false, 2>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+            break;
+    }
 }
 
 static bool use_zm(int nx, int ny, int nz) { return nx >= 64 && ny >= 4 && nz >= 8; }
@@ -1762,7 +1796,15 @@ __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >
 // x-y weighted sum u(k) of each fine plane is reused by the two coarse planes it feeds.
 // SPLIT: the fine level uses the red-black split layout (the pair (2I, 2I+1) of a fine row sits
 // at half position I of its two halves); RED_ONLY: its black cells are zero and not read.
-template <typename T, bool SPLIT, bool RED_ONLY>
+// Index of coarse cell (I, J, K) in natural order or, CSPLIT, in the red-black split layout.
+template <bool CSPLIT>
+__device__ __forceinline__ int64_t coarse_idx(const Transfer& t, int I, int J, int K) {
+    const int64_t rb = ((int64_t)K * t.ncy + J) * t.ncx;
+    if (!CSPLIT) return rb + I;
+    return rb + ((I + J + K) & 1) * (t.ncx >> 1) + (I >> 1);
+}
+
+template <typename T, bool SPLIT, bool RED_ONLY, bool CSPLIT = false>
 __global__ __launch_bounds__(kBlock) void k_restrict_zm(Transfer t, ZTiles zt,
                                                         const T* __restrict__ fine,
                                                         T* __restrict__ coarse) {
@@ -1833,8 +1875,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_zm(Transfer t, ZTiles zt,
         const T u2 = plane_sum(wrapi(2 * K + 1, nfz));
         const T u3 = plane_sum(wrapi(2 * K + 2, nfz));
         if (valid)
-            coarse[(int64_t)K * t.ncx * t.ncy + (int64_t)J * t.ncx + I] =
-                (T)w[0] * u0 + (T)w[1] * u1 + (T)w[2] * u2 + (T)w[3] * u3;
+            coarse[coarse_idx<CSPLIT>(t, I, J, K)] = (T)w[0] * u0 + (T)w[1] * u1 + (T)w[2] * u2 + (T)w[3] * u3;
         // the next coarse plane starts at fine plane 2K+1
         u0 = u2;
         u1 = u3;
@@ -1845,16 +1886,113 @@ static bool transfer_zm(const Transfer& t) {
     return t.fx && t.fy && t.fz && t.ncx >= 32 && t.ncy >= 4 && t.ncz >= 4;
 }
 
+// Red-only restriction from a split fine level (the residual after a zero-guess pre-smoothing
+// vanishes on black cells): the thread and plane structure of k_restrict_zm<T, true, true>, with
+// the red entries of the next two fine planes loaded while the current coarse plane is summed
+// and the coarse-plane loop unrolled by two, so that the loaded records alternate by renaming.
+template <typename T, bool CSPLIT>
+__global__ __launch_bounds__(kBlock) void k_restrict_red(Transfer t, ZTiles zt, const T* __restrict__ fine,
+                                                         T* __restrict__ coarse) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int lane = threadIdx.x & 63;
+    const int I = bx * 64 + lane;
+    const int J = by * 4 + (threadIdx.x >> 6);
+    const bool valid = I < t.ncx && J < t.ncy;
+    const int Ic = valid ? I : t.ncx - 1, Jc = J < t.ncy ? J : t.ncy - 1;
+    const int K0 = bz * zt.kz, K1 = min(K0 + zt.kz, t.ncz);
+    const int nfx = t.nfx, nfy = t.nfy, nfz = t.nfz;
+    const int64_t sf = (int64_t)nfx * nfy;
+    float wx[4], wy[4];
+    rweights4(Ic, nfx, t.perx, wx);
+    rweights4(Jc, nfy, t.pery, wy);
+    int row[4], jr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        jr[q] = wrapi(2 * Jc - 1 + q, nfy);  // rows with w 0 are harmless
+        row[q] = jr[q] * nfx;
+    }
+    const int hl = wrapi(2 * Ic - 1, nfx) >> 1, hr = wrapi(2 * Ic + 2, nfx) >> 1;
+    const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == t.ncx - 1);
+    // red entries of the four fine rows of one plane at half position Ic and, at a wave edge,
+    // the red outer neighbour (cell 2I-1 is red where the row parity is 1, cell 2I+2 where it is 0)
+    struct Raw {
+        T c[4], e[4];
+    };
+    auto load_plane = [&](int k, Raw& o) {
+        const T* base = fine + (int64_t)k * sf;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T* rp = base + row[q];
+            const int pf = (jr[q] + k) & 1;
+            o.c[q] = rp[Ic];
+            o.e[q] = (pf ? edge_l : edge_r) ? rp[pf ? hl : hr] : T(0);
+        }
+    };
+    // weighted x-y sum of fine plane k
+    auto plane_sum = [&](int k, const Raw& o) -> T {
+        T u = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int pf = (jr[q] + k) & 1;
+            const T v = o.c[q];
+            const T f0 = pf ? T(0) : v, f1 = pf ? v : T(0);
+            T left = __shfl_up(f1, 1, 64), right = __shfl_down(f0, 1, 64);
+            if (edge_l) left = pf ? o.e[q] : T(0);
+            if (edge_r) right = pf ? T(0) : o.e[q];
+            u += (T)wy[q] * ((T)wx[0] * left + (T)wx[1] * f0 + (T)wx[2] * f1 + (T)wx[3] * right);
+        }
+        return u;
+    };
+    // u of fine planes 2K0-1 and 2K0; plane indices wrap, so a missing Neumann plane reads a
+    // valid plane that then gets weight 0
+    T u0, u1;
+    {
+        Raw a, b;
+        const int ka = wrapi(2 * K0 - 1, nfz), kb = wrapi(2 * K0, nfz);
+        load_plane(ka, a);
+        load_plane(kb, b);
+        u0 = plane_sum(ka, a);
+        u1 = plane_sum(kb, b);
+    }
+    auto cstep = [&](int K, const Raw& p0, const Raw& p1, Raw& n0, Raw& n1) {
+        const int Kn = min(K + 1, K1 - 1);
+        load_plane(wrapi(2 * Kn + 1, nfz), n0);
+        load_plane(wrapi(2 * Kn + 2, nfz), n1);
+        float w[4];
+        rweights4(K, nfz, t.perz, w);
+        const T u2 = plane_sum(wrapi(2 * K + 1, nfz), p0);
+        const T u3 = plane_sum(wrapi(2 * K + 2, nfz), p1);
+        if (valid)
+            coarse[coarse_idx<CSPLIT>(t, I, J, K)] = (T)w[0] * u0 + (T)w[1] * u1 + (T)w[2] * u2 + (T)w[3] * u3;
+        // the next coarse plane starts at fine plane 2K+1
+        u0 = u2;
+        u1 = u3;
+    };
+    Raw A0, A1, B0, B1;
+    load_plane(wrapi(2 * K0 + 1, nfz), A0);
+    load_plane(wrapi(2 * K0 + 2, nfz), A1);
+    for (int K = K0; K < K1; K += 2) {
+        cstep(K, A0, A1, B0, B1);
+        if (K + 1 < K1) cstep(K + 1, B0, B1, A0, A1);
+    }
+}
+
 template <typename T>
 void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
         ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64, 2);
         zt.rev = t.rev;
         const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlock);
+        // a split coarse level always has a split fine level above it
         if (!t.fsplit)
             hipLaunchKernelGGL((k_restrict_zm<T, false, false>), grid, block, 0, s, t, zt, fine, coarse);
+        else if (red_only && t.csplit)
+            hipLaunchKernelGGL((k_restrict_red<T, true>), grid, block, 0, s, t, zt, fine, coarse);
         else if (red_only)
-            hipLaunchKernelGGL((k_restrict_zm<T, true, true>), grid, block, 0, s, t, zt, fine, coarse);
+            hipLaunchKernelGGL((k_restrict_red<T, false>), grid, block, 0, s, t, zt, fine, coarse);
+        else if (t.csplit)
+            hipLaunchKernelGGL((k_restrict_zm<T, true, false, true>), grid, block, 0, s, t, zt, fine, coarse);
         else
             hipLaunchKernelGGL((k_restrict_zm<T, true, false>), grid, block, 0, s, t, zt, fine, coarse);
         return;
@@ -1913,7 +2051,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Transfer t, const T* __r
 // The x-y interpolation v(K) of coarse planes K-1, K, K+1 is kept in registers while marching.
 // RED_ONLY (split layout): only the red cells are corrected, for a black half sweep that follows
 // and overwrites every black cell without reading it.
-template <typename T, bool SPLIT, bool RED_ONLY = false>
+template <typename T, bool SPLIT, bool RED_ONLY = false, bool CSPLIT = false>
 __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
                                                        const T* __restrict__ coarse,
                                                        T* __restrict__ fine) {
@@ -1937,12 +2075,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
     const int rowJ = J * ncx, rowJ2 = J2 * ncx;
     const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == ncx - 1);
     // v(K) for the two fine columns
+    auto cv = [&](int Ix, int Jy, int K) { return coarse[coarse_idx<CSPLIT>(t, Ix, Jy, K)]; };
     auto vplane = [&](int K, T& vlo, T& vhi) {
-        const T* cp = coarse + (int64_t)K * sc;
-        const T cy = T(0.75) * cp[rowJ + Ic] + T(0.25) * cp[rowJ2 + Ic];
+        const T cy = T(0.75) * cv(Ic, J, K) + T(0.25) * cv(Ic, J2, K);
         T cl = __shfl_up(cy, 1, 64), cr = __shfl_down(cy, 1, 64);
-        if (edge_l) cl = T(0.75) * cp[rowJ + xm] + T(0.25) * cp[rowJ2 + xm];
-        if (edge_r) cr = T(0.75) * cp[rowJ + xp] + T(0.25) * cp[rowJ2 + xp];
+        if (edge_l) cl = T(0.75) * cv(xm, J, K) + T(0.25) * cv(xm, J2, K);
+        if (edge_r) cr = T(0.75) * cv(xp, J, K) + T(0.25) * cv(xp, J2, K);
         vlo = T(0.75) * cy + T(0.25) * cl;
         vhi = T(0.75) * cy + T(0.25) * cr;
     };
@@ -1985,6 +2123,101 @@ __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
     }
 }
 
+// Red-only prolongation onto a split fine level (the following black half sweep overwrites the
+// black cells): the thread and plane structure of k_prolong_zm<T, true, true>, over fine planes
+// in pairs (one coarse plane each), with the coarse entries of the next coarse plane and the red
+// entries of the next two fine planes loaded a pair ahead, the pair loop unrolled by two.
+template <typename T, bool CSPLIT>
+__global__ __launch_bounds__(kBlock) void k_prolong_red(Transfer t, ZTiles zt, const T* __restrict__ coarse,
+                                                        T* __restrict__ fine) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int lane = threadIdx.x & 63;
+    const int I = bx * 64 + lane;
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const bool valid = I < t.ncx && j < t.nfy;
+    const int Ic = I < t.ncx ? I : t.ncx - 1, jc = j < t.nfy ? j : t.nfy - 1;
+    const int k0 = bz * zt.kz, k1 = min(k0 + zt.kz, t.nfz);  // k0 even
+    const int ncx = t.ncx, ncy = t.ncy, ncz = t.ncz;
+    const int64_t sc = (int64_t)ncx * ncy;
+    // x neighbours of the parent column (mirror onto the parent at a Neumann end)
+    const int xm = Ic > 0 ? Ic - 1 : (t.perx ? ncx - 1 : Ic);
+    const int xp = Ic < ncx - 1 ? Ic + 1 : (t.perx ? 0 : Ic);
+    // y: parent row and second row
+    const int J = jc >> 1;
+    int J2 = (jc & 1) ? J + 1 : J - 1;
+    if (J2 < 0 || J2 >= ncy) J2 = t.pery ? (J2 + ncy) % ncy : J;
+    const int rowJ = J * ncx, rowJ2 = J2 * ncx;
+    const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == ncx - 1);
+    // coarse entries of one coarse plane: parent and second row at Ic, and the outer columns at a
+    // wave edge
+    struct Raw {
+        T c0, c1, l0, l1, r0, r1;
+    };
+    auto load_raw = [&](int K, Raw& o) {
+        o.c0 = coarse[coarse_idx<CSPLIT>(t, Ic, J, K)];
+        o.c1 = coarse[coarse_idx<CSPLIT>(t, Ic, J2, K)];
+        o.l0 = edge_l ? coarse[coarse_idx<CSPLIT>(t, xm, J, K)] : T(0);
+        o.l1 = edge_l ? coarse[coarse_idx<CSPLIT>(t, xm, J2, K)] : T(0);
+        o.r0 = edge_r ? coarse[coarse_idx<CSPLIT>(t, xp, J, K)] : T(0);
+        o.r1 = edge_r ? coarse[coarse_idx<CSPLIT>(t, xp, J2, K)] : T(0);
+    };
+    // v(K) for the two fine columns
+    auto vplane = [&](const Raw& o, T& vlo, T& vhi) {
+        const T cy = T(0.75) * o.c0 + T(0.25) * o.c1;
+        T cl = __shfl_up(cy, 1, 64), cr = __shfl_down(cy, 1, 64);
+        if (edge_l) cl = T(0.75) * o.l0 + T(0.25) * o.l1;
+        if (edge_r) cr = T(0.75) * o.r0 + T(0.25) * o.r1;
+        vlo = T(0.75) * cy + T(0.25) * cl;
+        vhi = T(0.75) * cy + T(0.25) * cr;
+    };
+    auto zm = [&](int K) { return K > 0 ? K - 1 : (t.perz ? ncz - 1 : K); };
+    auto zp = [&](int K) { return K < ncz - 1 ? K + 1 : (t.perz ? 0 : K); };
+    // the red entry of fine plane k at half position Ic
+    auto zat = [&](int k) -> T* { return fine + ((int64_t)k * t.nfy + jc) * t.nfx + Ic; };
+    T mlo, mhi, clo, chi;
+    {
+        Raw a, b;
+        const int K = k0 >> 1;
+        load_raw(zm(K), a);
+        load_raw(K, b);
+        vplane(a, mlo, mhi);
+        vplane(b, clo, chi);
+    }
+    // fine planes k, k+1 of coarse plane K = k/2: the lower one takes the plane below (m), the
+    // upper one the plane above (n, from the entries loaded a pair earlier)
+    auto pstep = [&](int k, const Raw& rn, Raw& rnn, const T& z0, const T& z1, T& z0n, T& z1n) {
+        const int K = k >> 1;
+        load_raw(zp(min(K + 1, ncz - 1)), rnn);
+        z0n = *zat(min(k + 2, k1 - 1));
+        z1n = *zat(min(k + 3, k1 - 1));
+        T nlo, nhi;
+        vplane(rn, nlo, nhi);
+        if (valid) {
+            const int p = (jc + k) & 1;  // cell 2I of plane k has colour p; plane k+1 the other
+            const T dlo0 = T(0.75) * clo + T(0.25) * mlo, dhi0 = T(0.75) * chi + T(0.25) * mhi;
+            *zat(k) = z0 + (p ? dhi0 : dlo0);
+            if (k + 1 < k1) {
+                const T dlo1 = T(0.75) * clo + T(0.25) * nlo, dhi1 = T(0.75) * chi + T(0.25) * nhi;
+                *zat(k + 1) = z1 + (p ? dlo1 : dhi1);
+            }
+        }
+        mlo = clo;
+        mhi = chi;
+        clo = nlo;
+        chi = nhi;
+    };
+    Raw A, B;
+    T za0, za1, zb0, zb1;
+    load_raw(zp(k0 >> 1), A);
+    za0 = *zat(k0);
+    za1 = *zat(min(k0 + 1, k1 - 1));
+    for (int k = k0; k < k1; k += 4) {
+        pstep(k, A, B, za0, za1, zb0, zb1);
+        if (k + 2 < k1) pstep(k + 2, B, A, zb0, zb1, za0, za1);
+    }
+}
+
 template <typename T>
 void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
@@ -1992,12 +2225,15 @@ void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t
         zt.rev = t.rev;
         zt.kz += zt.kz & 1;  // chunks start on even fine planes
         zt.tz = (t.nfz + zt.kz - 1) / zt.kz;
-        if (t.fsplit && red_only)
-            hipLaunchKernelGGL((k_prolong_zm<T, true, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s,
-                               t, zt, coarse, fine);
+        const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlock);
+        if (t.fsplit && red_only && t.csplit)
+            hipLaunchKernelGGL((k_prolong_red<T, true>), grid, block, 0, s, t, zt, coarse, fine);
+        else if (t.fsplit && red_only)
+            hipLaunchKernelGGL((k_prolong_red<T, false>), grid, block, 0, s, t, zt, coarse, fine);
+        else if (t.fsplit && t.csplit)
+            hipLaunchKernelGGL((k_prolong_zm<T, true, false, true>), grid, block, 0, s, t, zt, coarse, fine);
         else if (t.fsplit)
-            hipLaunchKernelGGL((k_prolong_zm<T, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t,
-                               zt, coarse, fine);
+            hipLaunchKernelGGL((k_prolong_zm<T, true>), grid, block, 0, s, t, zt, coarse, fine);
         else
             hipLaunchKernelGGL((k_prolong_zm<T, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, t,
                                zt, coarse, fine);
@@ -2120,10 +2356,11 @@ __global__ __launch_bounds__(kBlock) void k_axpy_norm(T* __restrict__ r, const T
 // The same two updates over a split finest level in the tile order of the split kernels (and in
 // their direction), so that they start on what the previous pass left in the memory-side cache.
 // Four planes of loads are in flight per thread.
-template <typename T>
-__global__ __launch_bounds__(kBlockS) void k_axpy_norm_zs(ZTiles zt, int nx, int ny, int nz,
+template <typename T, int XW>
+__global__ __launch_bounds__(64 * XW * kRowsS) void k_axpy_norm_zs(ZTiles zt, int nx, int ny, int nz,
                                                           T* __restrict__ r, const T* __restrict__ q,
                                                           RedCtl rc) {
+    constexpr int kTW = 64 * XW;
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int hx = nx >> 1;
@@ -2157,10 +2394,11 @@ __global__ __launch_bounds__(kBlockS) void k_axpy_norm_zs(ZTiles zt, int nx, int
     block_partial(acc, rc.partials);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlockS) void k_xpby_x_zs(ZTiles zt, int nx, int ny, int nz,
+template <typename T, int XW>
+__global__ __launch_bounds__(64 * XW * kRowsS) void k_xpby_x_zs(ZTiles zt, int nx, int ny, int nz,
                                                        const T* __restrict__ z, T* __restrict__ p,
                                                        T* __restrict__ x, const double* __restrict__ scal) {
+    constexpr int kTW = 64 * XW;
     int bx, by, bz;
     ztile(zt, bx, by, bz);
     const int hx = nx >> 1;
@@ -2199,7 +2437,12 @@ void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t
         ZTiles zt = split_tiles(g->nx >> 1, g->ny, g->nz);
         zt.rev = g->rev;
         const int nb = zt.tx * zt.ty * zt.tz;
-        hipLaunchKernelGGL((k_axpy_norm_zs<T>), dim3(nb), dim3(kBlockS), 0, s, zt, g->nx, g->ny, g->nz, r, q, rc);
+        if (split_xw(g->nx >> 1) == 1)
+            hipLaunchKernelGGL((k_axpy_norm_zs<T, 1>), dim3(nb), split_block(g->nx >> 1), 0, s, zt, g->nx, g->ny,
+                               g->nz, r, q, rc);
+        else
+            hipLaunchKernelGGL((k_axpy_norm_zs<T, 2>), dim3(nb), split_block(g->nx >> 1), 0, s, zt, g->nx, g->ny,
+                               g->nz, r, q, rc);
         finalize(rc, nb, s);
         return;
     }
@@ -2225,8 +2468,12 @@ void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStr
     if (g && g->split) {
         ZTiles zt = split_tiles(g->nx >> 1, g->ny, g->nz);
         zt.rev = g->rev;
-        hipLaunchKernelGGL((k_xpby_x_zs<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlockS), 0, s, zt, g->nx, g->ny,
-                           g->nz, z, p, x, scal);
+        if (split_xw(g->nx >> 1) == 1)
+            hipLaunchKernelGGL((k_xpby_x_zs<T, 1>), dim3(zt.tx * zt.ty * zt.tz), split_block(g->nx >> 1), 0, s, zt,
+                               g->nx, g->ny, g->nz, z, p, x, scal);
+        else
+            hipLaunchKernelGGL((k_xpby_x_zs<T, 2>), dim3(zt.tx * zt.ty * zt.tz), split_block(g->nx >> 1), 0, s, zt,
+                               g->nx, g->ny, g->nz, z, p, x, scal);
         return;
     }
     hipLaunchKernelGGL((k_xpby_x<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,

@@ -162,6 +162,7 @@ Transfer transfer(const hp_handle* H, int l) {
     t.pery = H->bc.y == HP_BC_PERIODIC;
     t.perz = H->bc.z == HP_BC_PERIODIC;
     t.fsplit = F.split;
+    t.csplit = C.split;
     return t;
 }
 
@@ -311,8 +312,24 @@ bool split_allowed(const hp_handle* H) {
     return split_layout_ok(F.n[0], F.n[1], F.n[2], &t);
 }
 
-// Bring the finest level's coefficient arrays to the natural (0) or split (1) layout; the
-// relayout goes through the CG scratch vectors p and p32.
+// Whether level l can follow a split level l-1 in the split layout: the same conditions as the
+// finest level, and rows of at least 64 half positions (one wave per row).
+bool split_allowed_below(const hp_handle* H, size_t l) {
+    if (l + 1 >= H->lv.size()) return false;
+    const LevelData& L = H->lv[l];
+    Transfer t = transfer(H, (int)l);
+    return L.n[0] / 2 >= 64 && split_layout_ok(L.n[0], L.n[1], L.n[2], &t);
+}
+
+template <typename T>
+void relayout_l(hp_handle* H, int l, const T* src, T* dst, int to_split) {
+    const LevelData& L = H->lv[l];
+    launch_relayout<T>(src, dst, L.n[0], L.n[1], L.n[2], to_split, H->stream);
+}
+
+// Bring the coefficient arrays to the natural (0) or split (1) layout: the finest level and,
+// below it, every level that allows it as long as the level above is split. The relayout goes
+// through the CG scratch vectors p and p32.
 int set_layout(hp_handle* H, int split) {
     LevelData& F = H->lv[0];
     if (F.split == split) return HP_OK;
@@ -329,16 +346,24 @@ int set_layout(hp_handle* H, int split) {
         HIPCHK(hipMemcpyAsync(H->rho_nat, F.rho, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(H->m_nat, F.m, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    for (double* a : {F.rho, F.m, F.dinv}) {
-        launch_relayout<double>(a, H->p, F.n[0], F.n[1], F.n[2], split, s);
-        launch_copy<double>(H->p, a, N, s);
-    }
-    for (float* a : {F.rho32, F.m32, F.dinv32}) {
-        launch_relayout<float>(a, H->p32, F.n[0], F.n[1], F.n[2], split, s);
-        launch_copy<float>(H->p32, a, N, s);
+    for (size_t l = 0; l < H->lv.size(); ++l) {
+        LevelData& L = H->lv[l];
+        const int want = split && (l == 0 || (H->lv[l - 1].split && split_allowed_below(H, l)));
+        if (L.split == want) {
+            if (!want) break;
+            continue;
+        }
+        for (double* a : {L.rho, L.m, L.dinv}) {
+            relayout_l<double>(H, (int)l, a, H->p, want);
+            launch_copy<double>(H->p, a, L.N, s);
+        }
+        for (float* a : {L.rho32, L.m32, L.dinv32}) {
+            relayout_l<float>(H, (int)l, a, H->p32, want);
+            launch_copy<float>(H->p32, a, L.N, s);
+        }
+        L.split = want;
     }
     CHK(check_launch());
-    F.split = split;
     return HP_OK;
 }
 
@@ -359,7 +384,7 @@ int load_coefficients(hp_handle* H, const double* rho, const double* c2, double 
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HP_EINVAL, "dt must be positive and finite");
     H->dt = dt;
     LevelData& F = H->lv[0];
-    F.split = 0;  // every array below is recomputed in natural order
+    for (auto& L : H->lv) L.split = 0;  // every array below is recomputed in natural order
     *H->host_flag = 0;
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
     launch_setup_coef(rho, c2, F.rho, F.m, F.rho32, F.m32, F.N, H->flag, H->stream);
@@ -810,10 +835,10 @@ int apply_t(hp_handle* H, int level, const T* x, T* y) {
     LevelData& L = H->lv[level];
     if (L.split) {
         T *a = tmp_a<T>(H), *c = tmp_b<T>(H);
-        relayout0<T>(H, x, a, 1);
+        relayout_l<T>(H, level, x, a, 1);
         launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), a, nullptr, c, 0, red(H, OP_NONE),
                         H->stream);
-        relayout0<T>(H, c, y, 0);
+        relayout_l<T>(H, level, c, y, 0);
         return check_launch();
     }
     launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), x, nullptr, y, 0, red(H, OP_NONE),
@@ -829,10 +854,10 @@ int smooth_t(hp_handle* H, int level, const T* r, T* z, int colour) {
     LevelData& L = H->lv[level];
     if (L.split) {
         T *a = tmp_a<T>(H), *c = tmp_b<T>(H);
-        relayout0<T>(H, r, a, 1);
-        relayout0<T>(H, z, c, 1);
+        relayout_l<T>(H, level, r, a, 1);
+        relayout_l<T>(H, level, z, c, 1);
         launch_rbgs<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), a, c, colour, H->stream);
-        relayout0<T>(H, c, z, 0);
+        relayout_l<T>(H, level, c, z, 0);
         return check_launch();
     }
     launch_rbgs<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), r, z, colour, H->stream);
@@ -845,16 +870,19 @@ int restrict_t(hp_handle* H, int level, const T* r, const T* z, T* rc) {
     if (level + 1 >= (int)H->lv.size()) return fail(HP_EINVAL, "no coarser level below %d", level);
     if (!r || !z || !rc) return fail(HP_EINVAL, "null vector");
     LevelData& L = H->lv[level];
+    LevelData& C = H->lv[level + 1];
     if (L.split) {
         T *a = tmp_a<T>(H), *c = tmp_b<T>(H);
-        relayout0<T>(H, r, a, 1);
-        relayout0<T>(H, z, c, 1);
+        relayout_l<T>(H, level, r, a, 1);
+        relayout_l<T>(H, level, z, c, 1);
         r = a;
         z = c;
     }
     launch_apply<T>(geo<T>(H, L), lvl_rho<T>(L), lvl_m<T>(L), z, r, lvl_t<T>(L), 2, red(H, OP_NONE),
                     H->stream);
-    launch_restrict<T>(transfer(H, level), lvl_t<T>(L), rc, H->stream);
+    // a split coarse level: restrict into its scratch vector t, then back to natural order
+    launch_restrict<T>(transfer(H, level), lvl_t<T>(L), C.split ? lvl_t<T>(C) : rc, H->stream);
+    if (C.split) relayout_l<T>(H, level + 1, lvl_t<T>(C), rc, 0);
     return check_launch();
 }
 
@@ -863,11 +891,16 @@ int prolong_t(hp_handle* H, int level, const T* ec, T* z) {
     CHK(level_ok(H, level));
     if (level + 1 >= (int)H->lv.size()) return fail(HP_EINVAL, "no coarser level below %d", level);
     if (!ec || !z) return fail(HP_EINVAL, "null vector");
+    LevelData& C = H->lv[level + 1];
+    if (C.split) {  // the coarse correction in split order, in the coarse level's scratch vector t
+        relayout_l<T>(H, level + 1, ec, lvl_t<T>(C), 1);
+        ec = lvl_t<T>(C);
+    }
     if (H->lv[level].split) {
         T* a = tmp_a<T>(H);
-        relayout0<T>(H, z, a, 1);
+        relayout_l<T>(H, level, z, a, 1);
         launch_prolong_add<T>(transfer(H, level), ec, a, H->stream);
-        relayout0<T>(H, a, z, 0);
+        relayout_l<T>(H, level, a, z, 0);
         return check_launch();
     }
     launch_prolong_add<T>(transfer(H, level), ec, z, H->stream);

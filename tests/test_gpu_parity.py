@@ -71,6 +71,9 @@ def reference(n, mach, seed, rhs_seed):
 
 
 RAGGED = (80, 24, 40)
+# 256 x 32 x 32: the split layout reaches level 1 (128 x 16 x 16, one wave per row) as well
+DEEP = (256, 32, 32)
+GRIDS = [RAGGED, DEEP]
 
 
 # ------------------------------------------------------------------ building blocks (FP64/FP32)
@@ -90,10 +93,11 @@ def test_hierarchy_matches_oracle_levels():
             assert np.allclose(h, L.h, rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_apply_parity_every_level(f32, layout):
-    p = problem(RAGGED, 0.001)
+def test_apply_parity_every_level(f32, layout, grid):
+    p = problem(grid, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(0)
     dt = torch.float32 if f32 else torch.float64
@@ -106,10 +110,11 @@ def test_apply_parity_every_level(f32, layout):
             assert relerr(host(y), ref) <= (2e-5 if f32 else 1e-13), (l, f32)
 
 
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_smoother_half_sweeps_parity(f32, layout):
-    p = problem(RAGGED, 0.001)
+def test_smoother_half_sweeps_parity(f32, layout, grid):
+    p = problem(grid, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(1)
     dt = torch.float32 if f32 else torch.float64
@@ -129,10 +134,11 @@ def test_smoother_half_sweeps_parity(f32, layout):
                 assert relerr(host(zt), ref) <= (2e-5 if f32 else 1e-12), (l, c)
 
 
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_restrict_and_prolong_parity(f32, layout):
-    p = problem(RAGGED, 0.001)
+def test_restrict_and_prolong_parity(f32, layout, grid):
+    p = problem(grid, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(2)
     dt = torch.float32 if f32 else torch.float64
@@ -158,10 +164,11 @@ def test_restrict_and_prolong_parity(f32, layout):
             assert relerr(host(zt), zf + mg.prolong(Lf, Lc, ec)) <= (1e-6 if f32 else 1e-15), l
 
 
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_coarse_solve_and_vcycle_parity(f32, layout):
-    p = problem(RAGGED, 0.001)
+def test_coarse_solve_and_vcycle_parity(f32, layout, grid):
+    p = problem(grid, 0.001)
     lv = _hier(p)
     rng = np.random.default_rng(3)
     dt = torch.float32 if f32 else torch.float64
@@ -209,12 +216,13 @@ def test_mixed_ir_matches_oracle():
     assert relerr(host(x), xref) <= 1e-9
 
 
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
-def test_layouts_give_the_same_solve(mode):
-    """Natural and red-black split storage of the finest level: both solves meet the bar against
-    the oracle, and agree with each other to solver accuracy."""
-    p = problem(RAGGED, 0.001)
-    b, xref = reference(RAGGED, 0.001, 1, 2)
+def test_layouts_give_the_same_solve(mode, grid):
+    """Natural and red-black split storage (the finest level; on the deeper grid level 1 too):
+    both solves meet the bar against the oracle, and agree with each other to solver accuracy."""
+    p = problem(grid, 0.001)
+    b, xref = reference(grid, 0.001, 1, 2)
     m = hp.MODE_MIXED_IR if mode == "mixed" else hp.MODE_FP64_MGPCG
     xs = {}
     for layout in LAYOUTS:
