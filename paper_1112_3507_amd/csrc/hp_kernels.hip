@@ -1887,94 +1887,94 @@ static bool transfer_zm(const Transfer& t) {
 }
 
 // Red-only restriction from a split fine level (the residual after a zero-guess pre-smoothing
-// vanishes on black cells): the thread and plane structure of k_restrict_zm<T, true, true>, with
-// the red entries of the next two fine planes loaded while the current coarse plane is summed
-// and the coarse-plane loop unrolled by two, so that the loaded records alternate by renaming.
+// vanishes on black cells): one thread per coarse column (I, J), 64 consecutive I per wave, one
+// coarse row per wave, a chunk of coarse planes per workgroup. Each fine plane's ten fine rows
+// under the workgroup's four coarse rows are loaded once (a few rows per wave), weighted in x
+// (neighbour cells from the adjacent lanes) and put in LDS, where each coarse row sums its four
+// rows with the y weights; the x-y sums u(k) of the fine planes then combine in z, each reused
+// by the two coarse planes it feeds. The next fine plane's red entries are loaded while the
+// current one is summed. The weights and their order are those of k_restrict_zm.
 template <typename T, bool CSPLIT>
 __global__ __launch_bounds__(kBlock) void k_restrict_red(Transfer t, ZTiles zt, const T* __restrict__ fine,
                                                          T* __restrict__ coarse) {
+    constexpr int NR = 10;            // fine rows under four coarse rows
+    __shared__ T sx[2][NR][64];       // [slot][fine row 2 J0 - 1 + r][lane]: x-weighted sums
     int bx, by, bz;
     ztile(zt, bx, by, bz);
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int I = bx * 64 + lane;
-    const int J = by * 4 + (threadIdx.x >> 6);
+    const int J0 = by * 4, J = J0 + w;
     const bool valid = I < t.ncx && J < t.ncy;
-    const int Ic = valid ? I : t.ncx - 1, Jc = J < t.ncy ? J : t.ncy - 1;
+    const int Ic = I < t.ncx ? I : t.ncx - 1, Jc = J < t.ncy ? J : t.ncy - 1;
     const int K0 = bz * zt.kz, K1 = min(K0 + zt.kz, t.ncz);
     const int nfx = t.nfx, nfy = t.nfy, nfz = t.nfz;
     const int64_t sf = (int64_t)nfx * nfy;
     float wx[4], wy[4];
     rweights4(Ic, nfx, t.perx, wx);
     rweights4(Jc, nfy, t.pery, wy);
-    int row[4], jr[4];
+    // fine rows this wave loads: 2 J0 - 1 + w + 4 i (rows with w 0 are harmless)
+    int jr[3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        jr[q] = wrapi(2 * Jc - 1 + q, nfy);  // rows with w 0 are harmless
-        row[q] = jr[q] * nfx;
-    }
+    for (int i = 0; i < 3; ++i) jr[i] = wrapi(min(2 * J0 - 1 + w + 4 * i, 2 * J0 - 1 + NR - 1), nfy);
+    const int nri = w + 8 < NR ? 3 : 2;
     const int hl = wrapi(2 * Ic - 1, nfx) >> 1, hr = wrapi(2 * Ic + 2, nfx) >> 1;
     const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == t.ncx - 1);
-    // red entries of the four fine rows of one plane at half position Ic and, at a wave edge,
+    // red entries at half position Ic of this wave's rows of one fine plane and, at a wave edge,
     // the red outer neighbour (cell 2I-1 is red where the row parity is 1, cell 2I+2 where it is 0)
     struct Raw {
-        T c[4], e[4];
+        T c[3], e[3];
     };
-    auto load_plane = [&](int k, Raw& o) {
+    auto load_rows = [&](int k, Raw& o) {
         const T* base = fine + (int64_t)k * sf;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const T* rp = base + row[q];
-            const int pf = (jr[q] + k) & 1;
-            o.c[q] = rp[Ic];
-            o.e[q] = (pf ? edge_l : edge_r) ? rp[pf ? hl : hr] : T(0);
+        for (int i = 0; i < 3; ++i) {
+            o.c[i] = T(0);
+            o.e[i] = T(0);
+            if (i < nri) {
+                const T* rp = base + (int64_t)jr[i] * nfx;
+                const int pf = (jr[i] + k) & 1;
+                o.c[i] = rp[Ic];
+                o.e[i] = (pf ? edge_l : edge_r) ? rp[pf ? hl : hr] : T(0);
+            }
         }
     };
-    // weighted x-y sum of fine plane k
-    auto plane_sum = [&](int k, const Raw& o) -> T {
+    // x-y weighted sum of fine plane k from the entries in cur; loads plane kn into nxt
+    auto fstep = [&](int k, int kn, int sl, const Raw& cur, Raw& nxt) -> T {
+        load_rows(kn, nxt);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (i < nri) {
+                const int pf = (jr[i] + k) & 1;
+                const T v = cur.c[i];
+                const T f0 = pf ? T(0) : v, f1 = pf ? v : T(0);
+                T left = __shfl_up(f1, 1, 64), right = __shfl_down(f0, 1, 64);
+                if (edge_l) left = pf ? cur.e[i] : T(0);
+                if (edge_r) right = pf ? T(0) : cur.e[i];
+                sx[sl][w + 4 * i][lane] = (T)wx[0] * left + (T)wx[1] * f0 + (T)wx[2] * f1 + (T)wx[3] * right;
+            }
+        }
+        __syncthreads();
         T u = T(0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int pf = (jr[q] + k) & 1;
-            const T v = o.c[q];
-            const T f0 = pf ? T(0) : v, f1 = pf ? v : T(0);
-            T left = __shfl_up(f1, 1, 64), right = __shfl_down(f0, 1, 64);
-            if (edge_l) left = pf ? o.e[q] : T(0);
-            if (edge_r) right = pf ? T(0) : o.e[q];
-            u += (T)wy[q] * ((T)wx[0] * left + (T)wx[1] * f0 + (T)wx[2] * f1 + (T)wx[3] * right);
-        }
+        for (int q = 0; q < 4; ++q) u += (T)wy[q] * sx[sl][min(2 * w + q, NR - 1)][lane];
         return u;
     };
-    // u of fine planes 2K0-1 and 2K0; plane indices wrap, so a missing Neumann plane reads a
-    // valid plane that then gets weight 0
-    T u0, u1;
-    {
-        Raw a, b;
-        const int ka = wrapi(2 * K0 - 1, nfz), kb = wrapi(2 * K0, nfz);
-        load_plane(ka, a);
-        load_plane(kb, b);
-        u0 = plane_sum(ka, a);
-        u1 = plane_sum(kb, b);
-    }
-    auto cstep = [&](int K, const Raw& p0, const Raw& p1, Raw& n0, Raw& n1) {
-        const int Kn = min(K + 1, K1 - 1);
-        load_plane(wrapi(2 * Kn + 1, nfz), n0);
-        load_plane(wrapi(2 * Kn + 2, nfz), n1);
-        float w[4];
-        rweights4(K, nfz, t.perz, w);
-        const T u2 = plane_sum(wrapi(2 * K + 1, nfz), p0);
-        const T u3 = plane_sum(wrapi(2 * K + 2, nfz), p1);
+    // fine planes 2 K0 - 1, 2 K0, 2 K0 + 1, ... (indices wrap, so a missing Neumann plane reads a
+    // valid plane that then gets weight 0)
+    Raw A, B;
+    load_rows(wrapi(2 * K0 - 1, nfz), A);
+    T u0 = fstep(wrapi(2 * K0 - 1, nfz), wrapi(2 * K0, nfz), 0, A, B);
+    T u1 = fstep(wrapi(2 * K0, nfz), wrapi(2 * K0 + 1, nfz), 1, B, A);
+    for (int K = K0; K < K1; ++K) {
+        const T u2 = fstep(wrapi(2 * K + 1, nfz), wrapi(2 * K + 2, nfz), 0, A, B);
+        const T u3 = fstep(wrapi(2 * K + 2, nfz), wrapi(min(2 * K + 3, 2 * nfz - 1), nfz), 1, B, A);
+        float wz[4];
+        rweights4(K, nfz, t.perz, wz);
         if (valid)
-            coarse[coarse_idx<CSPLIT>(t, I, J, K)] = (T)w[0] * u0 + (T)w[1] * u1 + (T)w[2] * u2 + (T)w[3] * u3;
+            coarse[coarse_idx<CSPLIT>(t, I, J, K)] = (T)wz[0] * u0 + (T)wz[1] * u1 + (T)wz[2] * u2 + (T)wz[3] * u3;
         // the next coarse plane starts at fine plane 2K+1
         u0 = u2;
         u1 = u3;
-    };
-    Raw A0, A1, B0, B1;
-    load_plane(wrapi(2 * K0 + 1, nfz), A0);
-    load_plane(wrapi(2 * K0 + 2, nfz), A1);
-    for (int K = K0; K < K1; K += 2) {
-        cstep(K, A0, A1, B0, B1);
-        if (K + 1 < K1) cstep(K + 1, B0, B1, A0, A1);
     }
 }
 
@@ -2124,75 +2124,84 @@ __global__ __launch_bounds__(kBlock) void k_prolong_zm(Transfer t, ZTiles zt,
 }
 
 // Red-only prolongation onto a split fine level (the following black half sweep overwrites the
-// black cells): the thread and plane structure of k_prolong_zm<T, true, true>, over fine planes
-// in pairs (one coarse plane each), with the coarse entries of the next coarse plane and the red
-// entries of the next two fine planes loaded a pair ahead, the pair loop unrolled by two.
+// black cells): the thread and plane structure of k_prolong_zm<T, true, true>, over fine planes in
+// pairs (one coarse plane each). The four coarse rows a workgroup's fine rows interpolate from
+// (with one column on either side of its 64) go through LDS, one entry per thread per coarse
+// plane, loaded a pair of fine planes ahead like the fine red entries; the pair loop is unrolled
+// by two so that the loaded records alternate by renaming.
 template <typename T, bool CSPLIT>
 __global__ __launch_bounds__(kBlock) void k_prolong_red(Transfer t, ZTiles zt, const T* __restrict__ coarse,
                                                         T* __restrict__ fine) {
+    __shared__ T ce[2][4][66];  // [slot][coarse row 2 by - 1 + r][column I0 - 1 + l]
     int bx, by, bz;
     ztile(zt, bx, by, bz);
-    const int lane = threadIdx.x & 63;
-    const int I = bx * 64 + lane;
-    const int j = by * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int I0 = bx * 64;
+    const int I = I0 + lane;
+    const int j = by * 4 + w;
     const bool valid = I < t.ncx && j < t.nfy;
     const int Ic = I < t.ncx ? I : t.ncx - 1, jc = j < t.nfy ? j : t.nfy - 1;
     const int k0 = bz * zt.kz, k1 = min(k0 + zt.kz, t.nfz);  // k0 even
     const int ncx = t.ncx, ncy = t.ncy, ncz = t.ncz;
-    const int64_t sc = (int64_t)ncx * ncy;
     // x neighbours of the parent column (mirror onto the parent at a Neumann end)
-    const int xm = Ic > 0 ? Ic - 1 : (t.perx ? ncx - 1 : Ic);
-    const int xp = Ic < ncx - 1 ? Ic + 1 : (t.perx ? 0 : Ic);
-    // y: parent row and second row
+    auto xmo = [&](int c) { return c > 0 ? c - 1 : (t.perx ? ncx - 1 : c); };
+    auto xpo = [&](int c) { return c < ncx - 1 ? c + 1 : (t.perx ? 0 : c); };
+    const int xm = xmo(Ic), xp = xpo(Ic);
+    // y: parent row and second row, as rows 0 .. 3 of the workgroup's coarse rows 2 by - 1 + r
     const int J = jc >> 1;
-    int J2 = (jc & 1) ? J + 1 : J - 1;
-    if (J2 < 0 || J2 >= ncy) J2 = t.pery ? (J2 + ncy) % ncy : J;
-    const int rowJ = J * ncx, rowJ2 = J2 * ncx;
-    const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == ncx - 1);
-    // coarse entries of one coarse plane: parent and second row at Ic, and the outer columns at a
-    // wave edge
-    struct Raw {
-        T c0, c1, l0, l1, r0, r1;
-    };
-    auto load_raw = [&](int K, Raw& o) {
-        o.c0 = coarse[coarse_idx<CSPLIT>(t, Ic, J, K)];
-        o.c1 = coarse[coarse_idx<CSPLIT>(t, Ic, J2, K)];
-        o.l0 = edge_l ? coarse[coarse_idx<CSPLIT>(t, xm, J, K)] : T(0);
-        o.l1 = edge_l ? coarse[coarse_idx<CSPLIT>(t, xm, J2, K)] : T(0);
-        o.r0 = edge_r ? coarse[coarse_idx<CSPLIT>(t, xp, J, K)] : T(0);
-        o.r1 = edge_r ? coarse[coarse_idx<CSPLIT>(t, xp, J2, K)] : T(0);
-    };
-    // v(K) for the two fine columns
-    auto vplane = [&](const Raw& o, T& vlo, T& vhi) {
-        const T cy = T(0.75) * o.c0 + T(0.25) * o.c1;
-        T cl = __shfl_up(cy, 1, 64), cr = __shfl_down(cy, 1, 64);
-        if (edge_l) cl = T(0.75) * o.l0 + T(0.25) * o.l1;
-        if (edge_r) cr = T(0.75) * o.r0 + T(0.25) * o.r1;
-        vlo = T(0.75) * cy + T(0.25) * cl;
-        vhi = T(0.75) * cy + T(0.25) * cr;
-    };
+    const int dj = (jc & 1) ? 1 : -1;
+    const bool has2 = (J + dj >= 0 && J + dj < ncy) || t.pery;
+    const int J2 = has2 ? (J + dj + ncy) % ncy : J;
+    const int rJ = min(max(J - (2 * by - 1), 0), 3), rJ2 = min(max(has2 ? rJ + dj : rJ, 0), 3);
+    // coarse row of LDS row w (the rows that no fine row of the workgroup uses get any valid row)
+    int Jw = 2 * by - 1 + w;
+    Jw = Jw < 0 ? (t.pery ? Jw + ncy : 0) : (Jw >= ncy ? (t.pery ? Jw - ncy : ncy - 1) : Jw);
+    // LDS columns of the parent column and of its neighbours; edge columns 0 and 65 hold xm(I0)
+    // and xp of the last column of the tile
+    const int Ilast = min(I0 + 63, ncx - 1);
+    const int lc = Ic - I0 + 1;
+    const int ll = Ic > I0 ? Ic - I0 : 0;
+    const int lr = Ic < Ilast ? Ic - I0 + 2 : 65;
+    const int edge = lane == 0 ? xmo(I0) : (lane == 1 ? xpo(Ilast) : -1);  // edge column this lane loads
+    auto cv = [&](int Ix, int Jy, int K) { return coarse[coarse_idx<CSPLIT>(t, Ix, Jy, K)]; };
     auto zm = [&](int K) { return K > 0 ? K - 1 : (t.perz ? ncz - 1 : K); };
     auto zp = [&](int K) { return K < ncz - 1 ? K + 1 : (t.perz ? 0 : K); };
     // the red entry of fine plane k at half position Ic
     auto zat = [&](int k) -> T* { return fine + ((int64_t)k * t.nfy + jc) * t.nfx + Ic; };
+    // v(K) for the two fine columns straight from memory (start of the march)
+    auto vmem = [&](int K, T& vlo, T& vhi) {
+        const T cy = T(0.75) * cv(Ic, J, K) + T(0.25) * cv(Ic, J2, K);
+        const T cl = T(0.75) * cv(xm, J, K) + T(0.25) * cv(xm, J2, K);
+        const T cr = T(0.75) * cv(xp, J, K) + T(0.25) * cv(xp, J2, K);
+        vlo = T(0.75) * cy + T(0.25) * cl;
+        vhi = T(0.75) * cy + T(0.25) * cr;
+    };
+    // one coarse plane's entries of this thread: its LDS entry and, for lanes 0 and 1, an edge
+    struct Raw {
+        T c, e;
+    };
+    auto load_raw = [&](int K, Raw& o) {
+        o.c = cv(min(I, ncx - 1), Jw, K);
+        o.e = edge >= 0 ? cv(edge, Jw, K) : T(0);
+    };
     T mlo, mhi, clo, chi;
-    {
-        Raw a, b;
-        const int K = k0 >> 1;
-        load_raw(zm(K), a);
-        load_raw(K, b);
-        vplane(a, mlo, mhi);
-        vplane(b, clo, chi);
-    }
+    vmem(zm(k0 >> 1), mlo, mhi);
+    vmem(k0 >> 1, clo, chi);
     // fine planes k, k+1 of coarse plane K = k/2: the lower one takes the plane below (m), the
     // upper one the plane above (n, from the entries loaded a pair earlier)
     auto pstep = [&](int k, const Raw& rn, Raw& rnn, const T& z0, const T& z1, T& z0n, T& z1n) {
         const int K = k >> 1;
+        const int sl = K & 1;
+        ce[sl][w][lane + 1] = rn.c;
+        if (edge >= 0) ce[sl][w][lane == 0 ? 0 : 65] = rn.e;
+        __syncthreads();
         load_raw(zp(min(K + 1, ncz - 1)), rnn);
         z0n = *zat(min(k + 2, k1 - 1));
         z1n = *zat(min(k + 3, k1 - 1));
-        T nlo, nhi;
-        vplane(rn, nlo, nhi);
+        const T cy = T(0.75) * ce[sl][rJ][lc] + T(0.25) * ce[sl][rJ2][lc];
+        const T cl = T(0.75) * ce[sl][rJ][ll] + T(0.25) * ce[sl][rJ2][ll];
+        const T cr = T(0.75) * ce[sl][rJ][lr] + T(0.25) * ce[sl][rJ2][lr];
+        const T nlo = T(0.75) * cy + T(0.25) * cl, nhi = T(0.75) * cy + T(0.25) * cr;
         if (valid) {
             const int p = (jc + k) & 1;  // cell 2I of plane k has colour p; plane k+1 the other
             const T dlo0 = T(0.75) * clo + T(0.25) * mlo, dhi0 = T(0.75) * chi + T(0.25) * mhi;

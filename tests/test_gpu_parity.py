@@ -71,7 +71,7 @@ def reference(n, mach, seed, rhs_seed):
 
 
 RAGGED = (80, 24, 40)
-# 256 x 32 x 32: the split layout reaches level 1 (128 x 16 x 16, one wave per row) as well
+# 256 x 32 x 32: the split layout reaches levels 1 (128 x 16 x 16) and 2 (64 x 8 x 8) as well
 DEEP = (256, 32, 32)
 GRIDS = [RAGGED, DEEP]
 
