@@ -135,9 +135,10 @@ void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s)
 // deferred iterate update: r -= alpha q with ||r||^2 under rc; then x += alpha p and
 // p = z + beta p in one pass; x += alpha p alone where the iteration ends (alpha = scal[S_ALPHA])
 // (with g of a split finest level: in the tile order and direction of the split kernels)
+// (returns the number of per-workgroup partials of ||r||^2 it wrote)
 template <typename T>
-void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s,
-                      const Geo<T>* g = nullptr);
+int launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s,
+                     const Geo<T>* g = nullptr);
 template <typename T>
 void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s,
                    const Geo<T>* g = nullptr);
@@ -156,6 +157,9 @@ template <typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
 // flag nonzero if any entry is not finite
 void launch_check_finite(const double* x, int64_t n, int* bad, hipStream_t s);
+// natural -> split relayout of a solve's input with the finiteness check and, under rc, its norm
+void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* bad, const RedCtl& rc,
+                        hipStream_t s);
 
 // y = a x + b y
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);

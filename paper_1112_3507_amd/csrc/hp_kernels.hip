@@ -2260,6 +2260,39 @@ void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split,
                        to_split);
 }
 
+// Natural to split order for a caller's FP64 vector entering a solve, with the checks that go
+// with it in the same pass: any non-finite entry sets *bad, and with rc.op != OP_NONE the squared
+// norm is reduced under rc. Grid-stride over cell pairs with a bounded grid (one partial each).
+__global__ __launch_bounds__(kBlock) void k_relayout_in(const double* __restrict__ src, double* __restrict__ dst,
+                                                        int nx, int ny, int64_t npairs, int* bad,
+                                                        double* __restrict__ partials, int norm) {
+    const int hx = nx >> 1;
+    double acc = 0.0;
+    bool finite = true;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < npairs; q += (int64_t)gridDim.x * kBlock) {
+        const int64_t row = q / hx;
+        const int t = (int)(q - row * hx);
+        const int p = (int)((row % ny + row / ny) & 1);
+        const int64_t rb = row * nx;
+        const double v0 = src[rb + 2 * t], v1 = src[rb + 2 * t + 1];
+        dst[rb + p * hx + t] = v0;
+        dst[rb + (1 - p) * hx + t] = v1;
+        finite = finite && isfinite(v0) && isfinite(v1);
+        acc += v0 * v0 + v1 * v1;
+    }
+    if (!finite) atomicOr(bad, 1);
+    if (norm) block_partial(acc, partials);
+}
+
+void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* bad, const RedCtl& rc,
+                        hipStream_t s) {
+    const int64_t npairs = (int64_t)(nx >> 1) * ny * nz;
+    const int nb = vec_blocks(2 * npairs);
+    hipLaunchKernelGGL(k_relayout_in, dim3(nb), dim3(kBlock), 0, s, src, dst, nx, ny, npairs, bad, rc.partials,
+                       rc.op != OP_NONE ? 1 : 0);
+    finalize(rc, nb, s);
+}
+
 bool split_layout_ok(int nx, int ny, int nz, const Transfer* t) {
     return use_zm(nx, ny, nz) && (nx % 2 == 0) && (ny % kRowsS == 0) && t && transfer_zm(*t);
 }
@@ -2441,7 +2474,7 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_xpby_x_zs(ZTiles zt, int n
 }
 
 template <typename T>
-void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s, const Geo<T>* g) {
+int launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s, const Geo<T>* g) {
     if (g && g->split) {
         ZTiles zt = split_tiles(g->nx >> 1, g->ny, g->nz);
         zt.rev = g->rev;
@@ -2453,10 +2486,11 @@ void launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t
             hipLaunchKernelGGL((k_axpy_norm_zs<T, 2>), dim3(nb), split_block(g->nx >> 1), 0, s, zt, g->nx, g->ny,
                                g->nz, r, q, rc);
         finalize(rc, nb, s);
-        return;
+        return nb;
     }
     hipLaunchKernelGGL((k_axpy_norm<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, r, q, n, rc);
     finalize(rc, vec_blocks(n), s);
+    return vec_blocks(n);
 }
 
 template <typename T>
@@ -2627,7 +2661,7 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
     template void launch_dot<T>(const T*, const T*, int64_t, const RedCtl&, hipStream_t);       \
     template void launch_axpy2_norm<T>(T*, const T*, T*, const T*, int64_t, const RedCtl&,      \
                                        hipStream_t);                                            \
-    template void launch_axpy_norm<T>(T*, const T*, int64_t, const RedCtl&, hipStream_t,        \
+    template int launch_axpy_norm<T>(T*, const T*, int64_t, const RedCtl&, hipStream_t,         \
                                       const Geo<T>*);                                             \
     template void launch_xpby_x<T>(const T*, T*, T*, int64_t, const double*, hipStream_t,       \
                                    const Geo<T>*);                                                \

@@ -87,6 +87,8 @@ struct hp_handle {
     int* flag = nullptr;
     int64_t partial_cap = 0;
     double* host_scal = nullptr;  // pinned mirror of scal
+    double* host_part = nullptr;  // pinned mirror of the partials of the CG residual norm
+    int host_nparts = 0;          // how many of them the last post_scalars copied
     int* host_flag = nullptr;     // pinned
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_scal = nullptr;  // marks the copy of scal into host_scal
@@ -486,13 +488,25 @@ int read_scalars(hp_handle* H) {
 }
 
 // Split form of read_scalars: post_scalars enqueues the copy of the device scalars as they stand
-// at this point of the stream, later work may be enqueued behind it, and wait_scalars blocks
-// only until the copy itself has landed.
-int post_scalars(hp_handle* H) {
+// at this point of the stream, with the first nparts reduction partials (those of the CG residual
+// norm, summed on the host: no second reduction stage on the GPU), later work may be enqueued
+// behind it, and wait_scalars blocks only until the copy itself has landed.
+int post_scalars(hp_handle* H, int nparts) {
     HIPCHK(hipMemcpyAsync(H->host_scal, H->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                           H->stream));
+    if (nparts > 0)
+        HIPCHK(hipMemcpyAsync(H->host_part, H->partials, nparts * sizeof(double), hipMemcpyDeviceToHost,
+                              H->stream));
+    H->host_nparts = nparts;
     HIPCHK(hipEventRecord(H->ev_scal, H->stream));
     return HP_OK;
+}
+
+// ||r||^2 from the partials of the last post_scalars, in workgroup order
+double host_rr(const hp_handle* H) {
+    double s = 0.0;
+    for (int i = 0; i < H->host_nparts; ++i) s += H->host_part[i];
+    return s;
 }
 
 int wait_scalars(hp_handle* H) {
@@ -565,9 +579,9 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         }
         // r -= alpha q now; x += alpha p is deferred to the next direction update (or the exit)
         const Geo<double> gn = geo_pass(H, g, 0);
-        launch_axpy_norm<double>(H->r, H->q, N, red(H, OP_STORE, S_RR), s, &gn);
+        const int np = launch_axpy_norm<double>(H->r, H->q, N, red(H, OP_NONE), s, &gn);
         CHK(check_launch());
-        CHK(post_scalars(H));
+        CHK(post_scalars(H, np));
         // the next direction only reads r and the scalars, so it may run ahead of the check
         const bool ahead = st.iterations + 1 < H->max_iter && look_ahead(rr_prev, ratio, target);
         if (ahead) next_direction64(H, x);
@@ -575,7 +589,7 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         CHK(wait_scalars(H));
         st.iterations++;
         if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
-        double rr = H->host_scal[S_RR];
+        double rr = host_rr(H);
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite residual in iteration %d", st.iterations);
         ratio = rr_prev > 0.0 ? rr / rr_prev : 1.0;
         rr_prev = rr;
@@ -639,16 +653,16 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
     while (*its < budget) {
         // r -= alpha q; x += alpha p is deferred to the next direction update (or the end)
         const Geo<float> gn = geo_pass(H, g, 0);
-        launch_axpy_norm<float>(H->r32, H->q32, N, red(H, OP_STORE, S_RR), s, &gn);
+        const int np = launch_axpy_norm<float>(H->r32, H->q32, N, red(H, OP_NONE), s, &gn);
         CHK(check_launch());
-        CHK(post_scalars(H));
+        CHK(post_scalars(H, np));
         ahead = *its + 1 < budget && look_ahead(rr_prev, ratio, eta);
         if (ahead) next_direction32(H);
         CHK(check_launch());
         CHK(wait_scalars(H));
         (*its)++;
         if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "inner CG breakdown");
-        double rr = H->host_scal[S_RR];
+        double rr = host_rr(H);
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite inner residual");
         ratio = rr_prev > 0.0 ? rr / rr_prev : 1.0;
         rr_prev = rr;
@@ -1035,6 +1049,7 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
         (rc = dalloc(H, &H->flag, 1)))
         return bail(rc);
     if (hipHostMalloc((void**)&H->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&H->host_part, cap * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&H->host_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(HP_ENOMEM, "pinned host allocation failed"));
     if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess ||
@@ -1055,6 +1070,7 @@ void hp_free(hp_handle* H) {
     else (void)hipDeviceSynchronize();
     for (void* p : H->allocs) (void)hipFree(p);
     if (H->host_scal) (void)hipHostFree(H->host_scal);
+    if (H->host_part) (void)hipHostFree(H->host_part);
     if (H->host_flag) (void)hipHostFree(H->host_flag);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
@@ -1157,16 +1173,18 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     HIPCHK(hipEventRecord(H->ev0, s));
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), s));
     HIPCHK(hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), s));
-    launch_check_finite(b, N, H->flag, s);
-    launch_check_finite(x, N, H->flag, s);
-    launch_dot<double>(b, b, N, red(H, OP_STORE, S_BB), s);
-    // in the split layout the solve runs on split copies of b and x; x is copied back at the end
+    // in the split layout the solve runs on split copies of b and x (made in the pass that checks
+    // them and takes ||b||); x is copied back at the end
     double* xu = x;
     if (F.split) {
-        relayout0<double>(H, b, H->bs, 1);
-        relayout0<double>(H, x, H->xs, 1);
+        launch_relayout_in(b, H->bs, F.n[0], F.n[1], F.n[2], H->flag, red(H, OP_STORE, S_BB), s);
+        launch_relayout_in(x, H->xs, F.n[0], F.n[1], F.n[2], H->flag, red(H, OP_NONE), s);
         b = H->bs;
         x = H->xs;
+    } else {
+        launch_check_finite(b, N, H->flag, s);
+        launch_check_finite(x, N, H->flag, s);
+        launch_dot<double>(b, b, N, red(H, OP_STORE, S_BB), s);
     }
     launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
     int rc = check_launch();
