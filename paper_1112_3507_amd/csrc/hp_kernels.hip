@@ -1625,6 +1625,27 @@ bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, con
     return true;
 }
 
+// Zero-guess pre-smoothing in one pass over the cells of a level too small for the z march:
+// red cells z = r dinv, black cells dinv (r + sum_f w_f (r dinv)_nb) (their neighbours are red).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_presmooth(Geo<T> g, const T* __restrict__ rho,
+                                                      const T* __restrict__ dinv, const T* __restrict__ r,
+                                                      T* __restrict__ z) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+    const int a = i + g.nx * (j + g.ny * k);
+    if (!((i + j + k) & 1)) {
+        z[a] = r[a] * dinv[a];
+        return;
+    }
+    const T ra = rho[a];
+    T swq = T(0);
+    for_faces(g, i, j, k, a, [&](int nb, T c) { swq += c * face_kappa(ra, rho[nb]) * (r[nb] * dinv[nb]); });
+    z[a] = (r[a] + swq) * dinv[a];
+}
+
 template <typename T>
 bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, T* z, hipStream_t s) {
     if (g.split) {
@@ -1633,7 +1654,11 @@ bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, 
         launch_presmooth_zs<T>(g, zt, rho, dinv, r, z, s);
         return true;
     }
-    if (!use_zm(g.nx, g.ny, g.nz)) return false;
+    if (!use_zm(g.nx, g.ny, g.nz)) {
+        const Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
+        hipLaunchKernelGGL((k_presmooth<T>), sh.grid, sh.block, 0, s, g, rho, dinv, r, z);
+        return true;
+    }
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
     zt.rev = g.rev;
     hipLaunchKernelGGL((k_presmooth_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt, rho,
