@@ -157,9 +157,10 @@ template <typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
 // flag nonzero if any entry is not finite
 void launch_check_finite(const double* x, int64_t n, int* bad, hipStream_t s);
-// natural -> split relayout of a solve's input with the finiteness check and, under rc, its norm
-void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* bad, const RedCtl& rc,
-                        hipStream_t s);
+// natural -> split relayout of a solve's input with the finiteness check (bit 0 of *flags), the
+// nonzero check (bits nzbit) and, under rc, its norm
+void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* flags, int nzbit,
+                        const RedCtl& rc, hipStream_t s);
 
 // y = a x + b y
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);

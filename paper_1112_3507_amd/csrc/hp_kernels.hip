@@ -2286,14 +2286,15 @@ void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split,
 }
 
 // Natural to split order for a caller's FP64 vector entering a solve, with the checks that go
-// with it in the same pass: any non-finite entry sets *bad, and with rc.op != OP_NONE the squared
-// norm is reduced under rc. Grid-stride over cell pairs with a bounded grid (one partial each).
+// with it in the same pass: any non-finite entry sets bit 0 of *flags, any nonzero entry the bits
+// nzbit, and with rc.op != OP_NONE the squared norm is reduced under rc. Grid-stride over cell
+// pairs with a bounded grid (one partial each).
 __global__ __launch_bounds__(kBlock) void k_relayout_in(const double* __restrict__ src, double* __restrict__ dst,
-                                                        int nx, int ny, int64_t npairs, int* bad,
+                                                        int nx, int ny, int64_t npairs, int* flags, int nzbit,
                                                         double* __restrict__ partials, int norm) {
     const int hx = nx >> 1;
     double acc = 0.0;
-    bool finite = true;
+    bool finite = true, nonzero = false;
     for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < npairs; q += (int64_t)gridDim.x * kBlock) {
         const int64_t row = q / hx;
         const int t = (int)(q - row * hx);
@@ -2303,18 +2304,20 @@ __global__ __launch_bounds__(kBlock) void k_relayout_in(const double* __restrict
         dst[rb + p * hx + t] = v0;
         dst[rb + (1 - p) * hx + t] = v1;
         finite = finite && isfinite(v0) && isfinite(v1);
+        nonzero = nonzero || v0 != 0.0 || v1 != 0.0;
         acc += v0 * v0 + v1 * v1;
     }
-    if (!finite) atomicOr(bad, 1);
+    if (!finite) atomicOr(flags, 1);
+    if (nonzero && nzbit) atomicOr(flags, nzbit);
     if (norm) block_partial(acc, partials);
 }
 
-void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* bad, const RedCtl& rc,
-                        hipStream_t s) {
+void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* flags, int nzbit,
+                        const RedCtl& rc, hipStream_t s) {
     const int64_t npairs = (int64_t)(nx >> 1) * ny * nz;
     const int nb = vec_blocks(2 * npairs);
-    hipLaunchKernelGGL(k_relayout_in, dim3(nb), dim3(kBlock), 0, s, src, dst, nx, ny, npairs, bad, rc.partials,
-                       rc.op != OP_NONE ? 1 : 0);
+    hipLaunchKernelGGL(k_relayout_in, dim3(nb), dim3(kBlock), 0, s, src, dst, nx, ny, npairs, flags, nzbit,
+                       rc.partials, rc.op != OP_NONE ? 1 : 0);
     finalize(rc, nb, s);
 }
 

@@ -1174,26 +1174,40 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), s));
     HIPCHK(hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), s));
     // in the split layout the solve runs on split copies of b and x (made in the pass that checks
-    // them and takes ||b||); x is copied back at the end
+    // them, takes ||b|| and notes whether x is zero); x is copied back at the end
     double* xu = x;
+    int rc;
     if (F.split) {
-        launch_relayout_in(b, H->bs, F.n[0], F.n[1], F.n[2], H->flag, red(H, OP_STORE, S_BB), s);
-        launch_relayout_in(x, H->xs, F.n[0], F.n[1], F.n[2], H->flag, red(H, OP_NONE), s);
+        launch_relayout_in(b, H->bs, F.n[0], F.n[1], F.n[2], H->flag, 0, red(H, OP_STORE, S_BB), s);
+        launch_relayout_in(x, H->xs, F.n[0], F.n[1], F.n[2], H->flag, 2, red(H, OP_NONE), s);
         b = H->bs;
         x = H->xs;
+        if ((rc = check_launch())) return rc;
+        HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        if ((rc = read_scalars(H))) return rc;
+        if (*H->host_flag & 1) {
+            st.status = HP_ENAN;
+            return fail(HP_ENAN, "rhs or initial guess contains non-finite values");
+        }
+        if (*H->host_flag & 2) {
+            launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
+            if ((rc = check_launch()) || (rc = read_scalars(H))) return rc;
+        } else {  // x = 0: the initial residual is b itself
+            launch_copy<double>(b, H->r, N, s);
+            H->host_scal[S_RR] = H->host_scal[S_BB];
+        }
     } else {
         launch_check_finite(b, N, H->flag, s);
         launch_check_finite(x, N, H->flag, s);
         launch_dot<double>(b, b, N, red(H, OP_STORE, S_BB), s);
-    }
-    launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
-    int rc = check_launch();
-    if (rc) return rc;
-    HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    if ((rc = read_scalars(H))) return rc;
-    if (*H->host_flag) {
-        st.status = HP_ENAN;
-        return fail(HP_ENAN, "rhs or initial guess contains non-finite values");
+        launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
+        if ((rc = check_launch())) return rc;
+        HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        if ((rc = read_scalars(H))) return rc;
+        if (*H->host_flag) {
+            st.status = HP_ENAN;
+            return fail(HP_ENAN, "rhs or initial guess contains non-finite values");
+        }
     }
     double bnorm = std::sqrt(H->host_scal[S_BB]);
     if (bnorm == 0.0) {
