@@ -84,11 +84,18 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
 template <typename T>
 void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
                  hipStream_t s);
-// red-black half sweep that also reduces <r, z> (all cells, final values) under rc;
-// returns false (and does nothing) when the level uses the small-grid kernels
+// red-black half sweep that also reduces <r, z> (all cells, final values) under rc; in the split
+// layout the preceding sweep of the other colour (launch_rbgs_own_dot) reduced its own cells into
+// the nb2 entries of partials2, which the second stage adds; returns false (and does nothing) when
+// the level uses the small-grid kernels
 template <typename T>
 bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
-                     const RedCtl& rc, hipStream_t s);
+                     const RedCtl& rc, hipStream_t s, const double* partials2 = nullptr, int nb2 = 0);
+// split layout: half sweep of `colour` reducing <r, z> over its own cells into partials (no
+// second stage); returns the number of partials
+template <typename T>
+int launch_rbgs_own_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
+                        double* partials, hipStream_t s);
 // t = r - A z on red cells (valid right after a black half sweep, when the residual vanishes on
 // black cells); black cells of t are set to 0 in the natural layout and left unwritten in the
 // split layout. zero_guess: z is the one-pass zero-guess pre-smoothing (red values r dinv), so

@@ -80,10 +80,12 @@ __device__ void block_partial(double v, double* partials) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int nb,
+                                                     const double* __restrict__ partials2, int nb2,
                                                      double* __restrict__ sc, int op, int slot) {
     const int tid = threadIdx.x;
     double acc = 0.0;
     for (int b = tid; b < nb; b += kBlock) acc += partials[b];
+    for (int b = tid; b < nb2; b += kBlock) acc += partials2[b];
     double tot = block_sum(acc);
     if (tid != 0) return;
     switch (op) {
@@ -109,10 +111,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
     }
 }
 
-static void finalize(const RedCtl& rc, int nb, hipStream_t s) {
+// second stage over nb partials (and, for a reduction split over two launches, nb2 more)
+static void finalize(const RedCtl& rc, int nb, hipStream_t s, const double* partials2 = nullptr, int nb2 = 0) {
     if (rc.op == OP_NONE) return;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, rc.partials, nb, rc.scal, rc.op,
-                       rc.slot);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, rc.partials, nb, partials2, nb2, rc.scal,
+                       rc.op, rc.slot);
 }
 
 // Launch shape over cells: 256-thread 3D workgroups sized to the level.
@@ -927,7 +930,8 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_apply_zs(Geo<T> g, ZTiles 
 // t (the pair partner) and t-1 or t+1, y neighbours at t in rows j-1 and j+1, z neighbours at t
 // in the planes below and above; the other colour's z and rho at t of planes k-1 .. k+2 form the
 // register ring, and those of the current plane are exchanged through LDS for the x and y
-// neighbours. DOT also reduces <r, z> over both colours; RESID instead writes t = r - A z on the
+// neighbours. DOT also reduces <r, z> over the cells of colour c (the black and the red sweep of a
+// post-smoothing reduce half each); RESID instead writes t = r - A z on the
 // cells of colour c only. ZG (with RESID, colour red): z holds the zero-guess pre-smoothing,
 // whose red values are r dinv, so r - (m + sum w) z vanishes on red cells and t = sum_f w_f z_nb
 // (r and m are not read).
@@ -955,9 +959,9 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles z
     // halo items: 2 rows x (z, rho) x kTW columns of the other colour
     constexpr int HI = 4 * kTW, NH = (HI + kBlockS - 1) / kBlockS;
     // what a plane contributes besides the other colour's column: this colour's rho, r and m,
-    // the outer x neighbour where memory supplies it, r of the other colour (DOT), halo entries
+    // the outer x neighbour where memory supplies it, halo entries
     struct Own {
-        T ra, rr, mm, zx, rx, ror;
+        T ra, rr, mm, zx, rx;
         T h[NH];
     };
     auto load_own = [&](int kp, Own& o) {
@@ -972,7 +976,6 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles z
             o.zx = gxp ? z[rbp + oh + txp] : T(0);
             o.rx = gxp ? rho[rbp + oh + txp] : T(0);
         }
-        o.ror = DOT ? r[rbp + oh + t] : T(0);
 #pragma unroll
         for (int n = 0; n < NH; ++n) {
             const int i = threadIdx.x + n * kBlockS;
@@ -1045,7 +1048,7 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles z
             } else {
                 const T znew = (c.rr + swz) / (c.mm + sw);
                 z[rb + ch + t] = znew;
-                if (DOT) dsum += (double)c.rr * (double)znew + (double)c.ror * (double)zoc;
+                if (DOT) dsum += (double)c.rr * (double)znew;
             }
         }
     };
@@ -1686,15 +1689,26 @@ void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, in
     hipLaunchKernelGGL((k_rbgs<T>), sh.grid, sh.block, 0, s, g, rho, m, r, z, colour);
 }
 
+// Split layout: the half sweep of `colour` reducing <r, z> over its own cells into partials
+// (no second stage); returns the number of partials.
+template <typename T>
+int launch_rbgs_own_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
+                        double* partials, hipStream_t s) {
+    ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
+    zt.rev = g.rev;
+    launch_rbgs_zs<T, true, false, false>(g, zt, rho, m, r, z, colour, partials, nullptr, s);
+    return zt.tx * zt.ty * zt.tz;
+}
+
+// The last half sweep of a post-smoothing with <r, z> over every cell: in the split layout the
+// earlier (other-colour) sweep left nb2 partials of its own cells in partials2; otherwise the
+// z-march sweep reduces both colours itself.
 template <typename T>
 bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, int colour,
-                     const RedCtl& rc, hipStream_t s) {
+                     const RedCtl& rc, hipStream_t s, const double* partials2, int nb2) {
     if (g.split) {
-        ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
-        zt.rev = g.rev;
-        const int nb = zt.tx * zt.ty * zt.tz;
-        launch_rbgs_zs<T, true, false, false>(g, zt, rho, m, r, z, colour, rc.partials, nullptr, s);
-        finalize(rc, nb, s);
+        const int nb = launch_rbgs_own_dot<T>(g, rho, m, r, z, colour, rc.partials, s);
+        finalize(rc, nb, s, partials2, nb2);
         return true;
     }
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
@@ -2676,8 +2690,10 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
                                  hipStream_t);                                                  \
     template void launch_rbgs_zero<T>(const Geo<T>&, const T*, const T*, const T*, T*,          \
                                       hipStream_t);                                             \
+    template int launch_rbgs_own_dot<T>(const Geo<T>&, const T*, const T*, const T*, T*, int,      \
+                                        double*, hipStream_t);                                     \
     template bool launch_rbgs_dot<T>(const Geo<T>&, const T*, const T*, const T*, T*, int,      \
-                                     const RedCtl&, hipStream_t);                               \
+                                     const RedCtl&, hipStream_t, const double*, int);           \
     template bool launch_presmooth<T>(const Geo<T>&, const T*, const T*, const T*, T*,          \
                                       hipStream_t);                                             \
     template bool launch_resid_red<T>(const Geo<T>&, const T*, const T*, const T*, const T*, T*, \

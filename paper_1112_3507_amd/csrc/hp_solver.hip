@@ -84,6 +84,7 @@ struct hp_handle {
     double *bs = nullptr, *xs = nullptr, *rho_nat = nullptr, *m_nat = nullptr;
     double* scal = nullptr;
     double* partials = nullptr;
+    double* partials2 = nullptr;  // the first half of a reduction split over two launches
     int* flag = nullptr;
     int64_t partial_cap = 0;
     double* host_scal = nullptr;  // pinned mirror of scal
@@ -467,12 +468,19 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
     launch_prolong_add<T>(tr, lvl_z<T>(C), z, s, true);
     for (int it = 0; it < H->nu_post; ++it) {
         const bool timed = (l == 0 && sizeof(T) == 8);
+        const bool last_dot = dot && it == H->nu_post - 1;
+        // with <r, z> wanted in the split layout the black sweep reduces its own cells, the red
+        // sweep the rest
+        int nb2 = 0;
         if (timed) time_begin(H, TIME_SWEEP);
-        launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 1, s);
+        if (last_dot && g.split)
+            nb2 = launch_rbgs_own_dot<T>(geo_pass(H, g, l), rho, m, r, z, 1, H->partials2, s);
+        else
+            launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 1, s);
         if (timed) time_end(H);
-        if (dot && it == H->nu_post - 1) {
+        if (last_dot) {
             const Geo<T> gd = geo_pass(H, g, l);
-            return launch_rbgs_dot<T>(gd, rho, m, r, z, 0, *dot, s) ||
+            return launch_rbgs_dot<T>(gd, rho, m, r, z, 0, *dot, s, H->partials2, nb2) ||
                    (launch_rbgs<T>(gd, rho, m, r, z, 0, s), false);
         }
         launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 0, s);
@@ -1045,7 +1053,8 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
     for (auto& L : H->lv)
         cap = std::max(cap, reduce_blocks_cells(L.n[0], L.n[1], L.n[2]));
     H->partial_cap = cap;
-    if ((rc = dalloc(H, &H->partials, cap)) || (rc = dalloc(H, &H->scal, S_COUNT)) ||
+    if ((rc = dalloc(H, &H->partials, cap)) || (rc = dalloc(H, &H->partials2, cap)) ||
+        (rc = dalloc(H, &H->scal, S_COUNT)) ||
         (rc = dalloc(H, &H->flag, 1)))
         return bail(rc);
     if (hipHostMalloc((void**)&H->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
