@@ -39,6 +39,7 @@ struct RedCtl {
     double* scal;            // device scalar slots
     int op;
     int slot;
+    double* flag_out = nullptr;  // r -= alpha q only: where workgroup 0 copies the breakdown flag
 };
 
 // Geometry of one level as seen by a kernel. wx/wy/wz = dt^2 / h^2 per axis.

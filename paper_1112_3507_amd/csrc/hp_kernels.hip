@@ -676,23 +676,30 @@ struct SplitCol {
 // rotate by renaming: a register move at the loop end would wait for loads still in flight.
 static_assert(kRowsS >= 2, "the split kernels need separate first and last rows");
 
-#ifndef HP_ZS_WG
-#define HP_ZS_WG 0
+#ifndef HP_ZS_WG1
+#define HP_ZS_WG1 0
+#endif
+#ifndef HP_ZS_WG2
+#define HP_ZS_WG2 768
 #endif
 // Tiles of the split kernels over hx = nx/2 half positions: 64 XW per tile, kRowsS rows, z chunks
-// of at least HP_ZMIN planes, about 8192 waves in all.
+// of at least HP_ZMIN planes.  Two-wave rows (the finest level of 256^3 and up) take about
+// HP_ZS_WG2 workgroups, three per CU: at 256^3 the operator apply and the half sweeps ran
+// 2-4% faster with 768 than with 1024, and 10-20% slower with counts that do not split evenly
+// over the 32 CUs of an XCD (640, 704, 832, 896, 1152).  One-wave rows aim for about 8192 waves.
 static ZTiles split_tiles(int hx, int ny, int nz) {
     const int xw = split_xw(hx), tw = 64 * xw;
     ZTiles t;
     t.tx = (hx + tw - 1) / tw;
     t.ty = (ny + kRowsS - 1) / kRowsS;
     const int cols = t.tx * t.ty;
-    const int target = HP_ZS_WG > 0 ? HP_ZS_WG : 8192 / (xw * kRowsS);
+    const int wg = xw == 2 ? HP_ZS_WG2 : HP_ZS_WG1;
     t.kz = nz;
-    if (HP_ZS_WG > 0) {
-        const int want = std::max(1, std::min(nz, (target + cols / 2) / cols));
-        t.kz = (nz + want - 1) / want;
+    if (wg > 0) {
+        const int want = std::max(1, std::min(nz, (wg + cols / 2) / cols));
+        t.kz = std::max((nz + want - 1) / want, std::min(HP_ZMIN, nz));
     } else {
+        const int target = 8192 / (xw * kRowsS);
         while (t.kz > HP_ZMIN && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < target) t.kz = (t.kz + 1) / 2;
     }
     t.tz = (nz + t.kz - 1) / t.kz;
@@ -2421,6 +2428,13 @@ void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s)
                        s, z, p, n, scal);
 }
 
+// The host reads the residual-norm partials of r -= alpha q and the breakdown flag as they stand
+// when that kernel runs; with rc.partials and rc.flag_out in mapped pinned host memory the two
+// kernels below deliver both themselves (no copy launch behind them).
+__device__ __forceinline__ void export_flag(const RedCtl& rc) {
+    if (rc.flag_out && flat_bid() == 0 && flat_tid() == 0) rc.flag_out[0] = rc.scal[S_FLAG];
+}
+
 // The CG iterate update deferred by one iteration: r -= alpha q with ||r||^2 first, then
 // x += alpha p together with the next direction p = z + beta p (p is read once for both).
 template <typename T>
@@ -2435,6 +2449,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy_norm(T* __restrict__ r, const T
         acc += (double)ra * (double)ra;
     }
     block_partial(acc, rc.partials);
+    export_flag(rc);
 }
 
 // The same two updates over a split finest level in the tile order of the split kernels (and in
@@ -2476,6 +2491,7 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_axpy_norm_zs(ZTiles zt, in
         }
     }
     block_partial(acc, rc.partials);
+    export_flag(rc);
 }
 
 template <typename T, int XW>

@@ -88,8 +88,11 @@ struct hp_handle {
     int* flag = nullptr;
     int64_t partial_cap = 0;
     double* host_scal = nullptr;  // pinned mirror of scal
-    double* host_part = nullptr;  // pinned mirror of the partials of the CG residual norm
-    int host_nparts = 0;          // how many of them the last post_scalars copied
+    // partials of the CG residual norm and, after the last possible one (partial_cap), the
+    // breakdown flag, written by the r -= alpha q kernel itself into mapped pinned host memory
+    double* host_part = nullptr;
+    double* dev_part = nullptr;   // the device's address of host_part
+    int host_nparts = 0;          // how many partials the last r -= alpha q wrote
     int* host_flag = nullptr;     // pinned
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_scal = nullptr;  // marks the copy of scal into host_scal
@@ -187,10 +190,13 @@ int check_launch() {
 // ---- kernel timing (HP_OPT_KERNEL_TIMING) ----
 enum { TIME_SWEEP = 0, TIME_APPLY = 1 };
 
+// Timing events only take time stamps (the host reads no memory behind them), so they are
+// created without the system-scope release and acquire that a default event carries: that
+// fence's write-back is no part of the launch they bracket.
 hipEvent_t timing_event(hp_handle* H) {
     if (H->tev_used == H->tev.size()) {
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         H->tev.push_back(e);
     }
     return H->tev[H->tev_used++];
@@ -495,22 +501,27 @@ int read_scalars(hp_handle* H) {
     return HP_OK;
 }
 
-// Split form of read_scalars: post_scalars enqueues the copy of the device scalars as they stand
-// at this point of the stream, with the first nparts reduction partials (those of the CG residual
-// norm, summed on the host: no second reduction stage on the GPU), later work may be enqueued
-// behind it, and wait_scalars blocks only until the copy itself has landed.
+// What a CG loop hands to r -= alpha q: its workgroup partials of ||r||^2 (summed on the host: no
+// second reduction stage on the GPU) and the breakdown flag both go straight to host memory.
+RedCtl norm_export(const hp_handle* H) {
+    RedCtl rc = red(H, OP_NONE);
+    rc.partials = H->dev_part;
+    rc.flag_out = H->dev_part + H->partial_cap;
+    return rc;
+}
+
+// Split form of read_scalars for the CG loops: post_scalars marks the point of the stream up to
+// which the host wants the exported partials and flag (nparts of them, see norm_export), later
+// work may be enqueued behind it, and wait_scalars blocks only until that point is reached.
 int post_scalars(hp_handle* H, int nparts) {
-    HIPCHK(hipMemcpyAsync(H->host_scal, H->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                          H->stream));
-    if (nparts > 0)
-        HIPCHK(hipMemcpyAsync(H->host_part, H->partials, nparts * sizeof(double), hipMemcpyDeviceToHost,
-                              H->stream));
     H->host_nparts = nparts;
     HIPCHK(hipEventRecord(H->ev_scal, H->stream));
     return HP_OK;
 }
 
-// ||r||^2 from the partials of the last post_scalars, in workgroup order
+bool host_breakdown(const hp_handle* H) { return H->host_part[H->partial_cap] != 0.0; }
+
+// ||r||^2 from the partials of the last r -= alpha q, in workgroup order
 double host_rr(const hp_handle* H) {
     double s = 0.0;
     for (int i = 0; i < H->host_nparts; ++i) s += H->host_part[i];
@@ -587,7 +598,7 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         }
         // r -= alpha q now; x += alpha p is deferred to the next direction update (or the exit)
         const Geo<double> gn = geo_pass(H, g, 0);
-        const int np = launch_axpy_norm<double>(H->r, H->q, N, red(H, OP_NONE), s, &gn);
+        const int np = launch_axpy_norm<double>(H->r, H->q, N, norm_export(H), s, &gn);
         CHK(check_launch());
         CHK(post_scalars(H, np));
         // the next direction only reads r and the scalars, so it may run ahead of the check
@@ -596,7 +607,7 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         CHK(check_launch());
         CHK(wait_scalars(H));
         st.iterations++;
-        if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
+        if (host_breakdown(H)) return fail(HP_EBREAKDOWN, "CG breakdown: p^T A p <= 0");
         double rr = host_rr(H);
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite residual in iteration %d", st.iterations);
         ratio = rr_prev > 0.0 ? rr / rr_prev : 1.0;
@@ -661,7 +672,7 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
     while (*its < budget) {
         // r -= alpha q; x += alpha p is deferred to the next direction update (or the end)
         const Geo<float> gn = geo_pass(H, g, 0);
-        const int np = launch_axpy_norm<float>(H->r32, H->q32, N, red(H, OP_NONE), s, &gn);
+        const int np = launch_axpy_norm<float>(H->r32, H->q32, N, norm_export(H), s, &gn);
         CHK(check_launch());
         CHK(post_scalars(H, np));
         ahead = *its + 1 < budget && look_ahead(rr_prev, ratio, eta);
@@ -669,7 +680,7 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
         CHK(check_launch());
         CHK(wait_scalars(H));
         (*its)++;
-        if (H->host_scal[S_FLAG] != 0.0) return fail(HP_EBREAKDOWN, "inner CG breakdown");
+        if (host_breakdown(H)) return fail(HP_EBREAKDOWN, "inner CG breakdown");
         double rr = host_rr(H);
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite inner residual");
         ratio = rr_prev > 0.0 ? rr / rr_prev : 1.0;
@@ -1058,9 +1069,12 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
         (rc = dalloc(H, &H->flag, 1)))
         return bail(rc);
     if (hipHostMalloc((void**)&H->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&H->host_part, cap * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&H->host_part, (cap + 1) * sizeof(double),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc((void**)&H->host_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(HP_ENOMEM, "pinned host allocation failed"));
+    if (hipHostGetDevicePointer((void**)&H->dev_part, H->host_part, 0) != hipSuccess)
+        return bail(fail(HP_EHIP, "hipHostGetDevicePointer failed"));
     if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess ||
         hipEventCreateWithFlags(&H->ev_scal, hipEventDisableTiming) != hipSuccess)
         return bail(fail(HP_EHIP, "hipEventCreate failed"));
