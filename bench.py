@@ -90,9 +90,10 @@ def kernel_time_ms(fn, reps=50):
 
 def roofline(solver, rhs, x, n_cells, dev, warmup):
     """Roofline of the dominant finest-level kernel, measured live: the solver's own HIP-event
-    timing (on its stream) of every CG operator apply and every black post-smoothing half sweep
-    inside FP64 solves of the benchmark's right-hand sides; a plain device copy of 1 GiB (beyond
-    the 256 MB last-level cache) as the measured streaming reference."""
+    timing (on its stream; the events are attached to the dispatches themselves) of every CG
+    operator apply and every post-smoothing half sweep on the finest level inside FP64 solves of
+    the benchmark's right-hand sides; a plain device copy of 1 GiB (beyond the 256 MB last-level
+    cache) as the measured streaming reference."""
     import torch
     import paper_1112_3507_amd as hp
     solver.set_option(hp.OPT_KERNEL_TIMING, 1)
@@ -110,9 +111,10 @@ def roofline(solver, rhs, x, n_cells, dev, warmup):
     dst = torch.empty_like(src)
     copy_ms = kernel_time_ms(lambda: dst.copy_(src), reps=20)
     del src, dst
-    # both are launched once per CG iteration: the longer one is the dominant kernel (the
-    # operator apply; the pre-smoothing pass is close behind it, the half sweeps well below)
-    dom = max(times, key=times.get)
+    # the dominant kernel takes the largest share of the solve: the half sweep (two launches per
+    # CG iteration, the kernel with the largest total time in the rocprofv3 summary) ahead of the
+    # apply (one launch)
+    dom = max(acc, key=lambda k: acc[k][0])
     gbs = ALG_BYTES[dom] * n_cells / (times[dom] * 1e-3) / 1e9
     kern = {k: {"ms": round(v, 5), "launches_timed": acc[k][1], "alg_bytes_per_cell": ALG_BYTES[k],
                 "achieved_GBs": round(ALG_BYTES[k] * n_cells / (v * 1e-3) / 1e9, 1) if v > 0 else None}

@@ -68,6 +68,11 @@ struct Transfer {
 };
 
 // ---- launchers (hp_kernels.hip); all asynchronous on `s` ----
+// Kernel timing: the next split-layout apply or half sweep launched by this thread records its
+// start and end into these events (hipExtLaunchKernel); launch_events_pending tells whether that
+// launch has happened yet.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_pending();
 void launch_setup_coef(const double* rho, const double* c2, double* rho_out, double* m,
                        float* rho32, float* m32, int64_t n, int* bad, hipStream_t s);
 void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m_f,
@@ -166,9 +171,9 @@ void launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
 // flag nonzero if any entry is not finite
 void launch_check_finite(const double* x, int64_t n, int* bad, hipStream_t s);
 // natural -> split relayout of a solve's input with the finiteness check (bit 0 of *flags), the
-// nonzero check (bits nzbit) and, under rc, its norm
+// nonzero check (bits nzbit) and, under rc, its norm; where dst2 is given, a second split copy
 void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* flags, int nzbit,
-                        const RedCtl& rc, hipStream_t s);
+                        const RedCtl& rc, hipStream_t s, double* dst2 = nullptr);
 
 // y = a x + b y
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);

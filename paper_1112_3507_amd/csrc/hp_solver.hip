@@ -202,18 +202,23 @@ hipEvent_t timing_event(hp_handle* H) {
     return H->tev[H->tev_used++];
 }
 
-// brackets one launch: time_begin before it, time_end right after it, on the handle's stream
+// times one launch: time_begin before it hands a pair of events to the launcher, which attaches
+// them to the dispatch (split-layout stencils only); time_end right after it keeps the span if the
+// launch took them, else drops it
 void time_begin(hp_handle* H, int cls) {
     if (!H->timing) return;
     const size_t first = H->tev_used;
     hipEvent_t a = timing_event(H), b = timing_event(H);
     if (!a || !b) return;
-    (void)hipEventRecord(a, H->stream);
+    set_launch_events(a, b);
     H->spans.push_back({cls, (int)first});
 }
 void time_end(hp_handle* H) {
     if (!H->timing || H->spans.empty()) return;
-    (void)hipEventRecord(H->tev[H->spans.back().second + 1], H->stream);
+    if (launch_events_pending()) {
+        set_launch_events(nullptr, nullptr);
+        H->spans.pop_back();
+    }
 }
 
 // ---- coarsest level: dense FP64 operator, Cholesky, symmetric inverse (host) ----
@@ -486,10 +491,15 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
         if (timed) time_end(H);
         if (last_dot) {
             const Geo<T> gd = geo_pass(H, g, l);
-            return launch_rbgs_dot<T>(gd, rho, m, r, z, 0, *dot, s, H->partials2, nb2) ||
-                   (launch_rbgs<T>(gd, rho, m, r, z, 0, s), false);
+            if (timed) time_begin(H, TIME_SWEEP);
+            const bool done = launch_rbgs_dot<T>(gd, rho, m, r, z, 0, *dot, s, H->partials2, nb2);
+            if (!done) launch_rbgs<T>(gd, rho, m, r, z, 0, s);
+            if (timed) time_end(H);
+            return done;
         }
+        if (timed) time_begin(H, TIME_SWEEP);
         launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 0, s);
+        if (timed) time_end(H);
     }
     return false;
 }
@@ -592,7 +602,7 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
     while (true) {
         if (restart) {
             precond64(H, H->r, H->z, OP_RZINIT);
-            launch_copy<double>(H->z, H->p, N, s);
+            std::swap(H->z, H->p);   // p = z (z is rewritten before it is read again)
             launch_apply<double>(geo_pass(H, g, 0), F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
             restart = false;
         }
@@ -664,7 +674,7 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
         RedCtl rc = red(H, OP_RZINIT);
         if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, N, rc, s);
     }
-    launch_copy<float>(H->z32, H->p32, N, s);
+    std::swap(H->z32, H->p32);   // p = z (z is rewritten before it is read again)
     launch_apply<float>(geo_pass(H, g, 0), F.rho32, F.m32, H->p32, nullptr, H->q32, 1, red(H, OP_ALPHA), s);
     *its = 0;
     double rr_prev = 1.0, ratio = 1.0;
@@ -1197,11 +1207,12 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), s));
     HIPCHK(hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), s));
     // in the split layout the solve runs on split copies of b and x (made in the pass that checks
-    // them, takes ||b|| and notes whether x is zero); x is copied back at the end
+    // them, takes ||b|| and notes whether x is zero; the pass over b also leaves b in r, the initial
+    // residual when x is zero); x is copied back at the end
     double* xu = x;
     int rc;
     if (F.split) {
-        launch_relayout_in(b, H->bs, F.n[0], F.n[1], F.n[2], H->flag, 0, red(H, OP_STORE, S_BB), s);
+        launch_relayout_in(b, H->bs, F.n[0], F.n[1], F.n[2], H->flag, 0, red(H, OP_STORE, S_BB), s, H->r);
         launch_relayout_in(x, H->xs, F.n[0], F.n[1], F.n[2], H->flag, 2, red(H, OP_NONE), s);
         b = H->bs;
         x = H->xs;
@@ -1215,8 +1226,7 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
         if (*H->host_flag & 2) {
             launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
             if ((rc = check_launch()) || (rc = read_scalars(H))) return rc;
-        } else {  // x = 0: the initial residual is b itself
-            launch_copy<double>(b, H->r, N, s);
+        } else {  // x = 0: the initial residual is b itself, already in r
             H->host_scal[S_RR] = H->host_scal[S_BB];
         }
     } else {
