@@ -99,8 +99,9 @@ typedef struct {
     int status;            /* return code of the solve */
     int fallback;          /* MIXED_IR: 1 if refinement stagnated and FP64 MG-PCG finished */
     /* with HP_OPT_KERNEL_TIMING on (FP64 solves): finest-level launches timed with HIP events on
-       the handle's stream during the solve, and their average duration */
-    int timed_sweeps;      /* red-black half sweeps (the black post-smoothing sweep) */
+       the handle's stream during the solve (attached to the dispatches; split layout only), and
+       their average duration */
+    int timed_sweeps;      /* red-black half sweeps (both post-smoothing sweeps) */
     double sweep_ms;
     int timed_applies;     /* operator applies q = A p of the CG iteration */
     double apply_ms;
