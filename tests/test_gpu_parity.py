@@ -322,6 +322,31 @@ def test_update_coefficients_matches_fresh_setup():
     assert st["converged"] and relerr(host(x), xref) <= 1e-9
 
 
+def test_kernel_timing_counts_the_finest_launches():
+    """HP_OPT_KERNEL_TIMING: on a split finest level every operator apply of a new direction and
+    both post-smoothing half sweeps of every V-cycle are timed (events attached to the
+    dispatches), the timing changes nothing in the result, and with natural storage nothing is
+    timed."""
+    p = problem(DEEP, 0.001)
+    b = dev(wl.rhs_white(p.n, 9))
+    with make(p) as s:
+        x0 = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        st0 = s.solve(b, x0, tol=1e-10)
+        assert st0["timed_sweeps"] == 0 and st0["timed_applies"] == 0
+        s.set_option(hp.OPT_KERNEL_TIMING, 1)
+        x1 = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        st1 = s.solve(b, x1, tol=1e-10)
+        assert np.array_equal(host(x0), host(x1))
+        its = st1["iterations"]
+        assert st1["timed_sweeps"] % 2 == 0 and its <= st1["timed_sweeps"] // 2 <= its + 1
+        assert its - 1 <= st1["timed_applies"] <= its
+        assert 0.0 < st1["sweep_ms"] < st1["time_ms"] and 0.0 < st1["apply_ms"] < st1["time_ms"]
+        s.set_option(hp.OPT_LAYOUT, 0)
+        x2 = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        st2 = s.solve(b, x2, tol=1e-10)
+        assert st2["converged"] and st2["timed_sweeps"] == 0 and st2["timed_applies"] == 0
+
+
 def test_solve_is_deterministic():
     p = problem(RAGGED, 0.001)
     b, _ = reference(RAGGED, 0.001, 1, 2)
