@@ -1206,7 +1206,9 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
         const T wzm = czm * face_kappa(rbr, cm.rho), wzp = czp * face_kappa(rbr, cn.rho);
         swq += wzm * qm + wzp * qn;
         if (L.act) {
-            z[rb + t] = qc;
+            // the red values are next read by the prolongation after the coarse levels; the
+            // black ones by the residual right after this pass
+            __builtin_nontemporal_store(qc, &z[rb + t]);
             z[rb + hx + t] = (c.r + swq) * c.d;
         }
     };
