@@ -39,11 +39,12 @@ ALG_BYTES = {
 }
 
 # Algorithmic FP64 bytes per finest-level cell and MG-PCG iteration (every pass of the
-# iteration with the arrays it must touch once): apply 32, pre-smooth 32, red residual 16,
+# iteration with the arrays it must touch once): apply 32, r -= alpha q with ||r||^2 folded into
+# the next zero-guess pre-smoothing 48 (read r, q, dinv, rho; write r', z), red residual 16,
 # red-only restriction 5, red-only prolongation 9, black sweep 24, red sweep 24 (the two sweeps
-# each reduce their own half of <r, z>), r -= alpha q 24, x += alpha p with p = z + beta p 40;
-# plus the coarser levels (1/7 of the V-cycle's finest-level 110 bytes: 16).
-ITER_BYTES_PER_CELL = 32 + 32 + 16 + 5 + 9 + 24 + 24 + 24 + 40 + 16
+# each reduce their own half of <r, z>), x += alpha p with p = z + beta p 40; plus the coarser
+# levels (1/7 of the V-cycle's finest-level 110 bytes: 16).
+ITER_BYTES_PER_CELL = 32 + 48 + 16 + 5 + 9 + 24 + 24 + 40 + 16
 
 
 def log(msg):

@@ -170,6 +170,13 @@ template <typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
 // flag nonzero if any entry is not finite
 void launch_check_finite(const double* x, int64_t n, int* bad, hipStream_t s);
+// r' = r - alpha q with ||r'||^2 under rc (partials; flag exported as by launch_axpy_norm), folded
+// into the zero-guess pre-smoothing z of the next V-cycle on the split level g; r' goes to rn
+// (distinct from r). Returns the number of partials.
+template <typename T>
+int launch_presmooth_update(const Geo<T>& g, const T* rho, const T* dinv, const T* r, const T* q, T* rn, T* z,
+                            const RedCtl& rc, hipStream_t s);
+
 // natural -> split relayout of a solve's input with the finiteness check (bit 0 of *flags), the
 // nonzero check (bits nzbit) and, under rc, its norm; where dst2 is given, a second split copy
 void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* flags, int nzbit,

@@ -81,6 +81,13 @@ __device__ void block_partial(double v, double* partials) {
     if (flat_tid() == 0) partials[flat_bid()] = s;
 }
 
+// The host reads the residual-norm partials of the CG residual update and the breakdown flag as
+// they stand when that kernel runs; with rc.partials and rc.flag_out in mapped pinned host memory
+// the kernel delivers both itself (no copy launch behind it): workgroup 0 copies the flag.
+__device__ __forceinline__ void export_flag(const RedCtl& rc) {
+    if (rc.flag_out && flat_bid() == 0 && flat_tid() == 0) rc.flag_out[0] = rc.scal[S_FLAG];
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int nb,
                                                      const double* __restrict__ partials2, int nb2,
                                                      double* __restrict__ sc, int op, int slot) {
@@ -1098,12 +1105,17 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles z
 // z_black = dinv_b (r_b + sum_f w_f (r dinv)_nb) on black cells, whose neighbours are all red.
 // The red q = r dinv and rho of the current plane are exchanged through LDS; the red column
 // (r, dinv and rho at t, planes k-1 .. k+2) forms the register ring.
-template <typename T, bool FULL, int XW>
+// UPD: the CG residual update of the iteration is folded in: the pass reads r and q, smooths
+// r' = r - alpha q (alpha = scal[S_ALPHA]), writes r' to rn (a second array: other workgroups
+// read r around their tiles meanwhile) and reduces ||r'||^2 over its cells into partials, with
+// the breakdown flag copied by workgroup 0 (as r -= alpha q does).
+template <typename T, bool FULL, int XW, bool UPD>
 __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
                                                          const T* __restrict__ rho,
                                                          const T* __restrict__ dinv,
                                                          const T* __restrict__ r,
-                                                         T* __restrict__ z) {
+                                                         T* __restrict__ z, const T* __restrict__ qv,
+                                                         T* __restrict__ rn, RedCtl rc) {
     constexpr int kTW = 64 * XW, kBlockS = kTW * kRowsS;
     __shared__ T sx[2][2][kRowsS + 2][kTW];  // [plane slot][red q, red rho][row][column]
     int bx, by, bz;
@@ -1115,12 +1127,15 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
     const int lm = L.lm, lp = L.lp;
     const int k0 = bz * zt.kz;
     const int k1 = min(k0 + zt.kz, g.nz);
-    // red entries at t of one plane: r, dinv and rho
+    const T alpha = UPD ? (T)rc.scal[S_ALPHA] : T(0);
+    double nacc = 0.0;
+    // red entries at t of one plane: r (and q), dinv and rho; r' = r - alpha q is formed at use
     struct Red {
-        T r, d, rho;
+        T r, q, d, rho;
     };
     auto ldred = [&](int rbp, Red& o) {
         o.r = r[rbp + t];
+        o.q = UPD ? ld_stream(&qv[rbp + t]) : T(0);
         o.d = dinv[rbp + t];
         o.rho = rho[rbp + t];
     };
@@ -1128,26 +1143,28 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
     constexpr int HI = 4 * kTW, NH = (HI + kBlockS - 1) / kBlockS;
     // the black cell of a plane, its outer x neighbour where memory supplies it, halo entries
     struct Own {
-        T rho, r, d, xr, xd, xrho;
-        T h0[NH], h1[NH];
+        T rho, r, q, d, xr, xq, xd, xrho;
+        T h0[NH], h1[NH], h2[NH];
     };
     auto load_own = [&](int kp, Own& o) {
         const int rbp = srow(j, kp, nx, ny);
         o.rho = rho[rbp + hx + t];
         o.r = r[rbp + hx + t];
+        o.q = UPD ? ld_stream(&qv[rbp + hx + t]) : T(0);
         o.d = dinv[rbp + hx + t];
         if (!FULL) {
             const int ep = ((j + kp) & 1) ^ 1;
             const bool gxp = ep ? L.gr : L.gl;
             const int txp = ep ? sc.tp : sc.tm;
             o.xr = gxp ? r[rbp + txp] : T(0);
+            o.xq = (UPD && gxp) ? qv[rbp + txp] : T(0);
             o.xd = gxp ? dinv[rbp + txp] : T(0);
             o.xrho = gxp ? rho[rbp + txp] : T(0);
         }
 #pragma unroll
         for (int n = 0; n < NH; ++n) {
             const int i = threadIdx.x + n * kBlockS;
-            T v0 = T(0), v1 = T(1);
+            T v0 = T(0), v1 = T(1), v2 = T(0);
             if (i < HI) {
                 const int col = i % kTW, rest = i / kTW;
                 const int arr = rest & 1, side = rest >> 1;
@@ -1158,19 +1175,24 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
                 } else {
                     v0 = r[a];
                     v1 = dinv[a];
+                    if (UPD) v2 = qv[a];
                 }
             }
             o.h0[n] = v0;
             o.h1[n] = v1;
+            o.h2[n] = v2;
         }
     };
+    // r' of a loaded (r, q) pair (r itself without UPD)
+    auto rup = [&](T rv, T q) { return UPD ? rv - alpha * q : rv; };
     auto step = [&](int k, const Red& cm, const Red& cc, const Red& cn, Red& cnn, const Own& c, Own& nxt) {
         const int kn = min(k + 1, k1 - 1);
         load_own(kn, nxt);
         ldred(srow(j, kabove(kn, g.nz, g.pz), nx, ny), cnn);
         const int rb = srow(j, k, nx, ny);
         const int e = ((j + k) & 1) ^ 1;
-        const T qm = cm.r * cm.d, qc = cc.r * cc.d, qn = cn.r * cn.d;
+        const T rcr = rup(cc.r, cc.q), rcb = rup(c.r, c.q);   // r' of this plane's red and black cell
+        const T qm = rup(cm.r, cm.q) * cm.d, qc = rcr * cc.d, qn = rup(cn.r, cn.q) * cn.d;
         // exchange the red cells of plane k
         const int sl = k & 1;
         sx[sl][0][w + 1][lane] = qc;
@@ -1180,14 +1202,15 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
             const int i = threadIdx.x + n * kBlockS;
             if (i < HI) {
                 const int col = i % kTW, rest = i / kTW;
-                sx[sl][rest & 1][(rest >> 1) ? kRowsS + 1 : 0][col] = c.h0[n] * c.h1[n];
+                // rho entries carry v2 = 0: rup leaves them as loaded
+                sx[sl][rest & 1][(rest >> 1) ? kRowsS + 1 : 0][col] = rup(c.h0[n], c.h2[n]) * c.h1[n];
             }
         }
         __syncthreads();
         const int ln = e ? lp : lm;
         T qx = sx[sl][0][w + 1][ln], rx = sx[sl][1][w + 1][ln];
         if (!FULL && (e ? L.gr : L.gl)) {
-            qx = c.xr * c.xd;
+            qx = rup(c.xr, c.xq) * c.xd;
             rx = c.xrho;
         }
         const T qy0 = sx[sl][0][w][lane], ry0 = sx[sl][1][w][lane];
@@ -1209,10 +1232,15 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
             // the red values are next read by the prolongation after the coarse levels; the
             // black ones by the residual right after this pass
             __builtin_nontemporal_store(qc, &z[rb + t]);
-            z[rb + hx + t] = (c.r + swq) * c.d;
+            z[rb + hx + t] = (rcb + swq) * c.d;
+            if (UPD) {
+                rn[rb + t] = rcr;
+                rn[rb + hx + t] = rcb;
+                nacc += (double)rcr * (double)rcr + (double)rcb * (double)rcb;
+            }
         }
     };
-    Red C0, C1, C2, C3 = {T(0), T(0), T(0)};
+    Red C0, C1, C2, C3 = {T(0), T(0), T(0), T(0)};
     ldred(srow(j, kbelow(k0, g.nz, g.pz), nx, ny), C0);
     ldred(srow(j, k0, nx, ny), C1);
     ldred(srow(j, kabove(k0, g.nz, g.pz), nx, ny), C2);
@@ -1228,6 +1256,10 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
     if (k < k1) step(k, C0, C1, C2, C3, A, B);
     if (k + 1 < k1) step(k + 1, C1, C2, C3, C0, B, A);
     if (k + 2 < k1) step(k + 2, C2, C3, C0, C1, A, B);
+    if (UPD) {
+        block_partial(nacc, rc.partials);
+        export_flag(rc);
+    }
 }
 
 // Launch one split kernel over its tiles: one wave per row for rows of up to 64 half positions,
@@ -1298,22 +1330,38 @@ static void launch_rbgs_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, cons
             break;
     }
 }
-template <typename T>
+template <typename T, bool UPD = false>
 static void launch_presmooth_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, const T* dinv, const T* r,
-                                T* z, hipStream_t s) {
+                                T* z, hipStream_t s, const T* q = nullptr, T* rn = nullptr,
+                                const RedCtl& rc = RedCtl{}) {
     const int hx = g.nx >> 1;
     const dim3 grid(zt.tx * zt.ty * zt.tz), block = split_block(hx);
     switch (split_shape(hx)) {
         case SPLIT_FULL1:
-            hipLaunchKernelGGL((k_presmooth_zs<T, true, 1>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+            hipLaunchKernelGGL((k_presmooth_zs<T, true, 1, UPD>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
+                               rn, rc);
             break;
         case SPLIT_FULL2:
-            hipLaunchKernelGGL((k_presmooth_zs<T, true, 2>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+            hipLaunchKernelGGL((k_presmooth_zs<T, true, 2, UPD>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
+                               rn, rc);
             break;
         default:
-            hipLaunchKernelGGL((k_presmooth_zs<T, false, 2>), grid, block, 0, s, g, zt, rho, dinv, r, z);
+            hipLaunchKernelGGL((k_presmooth_zs<T, false, 2, UPD>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
+                               rn, rc);
             break;
     }
+}
+
+// The residual update r' = r - alpha q of a CG iteration with ||r'||^2 (under rc), folded into
+// the zero-guess pre-smoothing z of the next V-cycle on a split level; returns the number of
+// partials
+template <typename T>
+int launch_presmooth_update(const Geo<T>& g, const T* rho, const T* dinv, const T* r, const T* q, T* rn, T* z,
+                            const RedCtl& rc, hipStream_t s) {
+    ZTiles zt = split_tiles(g.nx >> 1, g.ny, g.nz);
+    zt.rev = g.rev;
+    launch_presmooth_zs<T, true>(g, zt, rho, dinv, r, z, s, q, rn, rc);
+    return zt.tx * zt.ty * zt.tz;
 }
 
 static bool use_zm(int nx, int ny, int nz) { return nx >= 64 && ny >= 4 && nz >= 8; }
@@ -2470,13 +2518,6 @@ void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s)
                        s, z, p, n, scal);
 }
 
-// The host reads the residual-norm partials of r -= alpha q and the breakdown flag as they stand
-// when that kernel runs; with rc.partials and rc.flag_out in mapped pinned host memory the two
-// kernels below deliver both themselves (no copy launch behind them).
-__device__ __forceinline__ void export_flag(const RedCtl& rc) {
-    if (rc.flag_out && flat_bid() == 0 && flat_tid() == 0) rc.flag_out[0] = rc.scal[S_FLAG];
-}
-
 // The CG iterate update deferred by one iteration: r -= alpha q with ||r||^2 first, then
 // x += alpha p together with the next direction p = z + beta p (p is read once for both).
 template <typename T>
@@ -2773,7 +2814,9 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
     template void launch_axpy_alpha<T>(T*, const T*, int64_t, const double*, hipStream_t);      \
     template void launch_xpby<T>(const T*, T*, int64_t, const double*, hipStream_t);            \
     template void launch_fill<T>(T*, T, int64_t, hipStream_t);                                  \
-    template void launch_copy<T>(const T*, T*, int64_t, hipStream_t);
+    template void launch_copy<T>(const T*, T*, int64_t, hipStream_t);                           \
+    template int launch_presmooth_update<T>(const Geo<T>&, const T*, const T*, const T*, const T*, T*,  \
+                                            T*, const RedCtl&, hipStream_t);
 
 HP_INST(double)
 HP_INST(float)

@@ -77,7 +77,9 @@ struct hp_handle {
     double* ainv = nullptr;
     std::vector<double> host_ainv;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double* r2 = nullptr;  // second residual array: the fused residual update writes r' there
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    float* r32b = nullptr;  // second FP32 residual array (fused residual update)
     // split layout of the finest level: whether it is wanted, split copies of the caller's rhs and
     // iterate, natural copies of rho and m for the network
     int want_split = 0;
@@ -445,7 +447,9 @@ template <> const float* lvl_dinv<float>(const LevelData& L) { return L.dinv32; 
 // V-cycle z = M r on level l. With dot != nullptr (level 0 only) the final red half sweep also
 // reduces <r, z> under *dot; returns true if it did (else the caller reduces separately).
 template <typename T>
-bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) {
+// pre_done: the zero-guess pre-smoothing of the finest level has already been launched (fused
+// with the CG residual update, see pcg64)
+bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr, bool pre_done = false) {
     LevelData& L = H->lv[l];
     hipStream_t s = H->stream;
     if (l == (int)H->lv.size() - 1) {
@@ -455,7 +459,8 @@ bool vcycle(hp_handle* H, int l, const T* r, T* z, const RedCtl* dot = nullptr) 
     Geo<T> g = geo<T>(H, L);
     const T* rho = lvl_rho<T>(L);
     const T* m = lvl_m<T>(L);
-    const bool fused_pre = launch_presmooth<T>(geo_pass(H, g, l), rho, lvl_dinv<T>(L), r, z, s);
+    const bool fused_pre =
+        (l == 0 && pre_done) || launch_presmooth<T>(geo_pass(H, g, l), rho, lvl_dinv<T>(L), r, z, s);
     if (!fused_pre) {
         launch_rbgs_zero<T>(geo_pass(H, g, l), rho, m, r, z, s);
         launch_rbgs<T>(geo_pass(H, g, l), rho, m, r, z, 1, s);
@@ -553,13 +558,13 @@ bool look_ahead(double rr_prev, double ratio, double target) {
 }
 
 // Preconditioner z = M r with <r, z> reduced under `op` (OP_RZINIT or OP_BETA).
-void precond64(hp_handle* H, const double* r, double* z, int op) {
+void precond64(hp_handle* H, const double* r, double* z, int op, bool pre_done = false) {
     int64_t N = H->lv[0].N;
     if (H->mode == HP_MODE_JACOBI_PCG) {
         launch_jacobi_apply(H->lv[0].dinv, r, z, N, red(H, op), H->stream);
     } else {
         RedCtl rc = red(H, op);
-        if (!vcycle<double>(H, 0, r, z, &rc)) launch_dot<double>(r, z, N, rc, H->stream);
+        if (!vcycle<double>(H, 0, r, z, &rc, pre_done)) launch_dot<double>(r, z, N, rc, H->stream);
     }
 }
 
@@ -577,10 +582,10 @@ int true_residual(hp_handle* H, const double* b, const double* x, double* out, d
 
 // Next direction of the FP64 PCG: z = M r (beta from <r, z>), x += alpha p (the deferred update
 // of the previous step), p = z + beta p, q = A p (alpha from <p, q>).
-void next_direction64(hp_handle* H, double* x) {
+void next_direction64(hp_handle* H, double* x, bool pre_done = false) {
     LevelData& F = H->lv[0];
     hipStream_t s = H->stream;
-    precond64(H, H->r, H->z, OP_BETA);
+    precond64(H, H->r, H->z, OP_BETA, pre_done);
     launch_xpby_x<double>(H->z, H->p, x, F.N, H->scal, s);
     time_begin(H, TIME_APPLY);
     launch_apply<double>(geo_pass(H, geo<double>(H, F), 0), F.rho, F.m, H->p, nullptr, H->q, 1,
@@ -606,14 +611,23 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
             launch_apply<double>(geo_pass(H, g, 0), F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_ALPHA), s);
             restart = false;
         }
-        // r -= alpha q now; x += alpha p is deferred to the next direction update (or the exit)
+        // r -= alpha q now; x += alpha p is deferred to the next direction update (or the exit).
+        // The next direction only reads r and the scalars, so it may run ahead of the check; it
+        // then starts with the V-cycle's zero-guess pre-smoothing, which on a split finest level
+        // takes the residual update along (r' into the second residual array)
         const Geo<double> gn = geo_pass(H, g, 0);
-        const int np = launch_axpy_norm<double>(H->r, H->q, N, norm_export(H), s, &gn);
+        const bool ahead = st.iterations + 1 < H->max_iter && look_ahead(rr_prev, ratio, target);
+        const bool fuse = ahead && H->mode == HP_MODE_FP64_MGPCG && F.split;
+        int np;
+        if (fuse) {
+            np = launch_presmooth_update<double>(gn, F.rho, F.dinv, H->r, H->q, H->r2, H->z, norm_export(H), s);
+            std::swap(H->r, H->r2);
+        } else {
+            np = launch_axpy_norm<double>(H->r, H->q, N, norm_export(H), s, &gn);
+        }
         CHK(check_launch());
         CHK(post_scalars(H, np));
-        // the next direction only reads r and the scalars, so it may run ahead of the check
-        const bool ahead = st.iterations + 1 < H->max_iter && look_ahead(rr_prev, ratio, target);
-        if (ahead) next_direction64(H, x);
+        if (ahead) next_direction64(H, x, fuse);
         CHK(check_launch());
         CHK(wait_scalars(H));
         st.iterations++;
@@ -653,11 +667,11 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
 }
 
 // Next direction of the inner FP32 PCG (the same steps as next_direction64 on the FP32 vectors).
-void next_direction32(hp_handle* H) {
+void next_direction32(hp_handle* H, bool pre_done = false) {
     LevelData& F = H->lv[0];
     hipStream_t s = H->stream;
     RedCtl rc = red(H, OP_BETA);
-    if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, F.N, rc, s);
+    if (!vcycle<float>(H, 0, H->r32, H->z32, &rc, pre_done)) launch_dot<float>(H->r32, H->z32, F.N, rc, s);
     launch_xpby_x<float>(H->z32, H->p32, H->x32, F.N, H->scal, s);
     launch_apply<float>(geo_pass(H, geo<float>(H, F), 0), F.rho32, F.m32, H->p32, nullptr, H->q32, 1,
                         red(H, OP_ALPHA), s);
@@ -680,13 +694,22 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
     double rr_prev = 1.0, ratio = 1.0;
     bool ahead = false;
     while (*its < budget) {
-        // r -= alpha q; x += alpha p is deferred to the next direction update (or the end)
+        // r -= alpha q; x += alpha p is deferred to the next direction update (or the end); as in
+        // pcg64 the update rides on the next pre-smoothing when the next direction runs ahead
         const Geo<float> gn = geo_pass(H, g, 0);
-        const int np = launch_axpy_norm<float>(H->r32, H->q32, N, norm_export(H), s, &gn);
+        ahead = *its + 1 < budget && look_ahead(rr_prev, ratio, eta);
+        const bool fuse = ahead && F.split;
+        int np;
+        if (fuse) {
+            np = launch_presmooth_update<float>(gn, F.rho32, F.dinv32, H->r32, H->q32, H->r32b, H->z32,
+                                                norm_export(H), s);
+            std::swap(H->r32, H->r32b);
+        } else {
+            np = launch_axpy_norm<float>(H->r32, H->q32, N, norm_export(H), s, &gn);
+        }
         CHK(check_launch());
         CHK(post_scalars(H, np));
-        ahead = *its + 1 < budget && look_ahead(rr_prev, ratio, eta);
-        if (ahead) next_direction32(H);
+        if (ahead) next_direction32(H, fuse);
         CHK(check_launch());
         CHK(wait_scalars(H));
         (*its)++;
@@ -1065,10 +1088,11 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
     }
     if ((rc = dalloc(H, &H->ainv, (int64_t)H->nc * H->nc))) return bail(rc);
     if ((rc = dalloc(H, &H->r, N)) || (rc = dalloc(H, &H->z, N)) || (rc = dalloc(H, &H->p, N)) ||
-        (rc = dalloc(H, &H->q, N)))
+        (rc = dalloc(H, &H->q, N)) || (rc = dalloc(H, &H->r2, N)))
         return bail(rc);
     if ((rc = dalloc(H, &H->x32, N)) || (rc = dalloc(H, &H->r32, N)) ||
-        (rc = dalloc(H, &H->z32, N)) || (rc = dalloc(H, &H->p32, N)) || (rc = dalloc(H, &H->q32, N)))
+        (rc = dalloc(H, &H->z32, N)) || (rc = dalloc(H, &H->p32, N)) || (rc = dalloc(H, &H->q32, N)) ||
+        (rc = dalloc(H, &H->r32b, N)))
         return bail(rc);
     int64_t cap = std::max<int64_t>(reduce_blocks_vec(N), 1);
     for (auto& L : H->lv)
