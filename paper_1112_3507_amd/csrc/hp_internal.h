@@ -154,9 +154,10 @@ int launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t 
                      const Geo<T>* g = nullptr);
 template <typename T>
 void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s,
-                   const Geo<T>* g = nullptr);
+                   const Geo<T>* g = nullptr, bool xzero = false);
+// (xzero: x is known to be zero and is written, not read, by the update; natural flat passes)
 template <typename T>
-void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s);
+void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s, bool xzero = false);
 // z = dinv * r with <r, z> reduced
 void launch_jacobi_apply(const double* dinv, const double* r, double* z, int64_t n,
                          const RedCtl& rc, hipStream_t s);
@@ -178,7 +179,8 @@ int launch_presmooth_update(const Geo<T>& g, const T* rho, const T* dinv, const 
                             const RedCtl& rc, hipStream_t s);
 
 // natural -> split relayout of a solve's input with the finiteness check (bit 0 of *flags), the
-// nonzero check (bits nzbit) and, under rc, its norm; where dst2 is given, a second split copy
+// nonzero check (bits nzbit) and, under rc, its norm; where dst2 is given, a second split copy;
+// with dst null only the checks (and the norm) are made
 void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, int* flags, int nzbit,
                         const RedCtl& rc, hipStream_t s, double* dst2 = nullptr);
 

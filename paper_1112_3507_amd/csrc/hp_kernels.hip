@@ -2408,8 +2408,10 @@ __global__ __launch_bounds__(kBlock) void k_relayout_in(const double* __restrict
         const int p = (int)((row % ny + row / ny) & 1);
         const int64_t rb = row * nx;
         const double v0 = src[rb + 2 * t], v1 = src[rb + 2 * t + 1];
-        dst[rb + p * hx + t] = v0;
-        dst[rb + (1 - p) * hx + t] = v1;
+        if (dst) {
+            dst[rb + p * hx + t] = v0;
+            dst[rb + (1 - p) * hx + t] = v1;
+        }
         if (dst2) {
             dst2[rb + p * hx + t] = v0;
             dst2[rb + (1 - p) * hx + t] = v1;
@@ -2634,7 +2636,7 @@ int launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t 
     return vec_blocks(n);
 }
 
-template <typename T>
+template <typename T, bool XZ>
 __global__ __launch_bounds__(kBlock) void k_xpby_x(const T* __restrict__ z, T* __restrict__ p,
                                                    T* __restrict__ x, int64_t n,
                                                    const double* __restrict__ scal) {
@@ -2645,13 +2647,15 @@ __global__ __launch_bounds__(kBlock) void k_xpby_x(const T* __restrict__ z, T* _
         // the next preconditioner), so that the memory-side cache keeps p for the operator apply
         // that follows (at 256^3 that apply went from 114 to 99 µs)
         const T pa = p[a];
-        __builtin_nontemporal_store(__builtin_nontemporal_load(&x[a]) + alpha * pa, &x[a]);
+        const T xa = XZ ? T(0) : __builtin_nontemporal_load(&x[a]);   // XZ: x is known to be zero
+        __builtin_nontemporal_store(xa + alpha * pa, &x[a]);
         p[a] = __builtin_nontemporal_load(&z[a]) + beta * pa;
     }
 }
 
 template <typename T>
-void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s, const Geo<T>* g) {
+void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s, const Geo<T>* g,
+                   bool xzero) {
     if (g && g->split) {
         ZTiles zt = split_tiles(g->nx >> 1, g->ny, g->nz);
         zt.rev = g->rev;
@@ -2663,22 +2667,26 @@ void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStr
                                g->nx, g->ny, g->nz, z, p, x, scal);
         return;
     }
-    hipLaunchKernelGGL((k_xpby_x<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, z, p, x, n, scal);
+    if (xzero)
+        hipLaunchKernelGGL((k_xpby_x<T, true>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, z, p, x, n, scal);
+    else
+        hipLaunchKernelGGL((k_xpby_x<T, false>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, z, p, x, n, scal);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axpy_alpha(T* __restrict__ x, const T* __restrict__ p,
-                                                       int64_t n, const double* __restrict__ scal) {
+                                                       int64_t n, const double* __restrict__ scal, int xzero) {
     const T alpha = (T)scal[S_ALPHA];
     int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (a < n) x[a] += alpha * p[a];
+    if (a < n) x[a] = (xzero ? T(0) : x[a]) + alpha * p[a];
 }
 
 template <typename T>
-void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s) {
+void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s, bool xzero) {
     hipLaunchKernelGGL((k_axpy_alpha<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, x, p, n, scal);
+                       s, x, p, n, scal, xzero ? 1 : 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_jacobi_apply(const double* __restrict__ dinv,
@@ -2810,8 +2818,8 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
     template int launch_axpy_norm<T>(T*, const T*, int64_t, const RedCtl&, hipStream_t,         \
                                       const Geo<T>*);                                             \
     template void launch_xpby_x<T>(const T*, T*, T*, int64_t, const double*, hipStream_t,       \
-                                   const Geo<T>*);                                                \
-    template void launch_axpy_alpha<T>(T*, const T*, int64_t, const double*, hipStream_t);      \
+                                   const Geo<T>*, bool);                                          \
+    template void launch_axpy_alpha<T>(T*, const T*, int64_t, const double*, hipStream_t, bool);\
     template void launch_xpby<T>(const T*, T*, int64_t, const double*, hipStream_t);            \
     template void launch_fill<T>(T*, T, int64_t, hipStream_t);                                  \
     template void launch_copy<T>(const T*, T*, int64_t, hipStream_t);                           \

@@ -78,6 +78,9 @@ struct hp_handle {
     std::vector<double> host_ainv;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double* r2 = nullptr;  // second residual array: the fused residual update writes r' there
+    // the split iterate of the running solve is zero and has not been written yet (a zero initial
+    // guess): its first update writes x = alpha p without reading it
+    bool x_unset = false;
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     float* r32b = nullptr;  // second FP32 residual array (fused residual update)
     // split layout of the finest level: whether it is wanted, split copies of the caller's rhs and
@@ -586,7 +589,8 @@ void next_direction64(hp_handle* H, double* x, bool pre_done = false) {
     LevelData& F = H->lv[0];
     hipStream_t s = H->stream;
     precond64(H, H->r, H->z, OP_BETA, pre_done);
-    launch_xpby_x<double>(H->z, H->p, x, F.N, H->scal, s);
+    launch_xpby_x<double>(H->z, H->p, x, F.N, H->scal, s, nullptr, H->x_unset);
+    H->x_unset = false;
     time_begin(H, TIME_APPLY);
     launch_apply<double>(geo_pass(H, geo<double>(H, F), 0), F.rho, F.m, H->p, nullptr, H->q, 1,
                          red(H, OP_ALPHA), s);
@@ -638,8 +642,10 @@ int pcg64(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
         rr_prev = rr;
         const bool conv = std::sqrt(rr) <= target;
         // with the look-ahead the deferred x update has already been applied
-        if ((conv || st.iterations >= H->max_iter) && !ahead)
-            launch_axpy_alpha<double>(x, H->p, N, H->scal, s);
+        if ((conv || st.iterations >= H->max_iter) && !ahead) {
+            launch_axpy_alpha<double>(x, H->p, N, H->scal, s, H->x_unset);
+            H->x_unset = false;
+        }
         if (conv) {
             double rel;
             CHK(true_residual(H, b, x, H->z, bnorm, &rel));
@@ -1237,7 +1243,8 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
     int rc;
     if (F.split) {
         launch_relayout_in(b, H->bs, F.n[0], F.n[1], F.n[2], H->flag, 0, red(H, OP_STORE, S_BB), s, H->r);
-        launch_relayout_in(x, H->xs, F.n[0], F.n[1], F.n[2], H->flag, 2, red(H, OP_NONE), s);
+        // x is only checked here; it is relaid only where it is not zero
+        launch_relayout_in(x, nullptr, F.n[0], F.n[1], F.n[2], H->flag, 2, red(H, OP_NONE), s);
         b = H->bs;
         x = H->xs;
         if ((rc = check_launch())) return rc;
@@ -1248,10 +1255,12 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
             return fail(HP_ENAN, "rhs or initial guess contains non-finite values");
         }
         if (*H->host_flag & 2) {
+            launch_relayout_in(xu, H->xs, F.n[0], F.n[1], F.n[2], H->flag, 0, red(H, OP_NONE), s);
             launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR), s);
             if ((rc = check_launch()) || (rc = read_scalars(H))) return rc;
-        } else {  // x = 0: the initial residual is b itself, already in r
+        } else {  // x = 0: the initial residual is b itself, already in r; the split x stays unset
             H->host_scal[S_RR] = H->host_scal[S_BB];
+            H->x_unset = true;
         }
     } else {
         launch_check_finite(b, N, H->flag, s);
@@ -1276,14 +1285,22 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
         st.converged = 1;
         st.rel_residual = std::sqrt(H->host_scal[S_RR]) / bnorm;
         rc = HP_OK;
-    } else if (H->mode == HP_MODE_MIXED_IR) {
-        rc = mixed_ir(H, b, x, tol, bnorm);
-    } else if (H->mode == HP_MODE_LEARNED) {
-        rc = fcg_learned(H, b, x, tol, bnorm);
     } else {
-        rc = pcg64(H, b, x, tol, bnorm);
+        // only FP64 MG-PCG and Jacobi-PCG take an unset (zero) split iterate; the others get zeros
+        if (H->x_unset && (H->mode == HP_MODE_MIXED_IR || H->mode == HP_MODE_LEARNED)) {
+            launch_fill<double>(x, 0.0, N, s);
+            H->x_unset = false;
+        }
+        if (H->mode == HP_MODE_MIXED_IR)
+            rc = mixed_ir(H, b, x, tol, bnorm);
+        else if (H->mode == HP_MODE_LEARNED)
+            rc = fcg_learned(H, b, x, tol, bnorm);
+        else
+            rc = pcg64(H, b, x, tol, bnorm);
     }
-    if (F.split && bnorm != 0.0) relayout0<double>(H, x, xu, 0);
+    // an iterate that was never written is the caller's zero initial guess, already in place
+    if (F.split && bnorm != 0.0 && !H->x_unset) relayout0<double>(H, x, xu, 0);
+    H->x_unset = false;
     HIPCHK(hipEventRecord(H->ev1, s));
     HIPCHK(hipEventSynchronize(H->ev1));
     float ms = 0.0f;
