@@ -322,6 +322,27 @@ def test_update_coefficients_matches_fresh_setup():
     assert st["converged"] and relerr(host(x), xref) <= 1e-9
 
 
+@pytest.mark.parametrize("max_iter", [1, 2, 3])
+def test_capped_solves_from_zero_return_their_iterate(max_iter):
+    """A solve from a zero guess stopped after 1-3 iterations (HP_ENOCONV) returns its last
+    iterate: the first update writes x = alpha p into an iterate never written before (the zero
+    guess is only checked), on every path (the final update alone, or the look-ahead direction
+    update), and the reported residual is the oracle's residual of what comes back."""
+    p = problem(DEEP, 0.001)
+    b = wl.rhs_white(p.n, 12)
+    with make(p) as s:
+        s.set_option(hp.OPT_MAX_ITER, max_iter)
+        x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        st = s.solve(dev(b), x, tol=1e-10, check=False)
+    assert st["rc"] == hp.ENOCONV and st["iterations"] == max_iter
+    xg = host(x)
+    assert np.all(np.isfinite(xg)) and np.linalg.norm(xg) > 0.0
+    r = oracle.residual(p.n, p.h, p.bc, p.rho, p.c2, p.dt, xg, b)
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    assert abs(rel - st["rel_residual"]) <= 1e-8 * rel
+    assert rel < 1.0
+
+
 def test_kernel_timing_counts_the_finest_launches():
     """HP_OPT_KERNEL_TIMING: on a split finest level every operator apply of a new direction and
     both post-smoothing half sweeps of every V-cycle are timed (events attached to the
