@@ -7,9 +7,13 @@ rho = T^1.5, c2 = T, +-1% multiplicative noise from seed 0, periodic x/y, Neuman
 zero initial guess to true relative residual 1e-10 with FP64 multigrid-preconditioned CG.
 One step = one solve of a fresh right-hand side; inputs are resident in HBM before timing.
 
-Also reported on the same line: the Ma = 0.001 box with FP64 MG-PCG and with the mixed-precision
-form (speedup at the same accuracy), the roofline of the dominant kernel (measured with HIP
-events on the solver's stream), and the CPU oracle timed on the host cores on a bounded sample.
+Also reported on the same line: the Ma = 0.001 box with FP64 MG-PCG, the mixed-precision form
+and the learned forms (speedup at the same accuracy; every timed mixed-precision solve is
+compared with the FP64 solve of the same right-hand side), the roofline of the dominant kernel
+(measured with HIP events on the solver's stream) beside the whole solve's fraction, and the CPU
+oracle leg: the oracle timed on the host cores on a bounded sample, and its reference solution of
+the first timed right-hand side at both Mach numbers, against which every form's error is stated
+(computed after all timing).
 """
 from __future__ import annotations
 
@@ -57,8 +61,11 @@ def make_rhs(n, seeds, dev):
     return [torch.from_numpy(wl.rhs_white(n, s)).to(dev) for s in seeds]
 
 
-def run_solves(solver, rhs, x, warmup, steps):
-    """Warm up, then time `steps` solves (each from x = 0). Returns (seconds, stats list)."""
+def run_solves(solver, rhs, x, warmup, steps, keep=None):
+    """Warm up, then time `steps` solves (each from a zero initial guess). With `keep` (a list
+    of zeroed solution buffers, one per timed solve, resident before timing) every timed solve
+    writes its own buffer, so the solutions can be compared afterwards; else all use x (zeroed
+    inside the timed loop). Returns (seconds, stats list)."""
     import torch
     for k in range(warmup):
         x.zero_()
@@ -67,10 +74,18 @@ def run_solves(solver, rhs, x, warmup, steps):
     stats = []
     t0 = time.perf_counter()
     for k in range(steps):
-        x.zero_()
-        stats.append(solver.solve(rhs[warmup + k], x, tol=TOL))
+        if keep is None:
+            x.zero_()
+            stats.append(solver.solve(rhs[warmup + k], x, tol=TOL))
+        else:
+            stats.append(solver.solve(rhs[warmup + k], keep[k], tol=TOL))
     torch.cuda.synchronize()
     return time.perf_counter() - t0, stats
+
+
+def rel_diff(a, b):
+    """||a - b|| / ||b|| of two device vectors (FP64, on the GPU)."""
+    return float((a - b).norm() / b.norm())
 
 
 def kernel_time_ms(fn, reps=50):
@@ -151,10 +166,11 @@ def measured_traffic(kernel, n_cells):
     return d.get("per_launch_bytes", {}).get(kernel)
 
 
-def learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base):
+def learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base, sols):
     """The trained network at 256^3, Ma = 0.001: (a) warm start x0 = g net(b) followed by FP64
     MG-PCG, timed including the network; (b) flexible CG with the network + V-cycle
-    preconditioner. Both stop on the same FP64 true residual 1e-10."""
+    preconditioner. Both stop on the same FP64 true residual 1e-10. The solution of the first
+    timed solve of each form goes into sols (for its error against the oracle)."""
     import torch
     import paper_1112_3507_amd as hp
     from paper_1112_3507_amd import train as tr
@@ -168,24 +184,28 @@ def learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base):
     out = {}
     s = hp.setup(p3.n, p3.h, p3.bc, rho3, c23, p3.dt, hp.MODE_FP64_MGPCG)
     s.attach_net(net)
+    first = torch.zeros_like(x)
     for name in ("warm_start", "fcg"):
         log("bench: Ma=0.001 learned %s" % name)
         if name == "fcg":
             s.set_option(hp.OPT_MODE, hp.MODE_LEARNED)
         stats = []
+        first.zero_()
         for k in range(W + K):
             if k == W:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
+            xk = first if k == W else x
             if name == "warm_start":
-                s.warm_start(rhs[k], x)
-            else:
+                s.warm_start(rhs[k], xk)
+            elif k != W:
                 x.zero_()
-            st = s.solve(rhs[k], x, tol=TOL)
+            st = s.solve(rhs[k], xk, tol=TOL)
             if k >= W:
                 stats.append(st)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
+        sols["learned_" + name] = first.clone()
         v = K / secs
         out[name] = {"value": round(v, 3), "unit": "solves/s", "ms_per_step": round(1e3 * secs / K, 4),
                      "iterations_mean": sum(q["iterations"] for q in stats) / K,
@@ -227,6 +247,19 @@ def training_leg(dev, steps=10):
     return {"grid": [128, 128, 128], "ms_per_step": round(ms, 3), "steps_timed": steps}
 
 
+def host_cpu():
+    """CPU model name and the number of host threads the process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(p, b, n, mach, budget_s=15.0):
     """The FP64 oracle (CSR Jacobi-PCG) on the host cores, on a bounded sample of iterations.
 
@@ -249,11 +282,31 @@ def cpu_baseline(p, b, n, mach, budget_s=15.0):
     t0 = time.perf_counter()
     oracle.pcg_fixed(A, b, k)
     per_it = (time.perf_counter() - t0) / k
+    model, nproc = host_cpu()
     return {"value": 1.0 / (per_it * full_iterations), "unit": "solves/s",
             "cores": oracle.max_threads(), "kind": "oracle",
+            "cpu_model": model, "nproc": nproc,
             "sample": "%d Jacobi-PCG iterations of the CPU oracle on the same 256^3 input "
                       "(%.3f s/iteration), scaled by the %d iterations its full solve to 1e-10 "
                       "takes" % (k, per_it, full_iterations)}
+
+
+def oracle_errors(p, b, sols):
+    """Part of the CPU-oracle leg: the oracle's reference solution (Jacobi-PCG to a true
+    relative residual of 1e-13) of one timed right-hand side, and each GPU form's relative L2
+    and max-abs error against it. sols maps a form's name to its solution of b (device)."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    xref, st = oracle.reference_solve(p.n, p.h, p.bc, p.rho, p.c2, p.dt, b)
+    out = {"reference": {"iterations": st["iterations"], "rel_residual": st["rel_residual"],
+                         "seconds": round(time.perf_counter() - t0, 1)}}
+    xn = float(np.linalg.norm(xref))
+    xm = float(np.max(np.abs(xref)))
+    for name, xg in sols.items():
+        d = xg.detach().cpu().numpy().reshape(xref.shape) - xref
+        out[name] = {"rel_l2": float(np.linalg.norm(d)) / xn, "max_abs_rel": float(np.max(np.abs(d))) / xm}
+    return out
 
 
 def main():
@@ -293,7 +346,10 @@ def main():
     solver = hp.setup(p.n, p.h, p.bc, rho, c2, p.dt, hp.MODE_FP64_MGPCG)
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t0)
-    secs, stats = run_solves(solver, rhs, x, W, K)
+    keep = [torch.zeros_like(x) for _ in range(K)]
+    secs, stats = run_solves(solver, rhs, x, W, K, keep)
+    sols01 = {"fp64_mgpcg": keep[0].clone()}
+    del keep
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solver.update_coefficients(rho, c2, p.dt)
@@ -327,19 +383,28 @@ def main():
         "note": "whole-solve algorithmic bytes (model) / wall time per solve"}
     if not args.no_roofline:
         result["roofline"] = roofline(solver, rhs, x, p.ncells, dev, W)
+        # the kernel figure is cache-assisted (it reads what the previous pass left in the
+        # 256 MB memory-side cache); the whole solve's fraction is stated beside it
+        result["roofline"]["whole_solve_frac"] = result["mgpcg_effective"]["frac_of_peak"]
+        result["roofline"]["cache_assisted"] = result["roofline"]["copy_reference"]["frac_of_copy"] > 1.0
         log("bench: roofline %s" % json.dumps(result["roofline"]))
     solver.close()
 
+    sols001 = {}
     if not args.no_variants:
         p3 = wl.config1(mach=0.001, n=args.n)
         rho3, c23 = torch.from_numpy(p3.rho).to(dev), torch.from_numpy(p3.c2).to(dev)
         var = {}
         base = None
+        kept = {}
         for name, mode in (("fp64_mgpcg", hp.MODE_FP64_MGPCG), ("mixed_ir", hp.MODE_MIXED_IR)):
             log("bench: Ma=0.001 %s" % name)
             s3 = hp.setup(p3.n, p3.h, p3.bc, rho3, c23, p3.dt, mode)
-            secs3, st3 = run_solves(s3, rhs, x, W, K)
+            keep = [torch.zeros_like(x) for _ in range(K)]
+            secs3, st3 = run_solves(s3, rhs, x, W, K, keep)
             s3.close()
+            kept[name] = keep
+            sols001[name] = keep[0]
             v = K / secs3
             var[name] = {"value": round(v, 3), "unit": "solves/s",
                          "ms_per_step": round(1e3 * secs3 / K, 4),
@@ -350,8 +415,14 @@ def main():
             if base is None:
                 base = v
             var[name]["speedup_vs_fp64_mgpcg"] = round(v / base, 3)
+        # every timed mixed-precision solve against the FP64 solve of the same right-hand side
+        diffs = [rel_diff(a, b) for a, b in zip(kept["mixed_ir"], kept["fp64_mgpcg"])]
+        var["mixed_ir"]["rel_l2_vs_fp64_per_solve"] = [float("%.3e" % d) for d in diffs]
+        var["mixed_ir"]["max_rel_l2_vs_fp64"] = max(diffs)
+        sols001 = {k: v.clone() for k, v in sols001.items()}
+        del kept, keep
         result["ma0.001"] = var
-        lv = learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base)
+        lv = learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base, sols001)
         if lv is not None:
             var["learned_warm_start"] = lv["warm_start"]
             var["learned_fcg"] = lv["fcg"]
@@ -363,6 +434,16 @@ def main():
         from paper_1112_3507_amd import workloads as wl2
         b0 = wl2.rhs_white(n, seeds[W])
         result["cpu_baseline"] = cpu_baseline(p, b0, args.n, 0.01)
+        # the oracle's reference solutions of the first timed right-hand side: error of every
+        # form against the FP64 oracle (computed after all timing)
+        log("bench: oracle reference, Ma=0.01")
+        errs = {"rhs_seed": seeds[W], "ma0.01": oracle_errors(p, b0, sols01)}
+        if sols001:
+            log("bench: oracle reference, Ma=0.001")
+            errs["ma0.001"] = oracle_errors(wl.config1(mach=0.001, n=args.n), b0, sols001)
+        result["err_vs_oracle"] = errs
+        result["err_vs_oracle_max"] = max(v["rel_l2"] for m in ("ma0.01", "ma0.001") if m in errs
+                                          for k, v in errs[m].items() if k != "reference")
 
     print(json.dumps(result), flush=True)
 

@@ -197,7 +197,10 @@ int hp_precond_f32(hp_handle* h, const float* r, float* z);
  */
 int hp_residual(hp_handle* h, const double* rhs, const double* p, double* r, double* rel);
 
-/* Deterministic FP64 dot product of device vectors of n entries (synchronises the stream). */
+/* Deterministic FP64 dot product of device vectors of n entries (synchronises the stream); x and
+ * y may be NULL when n = 0 (the result is 0). Lengths whose first reduction stage needs more
+ * partial sums than the handle holds (it holds those of a vector of the fine grid's size) are
+ * HP_EINVAL. */
 int hp_dot(hp_handle* h, const double* x, const double* y, long long n, double* out);
 
 /* ---- Learned warm start / preconditioner -------------------------------------------------
@@ -250,12 +253,14 @@ int hp_nn_adam(hp_net* net, float lr);
 /* One Adam step on the relative A-norm error of the network's estimate of the solution x of
  * A x = b (A of the handle; the net must be a training network on the same grid):
  * loss = <e, A e> / <x, A x>, e = s * out_scale * net(b, log rho, log c2, p_prev) - x.
- * *loss receives the loss before the step (synchronises). */
+ * *loss receives the loss before the step (synchronises). Allocates the learned stage's work
+ * vectors on first use, as hp_attach_net does. */
 int hp_nn_train_step_anorm(hp_handle* h, hp_net* net, const double* b, const double* p_prev,
                            const double* x, float lr, double* loss);
 
 /* Use `net` (same grid as the handle; NULL detaches) in HP_MODE_LEARNED and hp_warm_start.
- * Allocates two work vectors of the fine grid. */
+ * Allocates the learned stage's three work vectors of the fine grid on first use (shared with
+ * hp_nn_train_step_anorm, whichever comes first). */
 int hp_attach_net(hp_handle* h, hp_net* net);
 
 /* Initial guess x = g y from the attached network, y = net(b, p_prev) (p_prev may be NULL), with

@@ -145,17 +145,17 @@ void launch_axpy2_norm(T* x, const T* p, T* r, const T* q, int64_t n, const RedC
 // p = z + beta p (beta = scal[S_BETA])
 template <typename T>
 void launch_xpby(const T* z, T* p, int64_t n, const double* scal, hipStream_t s);
-// deferred iterate update: r -= alpha q with ||r||^2 under rc; then x += alpha p and
-// p = z + beta p in one pass; x += alpha p alone where the iteration ends (alpha = scal[S_ALPHA])
-// (with g of a split finest level: in the tile order and direction of the split kernels)
-// (returns the number of per-workgroup partials of ||r||^2 it wrote)
+// deferred iterate update: r -= alpha q with ||r||^2 under rc (with g of a split finest level: in
+// the tile order and direction of the split kernels; returns the number of per-workgroup partials
+// of ||r||^2 it wrote); then x += alpha p and p = z + beta p in one flat pass over any layout;
+// x += alpha p alone where the iteration ends (alpha = scal[S_ALPHA])
 template <typename T>
 int launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s,
                      const Geo<T>* g = nullptr);
+// (xzero: x is known to be zero and is written, not read, by the update)
 template <typename T>
 void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s,
-                   const Geo<T>* g = nullptr, bool xzero = false);
-// (xzero: x is known to be zero and is written, not read, by the update; natural flat passes)
+                   bool xzero = false);
 template <typename T>
 void launch_axpy_alpha(T* x, const T* p, int64_t n, const double* scal, hipStream_t s, bool xzero = false);
 // z = dinv * r with <r, z> reduced

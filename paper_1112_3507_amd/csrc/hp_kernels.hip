@@ -2579,43 +2579,6 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_axpy_norm_zs(ZTiles zt, in
     export_flag(rc);
 }
 
-template <typename T, int XW>
-__global__ __launch_bounds__(64 * XW * kRowsS) void k_xpby_x_zs(ZTiles zt, int nx, int ny, int nz,
-                                                       const T* __restrict__ z, T* __restrict__ p,
-                                                       T* __restrict__ x, const double* __restrict__ scal) {
-    constexpr int kTW = 64 * XW;
-    int bx, by, bz;
-    ztile(zt, bx, by, bz);
-    const int hx = nx >> 1;
-    const int t = bx * kTW + (int)(threadIdx.x % kTW), j = by * kRowsS + (int)(threadIdx.x / kTW);
-    const int k0 = bz * zt.kz, k1 = min(k0 + zt.kz, nz);
-    if (t >= hx) return;
-    const T alpha = (T)scal[S_ALPHA], beta = (T)scal[S_BETA];
-    for (int k = k0; k < k1; k += 4) {
-        T zv[8], pv[8], xv[8];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int a = srow(j, min(k + u, k1 - 1), nx, ny) + t;
-            zv[2 * u] = z[a];
-            zv[2 * u + 1] = z[a + hx];
-            pv[2 * u] = p[a];
-            pv[2 * u + 1] = p[a + hx];
-            xv[2 * u] = x[a];
-            xv[2 * u + 1] = x[a + hx];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (k + u < k1) {
-                const int a = srow(j, k + u, nx, ny) + t;
-                x[a] = xv[2 * u] + alpha * pv[2 * u];
-                x[a + hx] = xv[2 * u + 1] + alpha * pv[2 * u + 1];
-                p[a] = zv[2 * u] + beta * pv[2 * u];
-                p[a + hx] = zv[2 * u + 1] + beta * pv[2 * u + 1];
-            }
-        }
-    }
-}
-
 template <typename T>
 int launch_axpy_norm(T* r, const T* q, int64_t n, const RedCtl& rc, hipStream_t s, const Geo<T>* g) {
     if (g && g->split) {
@@ -2654,19 +2617,7 @@ __global__ __launch_bounds__(kBlock) void k_xpby_x(const T* __restrict__ z, T* _
 }
 
 template <typename T>
-void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s, const Geo<T>* g,
-                   bool xzero) {
-    if (g && g->split) {
-        ZTiles zt = split_tiles(g->nx >> 1, g->ny, g->nz);
-        zt.rev = g->rev;
-        if (split_xw(g->nx >> 1) == 1)
-            hipLaunchKernelGGL((k_xpby_x_zs<T, 1>), dim3(zt.tx * zt.ty * zt.tz), split_block(g->nx >> 1), 0, s, zt,
-                               g->nx, g->ny, g->nz, z, p, x, scal);
-        else
-            hipLaunchKernelGGL((k_xpby_x_zs<T, 2>), dim3(zt.tx * zt.ty * zt.tz), split_block(g->nx >> 1), 0, s, zt,
-                               g->nx, g->ny, g->nz, z, p, x, scal);
-        return;
-    }
+void launch_xpby_x(const T* z, T* p, T* x, int64_t n, const double* scal, hipStream_t s, bool xzero) {
     if (xzero)
         hipLaunchKernelGGL((k_xpby_x<T, true>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            s, z, p, x, n, scal);
@@ -2817,8 +2768,7 @@ void launch_set_scalar(double* scal, int slot, double value, hipStream_t s) {
                                        hipStream_t);                                            \
     template int launch_axpy_norm<T>(T*, const T*, int64_t, const RedCtl&, hipStream_t,         \
                                       const Geo<T>*);                                             \
-    template void launch_xpby_x<T>(const T*, T*, T*, int64_t, const double*, hipStream_t,       \
-                                   const Geo<T>*, bool);                                          \
+    template void launch_xpby_x<T>(const T*, T*, T*, int64_t, const double*, hipStream_t, bool); \
     template void launch_axpy_alpha<T>(T*, const T*, int64_t, const double*, hipStream_t, bool);\
     template void launch_xpby<T>(const T*, T*, int64_t, const double*, hipStream_t);            \
     template void launch_fill<T>(T*, T, int64_t, hipStream_t);                                  \

@@ -589,7 +589,7 @@ void next_direction64(hp_handle* H, double* x, bool pre_done = false) {
     LevelData& F = H->lv[0];
     hipStream_t s = H->stream;
     precond64(H, H->r, H->z, OP_BETA, pre_done);
-    launch_xpby_x<double>(H->z, H->p, x, F.N, H->scal, s, nullptr, H->x_unset);
+    launch_xpby_x<double>(H->z, H->p, x, F.N, H->scal, s, H->x_unset);
     H->x_unset = false;
     time_begin(H, TIME_APPLY);
     launch_apply<double>(geo_pass(H, geo<double>(H, F), 0), F.rho, F.m, H->p, nullptr, H->q, 1,
@@ -775,6 +775,19 @@ int mixed_ir(hp_handle* H, const double* b, double* x, double tol, double bnorm)
                 st.rel_residual);
 }
 
+// The three fine-grid work vectors of the learned stage (warm start, FCG preconditioner, A-norm
+// training step), allocated together on first use by whichever of those calls comes first.
+int ensure_net_work(hp_handle* H) {
+    const int64_t N = H->lv[0].N;
+    int rc;
+    if (!H->w1 && (rc = dalloc(H, &H->w1, N))) return rc;
+    if (!H->w2 && (rc = dalloc(H, &H->w2, N))) return rc;
+    if (!H->w3 && (rc = dalloc(H, &H->w3, N))) return rc;
+    return HP_OK;
+}
+
+bool net_work_ready(const hp_handle* H) { return H->w1 && H->w2 && H->w3; }
+
 // Flexible CG (Notay's FCG with one stored direction) with the preconditioner
 // B(r) = g z1 + M (r - g A z1), z1 = network estimate of A^-1 r, M = one V-cycle, and
 // g = <r, z1> / <z1, A z1> the step that minimises the A-norm error of g z1 (0 if the network
@@ -786,6 +799,7 @@ int mixed_ir(hp_handle* H, const double* b, double* x, double tol, double bnorm)
 // modes.
 int fcg_learned(hp_handle* H, const double* b, double* x, double tol, double bnorm) {
     if (!H->net) return fail(HP_EINVAL, "HP_MODE_LEARNED needs a network (hp_attach_net)");
+    if (!net_work_ready(H)) return fail(HP_EINVAL, "learned-stage work vectors are missing");
     LevelData& F = H->lv[0];
     const int64_t N = F.N;
     Geo<double> g = geo<double>(H, F);
@@ -1387,12 +1401,7 @@ int hp_attach_net(hp_handle* H, hp_net* net) {
         if (nx != F.n[0] || ny != F.n[1] || nz != F.n[2])
             return fail(HP_EINVAL, "network grid %dx%dx%d differs from the solver grid %dx%dx%d", nx, ny,
                         nz, F.n[0], F.n[1], F.n[2]);
-        if (!H->w1) {
-            int rc;
-            if ((rc = dalloc(H, &H->w1, F.N)) || (rc = dalloc(H, &H->w2, F.N)) ||
-                (rc = dalloc(H, &H->w3, F.N)))
-                return rc;
-        }
+        CHK(ensure_net_work(H));
     }
     H->net = net;
     return HP_OK;
@@ -1403,6 +1412,7 @@ int hp_warm_start(hp_handle* H, const double* b, const double* p_prev, double* x
     g_err.clear();
     if (!H->net) return fail(HP_EINVAL, "hp_warm_start needs a network (hp_attach_net)");
     if (!b || !x) return fail(HP_EINVAL, "null vector");
+    if (!net_work_ready(H)) return fail(HP_EINVAL, "learned-stage work vectors are missing");
     LevelData& F = H->lv[0];
     const int64_t N = F.N;
     hipStream_t s = H->stream;
@@ -1438,10 +1448,7 @@ int hp_nn_train_step_anorm(hp_handle* H, hp_net* net, const double* b, const dou
     nn_grid(net, &nx, &ny, &nz);
     LevelData& F = H->lv[0];
     if (nx != F.n[0] || ny != F.n[1] || nz != F.n[2]) return fail(HP_EINVAL, "network grid differs from the solver grid");
-    if (!H->w1) {
-        int rc;
-        if ((rc = dalloc(H, &H->w1, F.N)) || (rc = dalloc(H, &H->w2, F.N))) return rc;
-    }
+    CHK(ensure_net_work(H));
     const int64_t N = F.N;
     hipStream_t s = H->stream;
     Geo<double> g = geo<double>(H, F);
@@ -1482,7 +1489,7 @@ int hp_nn_train_step_anorm(hp_handle* H, hp_net* net, const double* b, const dou
 }
 
 int hp_dot(hp_handle* H, const double* x, const double* y, long long n, double* out) {
-    if (!H || !x || !y || !out) return fail(HP_EINVAL, "null argument");
+    if (!H || !out || (n > 0 && (!x || !y))) return fail(HP_EINVAL, "null argument");
     if (n < 0 || reduce_blocks_vec(n) > H->partial_cap) return fail(HP_EINVAL, "bad length");
     launch_dot<double>(x, y, n, red(H, OP_STORE, S_TMP), H->stream);
     CHK(check_launch());

@@ -260,3 +260,99 @@ def test_trained_network_gain():
     for kind in ("white", "smooth"):
         assert report[(kind, "trained")][0] < report[(kind, "untrained")][0]
         assert report[(kind, "trained")][0] < 0.9
+
+
+@pytest.mark.parametrize("with_prev", [False, True])
+def test_physical_units_path_matches_oracle(with_prev):
+    """hp_nn_forward and hp_warm_start in physical units against the oracle: the features
+    (b/s, log rho, log c2, p_prev/s with s = RMS(b)), the bfloat16 network, the output scaling
+    s * out_scale, and for the warm start the A-norm-optimal step g = <b, y> / <y, A y> with A the
+    oracle's operator. 256-wide rows (the split finest level with two-wave row tiles)."""
+    n = (256, 16, 16)
+    p = wl.polytrope(n, 0.001, seed=31)
+    rng = np.random.default_rng(32)
+    b = wl.rhs_white(n, 33) * 7.5
+    pp = rng.standard_normal(p.shape) * 3.0 if with_prev else np.zeros(p.shape)
+    theta = (nn.init_params(9) + 0.02 * rng.standard_normal(nn.num_params())).astype(np.float32)
+    out_scale = 2.5e-4
+    inp, s = nn.features(b, p.rho, p.c2, pp)
+    x_ref = s * out_scale * nn.forward(theta.astype(np.float64), inp, bf16=True)
+    A = oracle.assemble(p.n, p.h, p.bc, p.rho, p.c2, p.dt)
+    ax = A.matvec(x_ref).reshape(p.shape)
+    g_ref = float(np.sum(b * x_ref) / np.sum(x_ref * ax))
+    assert g_ref > 0.0
+
+    rho = torch.from_numpy(p.rho).to(DEV)
+    c2 = torch.from_numpy(p.c2).to(DEV)
+    bt = torch.from_numpy(b).to(DEV)
+    ppt = torch.from_numpy(pp).to(DEV) if with_prev else None
+    net = hp.Net(n)
+    net.set_params(torch.from_numpy(theta).to(DEV))
+    net.set_output_scale(out_scale)
+    x = torch.empty_like(bt)
+    net.forward(bt, rho, c2, ppt, x)
+    with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as sv:
+        assert sv.get_option(hp.OPT_LAYOUT) == 1
+        sv.attach_net(net)
+        xw = torch.empty_like(bt)
+        sv.warm_start(bt, xw, p_prev=ppt)
+        sv.attach_net(None)
+    torch.cuda.synchronize()
+    xg, xwg = x.cpu().numpy(), xw.cpu().numpy()
+    err = np.linalg.norm(xg - x_ref) / np.linalg.norm(x_ref)
+    # Both sides round the features, ten convolution outputs and two pooled tensors to bfloat16
+    # (8-bit significand: one unit in the last place is 2^-8 = 3.9e-3 relative); FP32 (MFMA)
+    # against FP64 accumulation flips a few of those roundings by one unit, which moves the
+    # output by a few 1e-3 relative. The bar is four units in the last place.
+    tol = 4 * 2.0 ** -8
+    print("physical units (p_prev=%s): forward rel err %.2e (bar %.2e), g_ref %.4e"
+          % (with_prev, err, tol, g_ref), flush=True)
+    assert err <= tol, err
+    # the bar separates the right features and scaling from plausible mistakes: the oracle with
+    # log rho and log c2 swapped, with p_prev not divided by s, or with the output not scaled by
+    # s is at least four bars away
+    wrong = [inp[..., [0, 2, 1, 3]], ]
+    if with_prev:
+        wrong.append(np.concatenate([inp[..., :3], pp[..., None]], axis=-1))
+    for wi in wrong:
+        xw_ref = s * out_scale * nn.forward(theta.astype(np.float64), wi, bf16=True)
+        assert np.linalg.norm(xg - xw_ref) / np.linalg.norm(x_ref) > 4 * tol
+    assert abs(s - 1.0) > 0.5 and np.linalg.norm(xg - x_ref / s) / np.linalg.norm(x_ref) > 4 * tol
+    werr = np.linalg.norm(xwg - g_ref * x_ref) / np.linalg.norm(g_ref * x_ref)
+    assert werr <= 2 * tol, werr
+    # g is the A-norm-optimal step <b, y> / <y, A y>: the GPU's agrees with the oracle's to the
+    # network's own deviation, and differs by orders of magnitude from <b, y> / <y, y>
+    g_gpu = float(np.sum(xwg * xg) / np.sum(xg * xg))
+    assert abs(g_gpu - g_ref) <= 2 * tol * g_ref, (g_gpu, g_ref)
+    g_wrong = float(np.sum(b * x_ref) / np.sum(x_ref * x_ref))
+    assert abs(g_wrong - g_ref) > 10.0 * g_ref
+    net.close()
+
+
+def test_train_then_attach_then_learned_solve():
+    """The A-norm training step may come before hp_attach_net: the learned stage's work vectors
+    are then allocated by the training step, and a learned (FCG) solve on the split finest level
+    afterwards meets the bar against the oracle."""
+    n = (64, 16, 16)
+    p = wl.polytrope(n, 0.001, seed=41)
+    b = wl.rhs_white(n, 42)
+    xref, _ = oracle.reference_solve(p.n, p.h, p.bc, p.rho, p.c2, p.dt, b)
+    rho = torch.from_numpy(p.rho).to(DEV)
+    c2 = torch.from_numpy(p.c2).to(DEV)
+    bt = torch.from_numpy(b).to(DEV)
+    net = hp.Net(n, training=True)
+    net.set_params(torch.from_numpy(nn.init_params(10).astype(np.float32)).to(DEV))
+    net.set_output_scale(float(np.linalg.norm(xref) / np.linalg.norm(b)))
+    with hp.setup(p.n, p.h, p.bc, rho, c2, p.dt) as s:
+        assert s.get_option(hp.OPT_LAYOUT) == 1
+        xt = torch.from_numpy(xref).to(DEV)
+        loss = s.train_step_anorm(net, bt, xt, 1e-4)
+        assert np.isfinite(loss)
+        s.attach_net(net)
+        s.set_option(hp.OPT_MODE, hp.MODE_LEARNED)
+        x = torch.zeros_like(bt)
+        st = s.solve(bt, x, tol=1e-10)
+    torch.cuda.synchronize()
+    assert st["converged"] and st["rel_residual"] <= 1e-10
+    assert np.linalg.norm(x.cpu().numpy() - xref) / np.linalg.norm(xref) <= 1e-9
+    net.close()

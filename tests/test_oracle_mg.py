@@ -144,3 +144,27 @@ def test_vcycle_preconditioned_cg_reaches_oracle():
         its += 1
         assert its < 40
     assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("flags", [(True, True, True), (True, False, True), (False, True, False)])
+def test_child_mean_of_an_affine_field_is_its_centroid_value(flags):
+    """The coarse coefficients are 8-child (or 4-, 2-child) means: for the affine field
+    a(i, j, k) = i + 10 j + 100 k (exact in FP64) the mean over the children of coarse cell
+    (I, J, K) is the field at the children's centroid, e.g. 2I + 1/2 in x on a coarsened axis and
+    I itself on one that is not coarsened."""
+    nz, ny, nx = 6, 4, 8
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a = i + 10.0 * j + 100.0 * k
+    got = mg.child_mean(a, flags)
+    fx, fy, fz = (2 if flags[0] else 1), (2 if flags[1] else 1), (2 if flags[2] else 1)
+    assert got.shape == (nz // fz, ny // fy, nx // fx)
+    K, J, I = np.meshgrid(np.arange(nz // fz), np.arange(ny // fy), np.arange(nx // fx), indexing="ij")
+    cx = fx * I + (0.5 if flags[0] else 0.0)
+    cy = fy * J + (0.5 if flags[1] else 0.0)
+    cz = fz * K + (0.5 if flags[2] else 0.0)
+    assert np.array_equal(got, cx + 10.0 * cy + 100.0 * cz)
+    # a positive field keeps its total (mean preserving) and stays within the children's range
+    b = np.random.default_rng(4).uniform(0.5, 2.0, (nz, ny, nx))
+    cb = mg.child_mean(b, flags)
+    assert abs(cb.sum() * fx * fy * fz - b.sum()) <= 1e-12 * b.sum()
+    assert cb.min() >= b.min() and cb.max() <= b.max()

@@ -94,3 +94,38 @@ def test_bf16_round_matches_torch():
     a = rng.standard_normal(10000) * 10.0 ** rng.uniform(-5, 5, 10000)
     ref = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(nn.bf16_round(a), ref)
+
+
+def test_features_hand_built_2x2x2():
+    """Input channels of the network (b / s, log rho, log c2, p_prev / s, s = RMS(b)) on a
+    hand-built 2x2x2 input whose values are exact: b = +-2 gives s = 2, rho = e^k, c2 = e^-k,
+    p_prev = 2k."""
+    k = np.arange(8, dtype=np.float64).reshape(2, 2, 2)
+    b = np.where(k % 2 == 0, 2.0, -2.0)
+    rho = np.exp(k)
+    c2 = np.exp(-k)
+    inp, s = nn.features(b, rho, c2, 2.0 * k)
+    assert s == 2.0 and inp.shape == (2, 2, 2, 4)
+    assert np.array_equal(inp[..., 0], np.where(k % 2 == 0, 1.0, -1.0))
+    assert np.allclose(inp[..., 1], k, rtol=0, atol=1e-15)
+    assert np.allclose(inp[..., 2], -k, rtol=0, atol=1e-15)
+    assert np.array_equal(inp[..., 3], k)
+
+
+def test_features_scale_invariance_and_mass_term():
+    """Scaling b and p_prev together leaves every channel unchanged and scales s; log c2 equals
+    -log(rho m) with the mass term m = 1 / (rho c2) the solver holds; b = 0 gives s = 1."""
+    rng = np.random.default_rng(7)
+    shape = (3, 4, 5)
+    b = rng.standard_normal(shape)
+    rho = rng.uniform(0.5, 30.0, shape)
+    c2 = rng.uniform(1.0, 10.0, shape)
+    pp = rng.standard_normal(shape)
+    inp, s = nn.features(b, rho, c2, pp)
+    assert np.isclose(s, np.sqrt(np.mean(b * b)), rtol=1e-15)
+    inp2, s2 = nn.features(8.0 * b, rho, c2, 8.0 * pp)
+    assert s2 == 8.0 * s and np.array_equal(inp2, inp)
+    m = 1.0 / (rho * c2)
+    assert np.allclose(inp[..., 2], -np.log(rho * m), rtol=0, atol=1e-14)
+    z, s0 = nn.features(np.zeros(shape), rho, c2, np.zeros(shape))
+    assert s0 == 1.0 and not np.any(z[..., 0]) and not np.any(z[..., 3])
