@@ -144,6 +144,41 @@ int hp_get_option(const hp_handle* h, int key, double* value);
  */
 int hp_update_coefficients(hp_handle* h, const double* rho, const double* c2, double dt);
 
+/*
+ * The operator with the two densities of eqs. cpoiss and kappapoiss (Section 2): the mass term
+ * takes the density of time level n and the face coefficient that of time level n+1,
+ *
+ *     m_a = 1 / (rho_n_a c2_a),   w_f = dt^2 * (2 / (rho_np1_a + rho_np1_b)) / h_d^2.
+ *
+ *   rho_n, rho_np1, c2  device FP64 cell arrays (natural layout), copied; all must be positive
+ *                       and finite (HP_EDOMAIN otherwise).
+ * Everything else is as hp_setup / hp_update_coefficients (which are these calls with
+ * rho_np1 = rho_n). The learned stage then sees log rho_np1 and -log(rho_np1 m) as its
+ * coefficient channels.
+ */
+int hp_setup_two_density(const hp_grid* grid, const double* rho_n, const double* rho_np1,
+                         const double* c2, double dt, const hp_bc* bc, hp_handle** out);
+int hp_update_coefficients_two_density(hp_handle* h, const double* rho_n, const double* rho_np1,
+                                       const double* c2, double dt);
+
+/*
+ * Inhomogeneous Neumann data (the stability problem of Section 2 prescribes the outward normal
+ * derivative of the solution on the boundary): adds the known boundary flux to the right-hand
+ * side of the cells next to boundary `side` (0: low, 1: high) of `axis` (0 x, 1 y, 2 z), which
+ * must be a Neumann axis of the handle (the operator itself keeps no flux there):
+ *
+ *     rhs_a += dt^2 q_f / h_axis
+ *
+ *   q    device FP64, one value per boundary face: the prescribed outward normal flux
+ *        kappa dphi/dn (with kappa = 1, as in the stability problem, the normal derivative; a
+ *        caller with derivative data g and face coefficient kappa passes kappa g), indexed over the
+ *        plane of the two other axes with the lower-numbered axis fastest
+ *        (axis x: j + ny k; axis y: i + nx k; axis z: i + nx j); read only.
+ *   rhs  device FP64 cell array (natural layout), updated in place; stream-ordered, no sync.
+ * Errors: HP_EINVAL (null pointer, axis or side out of range, axis not Neumann), HP_EHIP.
+ */
+int hp_neumann_rhs(hp_handle* h, int axis, int side, const double* q, double* rhs);
+
 int hp_get_stats(const hp_handle* h, hp_stats* out);
 
 /* Thread-local message of the last error ("" if none). */

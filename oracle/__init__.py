@@ -9,6 +9,10 @@ step (viii) of the fractional-step algorithm), multiplied by dt^2:
     (A p)_a = m_a p_a + sum_{faces f at a} w_f (p_a - p_b),
     m_a = 1 / (rho_a c2_a),   w_f = dt^2 * (2 / (rho_a + rho_b)) / h_d^2.
 
+With two densities (eqs. cpoiss and kappapoiss: rho^n in the mass term, rho^{n+1} in kappa) the
+functions take ``rho`` as rho^n and ``rho_face`` as rho^{n+1}: m_a = 1 / (rho^n_a c2_a) and
+w_f = dt^2 (2 / (rho^{n+1}_a + rho^{n+1}_b)) / h_d^2. ``rho_face=None`` means rho^{n+1} = rho^n.
+
 Arrays are cell-centred, shaped (nz, ny, nx) in C order (x fastest). ``bc`` holds one entry per
 axis (x, y, z): 0 = periodic, 1 = homogeneous Neumann.
 
@@ -71,14 +75,17 @@ def _load():
             i64_p = P(ctypes.c_int64)
             lib.or_ncells.restype = ctypes.c_int64
             lib.or_ncells.argtypes = [P(_Grid)]
-            lib.or_assemble.restype = ctypes.c_int64
-            lib.or_assemble.argtypes = [P(_Grid), d_p, d_p, ctypes.c_double, i64_p, i64_p, d_p]
+            lib.or_assemble2.restype = ctypes.c_int64
+            lib.or_assemble2.argtypes = [P(_Grid), d_p, d_p, d_p, ctypes.c_double, i64_p, i64_p, d_p]
             lib.or_spmv.restype = None
             lib.or_spmv.argtypes = [ctypes.c_int64, i64_p, i64_p, d_p, d_p, d_p]
             lib.or_dot.restype = ctypes.c_double
             lib.or_dot.argtypes = [ctypes.c_int64, d_p, d_p]
-            lib.or_residual_mf.restype = None
-            lib.or_residual_mf.argtypes = [P(_Grid), d_p, d_p, ctypes.c_double, d_p, d_p, d_p]
+            lib.or_residual_mf2.restype = None
+            lib.or_residual_mf2.argtypes = [P(_Grid), d_p, d_p, d_p, ctypes.c_double, d_p, d_p, d_p]
+            lib.or_neumann_rhs.restype = None
+            lib.or_neumann_rhs.argtypes = [P(_Grid), ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                           d_p, d_p]
             lib.or_pcg.restype = ctypes.c_int
             lib.or_pcg.argtypes = [ctypes.c_int64, i64_p, i64_p, d_p, d_p, d_p, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_int, d_p, d_p, ctypes.c_int,
@@ -141,31 +148,54 @@ class CSR:
         return self.to_scipy().toarray()
 
 
-def assemble(n, h, bc, rho, c2, dt) -> CSR:
+def assemble(n, h, bc, rho, c2, dt, rho_face=None) -> CSR:
     """Assemble A (see module docstring) by looping over faces; duplicate faces are summed."""
     lib = _load()
     g = _grid(n, h, bc)
     N = int(lib.or_ncells(ctypes.byref(g)))
     rho = _f64(rho, N)
     c2 = _f64(c2, N)
+    rf = rho if rho_face is None else _f64(rho_face, N)
     rowptr = np.zeros(N + 1, dtype=np.int64)
     colind = np.zeros(7 * N, dtype=np.int64)
     val = np.zeros(7 * N, dtype=np.float64)
-    nnz = lib.or_assemble(ctypes.byref(g), _dptr(rho), _dptr(c2), float(dt), _iptr(rowptr),
-                          _iptr(colind), _dptr(val))
+    nnz = lib.or_assemble2(ctypes.byref(g), _dptr(rho), _dptr(rf), _dptr(c2), float(dt),
+                           _iptr(rowptr), _iptr(colind), _dptr(val))
     return CSR(rowptr, colind[:nnz].copy(), val[:nnz].copy())
 
 
-def residual(n, h, bc, rho, c2, dt, x, b) -> np.ndarray:
+def residual(n, h, bc, rho, c2, dt, x, b, rho_face=None) -> np.ndarray:
     """Matrix-free r = b - A x (same face definition, no CSR; any size that fits in memory)."""
     lib = _load()
     g = _grid(n, h, bc)
     N = int(lib.or_ncells(ctypes.byref(g)))
     rho, c2, x, b = _f64(rho, N), _f64(c2, N), _f64(x, N), _f64(b, N)
+    rf = rho if rho_face is None else _f64(rho_face, N)
     r = np.empty(N, dtype=np.float64)
-    lib.or_residual_mf(ctypes.byref(g), _dptr(rho), _dptr(c2), float(dt), _dptr(x), _dptr(b),
-                       _dptr(r))
+    lib.or_residual_mf2(ctypes.byref(g), _dptr(rho), _dptr(rf), _dptr(c2), float(dt), _dptr(x),
+                        _dptr(b), _dptr(r))
     return r
+
+
+def neumann_rhs(n, h, bc, dt, axis: int, side: int, q, b=None) -> np.ndarray:
+    """Right-hand side term of inhomogeneous Neumann data: for every cell next to boundary `side`
+    (0 low, 1 high) of the Neumann axis `axis` (0 x, 1 y, 2 z), b += dt^2 q / h_axis with q the
+    prescribed outward normal flux kappa dphi/dn through that boundary face. q is shaped like the
+    boundary plane of the (nz, ny, nx) array with that axis removed. Returns b (a new zero array
+    if b is None), shaped (nz, ny, nx)."""
+    lib = _load()
+    if bc[axis] != NEUMANN:
+        raise ValueError("Neumann data needs a Neumann axis")
+    gr = _grid(n, h, bc)
+    N = int(lib.or_ncells(ctypes.byref(gr)))
+    out = np.zeros(N) if b is None else _f64(b, N).copy()
+    qv = _f64(q)
+    others = [d for d in range(3) if d != axis]
+    if qv.size != n[others[0]] * n[others[1]]:
+        raise ValueError("boundary data has %d entries, the boundary has %d faces"
+                         % (qv.size, n[others[0]] * n[others[1]]))
+    lib.or_neumann_rhs(ctypes.byref(gr), float(dt), int(axis), int(side), _dptr(qv), _dptr(out))
+    return out.reshape(n[2], n[1], n[0])
 
 
 def dot(x, y) -> float:
@@ -204,17 +234,18 @@ def pcg_fixed(A: CSR, b, iters: int) -> float:
 
 
 def solve(n, h, bc, rho, c2, dt, b, x0=None, tol=1e-10, maxiter=1_000_000, stag_window=0,
-          coef_cap=0):
+          coef_cap=0, rho_face=None):
     """Assemble and solve A x = b with Jacobi-PCG. Returns (x shaped like b, stats)."""
     shape = np.shape(b)
-    A = assemble(n, h, bc, rho, c2, dt)
+    A = assemble(n, h, bc, rho, c2, dt, rho_face)
     x, st = pcg(A, b, x0, tol, maxiter, stag_window, coef_cap)
     return x.reshape(shape), st
 
 
-def reference_solve(n, h, bc, rho, c2, dt, b, maxiter=1_000_000):
+def reference_solve(n, h, bc, rho, c2, dt, b, maxiter=1_000_000, rho_face=None):
     """Reference solution for parity: tol 1e-13 or stagnation of the true residual."""
-    return solve(n, h, bc, rho, c2, dt, b, tol=1e-13, maxiter=maxiter, stag_window=50)
+    return solve(n, h, bc, rho, c2, dt, b, tol=1e-13, maxiter=maxiter, stag_window=50,
+                 rho_face=rho_face)
 
 
 def lanczos_extremes(alpha: np.ndarray, beta: np.ndarray):

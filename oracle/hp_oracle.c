@@ -13,6 +13,11 @@
  * multiplied through by dt^2, so that the mass term is m = 1/(rho c^2) and the right-hand side
  * is b = dt^2 f (the relative residual is unchanged by this positive scaling).
  *
+ * Two densities (eqs. cpoiss and kappapoiss): the mass term takes the density of time level n,
+ * m = 1/(rho^n c^2), and the face coefficient that of time level n+1, kappa = 1/rho^{n+1}. The
+ * "2" entry points take both (rho_mass = rho^n, rho_face = rho^{n+1}); the one-density entry
+ * points pass the same array for both.
+ *
  * Discretization (cell-centred finite volumes on an equidistant rectangular grid; the paper's
  * Section 5 grid description): cell a = (i, j, k), centre ((i+1/2) hx, (j+1/2) hy, (k+1/2) hz).
  * For every pair of cells (a, b) adjacent along axis d there is a face f with
@@ -88,8 +93,8 @@ int64_t or_ncells(const or_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2
  * rowptr has ncells+1 entries; colind/val must hold 7*ncells entries.
  * Returns the number of nonzeros.
  */
-int64_t or_assemble(const or_grid* g, const double* rho, const double* c2, double dt,
-                    int64_t* rowptr, int64_t* colind, double* val) {
+int64_t or_assemble2(const or_grid* g, const double* rho_mass, const double* rho_face,
+                     const double* c2, double dt, int64_t* rowptr, int64_t* colind, double* val) {
     int64_t N = or_ncells(g);
     /* first pass: count distinct columns per row */
     int64_t* cnt = (int64_t*)calloc((size_t)N, sizeof(int64_t));
@@ -124,7 +129,7 @@ int64_t or_assemble(const or_grid* g, const double* rho, const double* c2, doubl
         int64_t cols[7];
         double vals[7];
         int nc = 0;
-        double m = 1.0 / (rho[a] * c2[a]);
+        double m = 1.0 / (rho_mass[a] * c2[a]);
         cols[nc] = a;
         vals[nc] = m;
         nc++;
@@ -132,7 +137,7 @@ int64_t or_assemble(const or_grid* g, const double* rho, const double* c2, doubl
             for (int s = -1; s <= 1; s += 2) {
                 int64_t b = or_neighbor(g, i, j, k, d, s);
                 if (b < 0) continue;
-                double kappa = 2.0 / (rho[a] + rho[b]);
+                double kappa = 2.0 / (rho_face[a] + rho_face[b]);
                 double w = dt2 * kappa / (g->h[d] * g->h[d]);
                 vals[0] += w; /* diagonal */
                 int q;
@@ -167,6 +172,11 @@ int64_t or_assemble(const or_grid* g, const double* rho, const double* c2, doubl
     return rowptr[N];
 }
 
+int64_t or_assemble(const or_grid* g, const double* rho, const double* c2, double dt,
+                    int64_t* rowptr, int64_t* colind, double* val) {
+    return or_assemble2(g, rho, rho, c2, dt, rowptr, colind, val);
+}
+
 /* y = A x (CSR) */
 void or_spmv(int64_t N, const int64_t* rowptr, const int64_t* colind, const double* val,
              const double* x, double* y) {
@@ -199,8 +209,8 @@ double or_dot(int64_t N, const double* x, const double* y) {
  * Matrix-free residual r = b - A x straight from the face definition (no CSR), for sizes where
  * the CSR matrix does not fit. Used to certify a solution returned by another solver.
  */
-void or_residual_mf(const or_grid* g, const double* rho, const double* c2, double dt,
-                    const double* x, const double* b, double* r) {
+void or_residual_mf2(const or_grid* g, const double* rho_mass, const double* rho_face,
+                     const double* c2, double dt, const double* x, const double* b, double* r) {
     int64_t N = or_ncells(g);
     double dt2 = dt * dt;
 #pragma omp parallel for schedule(static)
@@ -208,16 +218,48 @@ void or_residual_mf(const or_grid* g, const double* rho, const double* c2, doubl
         int i = (int)(a % g->n[0]);
         int j = (int)((a / g->n[0]) % g->n[1]);
         int k = (int)(a / ((int64_t)g->n[0] * g->n[1]));
-        double ax = x[a] / (rho[a] * c2[a]);
+        double ax = x[a] / (rho_mass[a] * c2[a]);
         for (int d = 0; d < 3; ++d)
             for (int s = -1; s <= 1; s += 2) {
                 int64_t nb = or_neighbor(g, i, j, k, d, s);
                 if (nb < 0) continue;
-                double w = dt2 * (2.0 / (rho[a] + rho[nb])) / (g->h[d] * g->h[d]);
+                double w = dt2 * (2.0 / (rho_face[a] + rho_face[nb])) / (g->h[d] * g->h[d]);
                 ax += w * (x[a] - x[nb]);
             }
         r[a] = b[a] - ax;
     }
+}
+
+void or_residual_mf(const or_grid* g, const double* rho, const double* c2, double dt,
+                    const double* x, const double* b, double* r) {
+    or_residual_mf2(g, rho, rho, c2, dt, x, b, r);
+}
+
+/*
+ * Inhomogeneous Neumann data on one boundary (the stability problem of Section 2 prescribes the
+ * outward normal derivative of the solution on the x boundaries). The datum is the outward normal
+ * flux q = kappa dphi/dn through each boundary face (for the stability problem kappa = 1, so
+ * q = dphi/dn; a perturbation of kappa leaves the prescribed flux unchanged). The operator keeps
+ * no flux there, so in the dt^2-scaled equation the known flux moves to the right-hand side:
+ *
+ *     b_a += dt^2 q / h_d
+ *
+ * for every cell a next to boundary `side` (0: low, 1: high) of axis d, which must be a Neumann
+ * axis. q holds one value per boundary face, indexed over the plane of the two other axes with
+ * the lower-numbered axis fastest (x: j + ny k; y: i + nx k; z: i + nx j).
+ */
+void or_neumann_rhs(const or_grid* g, double dt, int d, int side, const double* q, double* b) {
+    int e0 = d == 0 ? 1 : 0, e1 = d == 2 ? 1 : 2;  /* the two other axes, lower first */
+    int n0 = g->n[e0], n1 = g->n[e1];
+    double f = dt * dt / g->h[d];
+    for (int v = 0; v < n1; ++v)
+        for (int u = 0; u < n0; ++u) {
+            int c[3];
+            c[d] = side ? g->n[d] - 1 : 0;
+            c[e0] = u;
+            c[e1] = v;
+            b[or_cell(g, c[0], c[1], c[2])] += f * q[u + (int64_t)n0 * v];
+        }
 }
 
 /*
@@ -256,6 +298,7 @@ int or_pcg(int64_t N, const int64_t* rowptr, const int64_t* colind, const double
     }
     double bnorm = sqrt(or_dot(N, b, b));
     int status = 1;
+    int it = 0; /* before the first jump to done, which reads it */
     if (bnorm == 0.0) {
         memset(x, 0, (size_t)N * sizeof(double));
         st->converged = 1;
@@ -276,7 +319,6 @@ int or_pcg(int64_t N, const int64_t* rowptr, const int64_t* colind, const double
     }
     int restart = 1;
     double rz = 0.0;
-    int it = 0;
     while (it < maxiter) {
         if (restart) {
 #pragma omp parallel for schedule(static)

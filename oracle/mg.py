@@ -59,10 +59,14 @@ def can_coarsen(n: int, bc: int) -> bool:
     return True
 
 
-def build_hierarchy(n, h, bc, rho, c2, dt, coarsest_max: int = 512):
+def build_hierarchy(n, h, bc, rho, c2, dt, coarsest_max: int = 512, rho_face=None):
+    """Levels from the fine coefficients. Level.rho is the density of the face coefficients and
+    Level.m the mass term; with two densities (eqs. cpoiss and kappapoiss) rho is rho^n
+    (m = 1 / (rho^n c2)) and rho_face is rho^{n+1} (None: the same as rho)."""
     rho = np.asarray(rho, dtype=np.float64).reshape(n[2], n[1], n[0])
     c2 = np.asarray(c2, dtype=np.float64).reshape(n[2], n[1], n[0])
-    levels = [Level(tuple(n), tuple(float(v) for v in h), tuple(bc), rho, 1.0 / (rho * c2),
+    rf = rho if rho_face is None else np.asarray(rho_face, dtype=np.float64).reshape(n[2], n[1], n[0])
+    levels = [Level(tuple(n), tuple(float(v) for v in h), tuple(bc), rf, 1.0 / (rho * c2),
                     float(dt))]
     while True:
         L = levels[-1]

@@ -51,10 +51,13 @@ def _thomas_batched(lower, diag, upper, rhs):
     return x
 
 
-def solve_stratified(n, h, bc, rho_z, c2_z, dt, b) -> np.ndarray:
+def solve_stratified(n, h, bc, rho_z, c2_z, dt, b, rho_face_z=None) -> np.ndarray:
     """Solve A x = b for rho, c2 given per z-plane (length nz arrays); b shaped (nz, ny, nx).
 
-    bc must be periodic (or n = 1) on x and y and Neumann on z.
+    bc must be periodic (or n = 1) on x and y and Neumann on z. With two densities
+    (eqs. cpoiss and kappapoiss) rho_z is rho^n (mass term m_k = 1 / (rho^n_k c2_k)) and
+    rho_face_z is rho^{n+1} (horizontal kappa 1 / rho^{n+1}_k, vertical faces
+    2 / (rho^{n+1}_k + rho^{n+1}_{k+1})); rho_face_z = None means rho^{n+1} = rho^n.
     """
     nx, ny, nz = (int(v) for v in n)
     hx, hy, hz = (float(v) for v in h)
@@ -64,11 +67,12 @@ def solve_stratified(n, h, bc, rho_z, c2_z, dt, b) -> np.ndarray:
         raise ValueError("z axis must be Neumann")
     rho_z = np.asarray(rho_z, dtype=np.float64).reshape(nz)
     c2_z = np.asarray(c2_z, dtype=np.float64).reshape(nz)
+    rf = rho_z if rho_face_z is None else np.asarray(rho_face_z, dtype=np.float64).reshape(nz)
     b = np.asarray(b, dtype=np.float64).reshape(nz, ny, nx)
     dt2 = float(dt) ** 2
     m = 1.0 / (rho_z * c2_z)
     # vertical face weights, w[k] between k and k+1
-    wv = dt2 * (2.0 / (rho_z[:-1] + rho_z[1:])) / (hz * hz)
+    wv = dt2 * (2.0 / (rf[:-1] + rf[1:])) / (hz * hz)
     lower = np.zeros(nz)
     upper = np.zeros(nz)
     lower[1:] = -wv
@@ -79,7 +83,7 @@ def solve_stratified(n, h, bc, rho_z, c2_z, dt, b) -> np.ndarray:
     mux = horizontal_symbol(nx)[: nx // 2 + 1]          # rfft along x keeps q = 0 .. nx/2
     muy = horizontal_symbol(ny)
     hsym = (muy[:, None] / (hy * hy) + mux[None, :] / (hx * hx)).reshape(-1)  # (ny*(nx//2+1))
-    diag = (m + vsum)[:, None] + (dt2 / rho_z)[:, None] * hsym[None, :]
+    diag = (m + vsum)[:, None] + (dt2 / rf)[:, None] * hsym[None, :]
     bh = np.fft.rfft2(b, axes=(1, 2)).reshape(nz, -1)
     xh = _thomas_batched(lower, diag, upper, bh)
     x = np.fft.irfft2(xh.reshape(nz, ny, nx // 2 + 1), s=(ny, nx), axes=(1, 2))

@@ -38,6 +38,7 @@ EXPORTS = [
     "hp_nn_set_params", "hp_nn_get_params", "hp_nn_get_grad", "hp_nn_set_output_scale",
     "hp_nn_forward", "hp_nn_train_step", "hp_nn_forward_raw", "hp_nn_loss_grad_raw", "hp_nn_adam",
     "hp_attach_net", "hp_warm_start", "hp_nn_train_step_anorm",
+    "hp_setup_two_density", "hp_update_coefficients_two_density", "hp_neumann_rhs",
 ]
 
 
@@ -130,6 +131,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                 "hp_warm_start": (ip, [H, dp, dp, dp]),
                 "hp_nn_train_step_anorm": (ip, [H, vp, dp, dp, dp, ctypes.c_float,
                                                 ctypes.POINTER(ctypes.c_double)]),
+                "hp_setup_two_density": (ip, [ctypes.POINTER(Grid), dp, dp, dp, ctypes.c_double,
+                                              ctypes.POINTER(BC), ctypes.POINTER(ctypes.c_void_p)]),
+                "hp_update_coefficients_two_density": (ip, [H, dp, dp, dp, ctypes.c_double]),
+                "hp_neumann_rhs": (ip, [H, ip, ip, dp, dp]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -175,11 +180,12 @@ def _ptr(t, dtype_name: str, numel: int, device_index: int):
 class Solver:
     """Handle around hp_setup / hp_solve / hp_free (one grid, one coefficient set at a time)."""
 
-    def __init__(self, n, h, bc, rho, c2, dt: float, mode: int | None = None):
+    def __init__(self, n, h, bc, rho, c2, dt: float, mode: int | None = None, rho_face=None):
         torch = _torch()
         lib = load_library()
         self._lib = lib
         self.n = tuple(int(v) for v in n)
+        self.bc = tuple(int(v) for v in bc)
         self.ncells = self.n[0] * self.n[1] * self.n[2]
         self.device = torch.cuda.current_device()
         g = Grid(self.n[0], self.n[1], self.n[2], float(h[0]), float(h[1]), float(h[2]))
@@ -188,8 +194,13 @@ class Solver:
         rp = _ptr(rho, "f64", self.ncells, self.device)
         cp = _ptr(c2, "f64", self.ncells, self.device)
         torch.cuda.current_stream().synchronize()
-        _check(lib.hp_setup(ctypes.byref(g), rp, cp, float(dt), ctypes.byref(b),
-                            ctypes.byref(handle)))
+        if rho_face is None:
+            _check(lib.hp_setup(ctypes.byref(g), rp, cp, float(dt), ctypes.byref(b),
+                                ctypes.byref(handle)))
+        else:
+            fp_ = _ptr(rho_face, "f64", self.ncells, self.device)
+            _check(lib.hp_setup_two_density(ctypes.byref(g), rp, fp_, cp, float(dt), ctypes.byref(b),
+                                            ctypes.byref(handle)))
         self._h = handle
         self.set_stream(torch.cuda.current_stream())
         if mode is not None:
@@ -225,10 +236,22 @@ class Solver:
         _check(self._lib.hp_get_option(self._h, int(key), ctypes.byref(v)))
         return v.value
 
-    def update_coefficients(self, rho, c2, dt: float):
-        _check(self._lib.hp_update_coefficients(self._h, _ptr(rho, "f64", self.ncells, self.device),
-                                                _ptr(c2, "f64", self.ncells, self.device),
-                                                float(dt)))
+    def update_coefficients(self, rho, c2, dt: float, rho_face=None):
+        rp = _ptr(rho, "f64", self.ncells, self.device)
+        cp = _ptr(c2, "f64", self.ncells, self.device)
+        if rho_face is None:
+            _check(self._lib.hp_update_coefficients(self._h, rp, cp, float(dt)))
+        else:
+            _check(self._lib.hp_update_coefficients_two_density(
+                self._h, rp, _ptr(rho_face, "f64", self.ncells, self.device), cp, float(dt)))
+
+    def neumann_rhs(self, axis: int, side: int, q, rhs):
+        """hp_neumann_rhs: rhs += dt^2 q / h on the cells next to that boundary (q: prescribed
+        outward normal flux per boundary face)."""
+        others = [d for d in range(3) if d != axis]
+        nf = self.n[others[0]] * self.n[others[1]]
+        _check(self._lib.hp_neumann_rhs(self._h, int(axis), int(side), _ptr(q, "f64", nf, self.device),
+                                        _ptr(rhs, "f64", self.ncells, self.device)))
 
     # -- the solve --
     def solve(self, rhs, p, tol: float = 1e-10, check: bool = True) -> dict:
@@ -406,6 +429,7 @@ class Net:
         _check_nn(self._lib.hp_nn_adam(self._h, float(lr)))
 
 
-def setup(n, h, bc, rho, c2, dt, mode=None) -> Solver:
-    """Python spelling of hp_setup."""
-    return Solver(n, h, bc, rho, c2, dt, mode)
+def setup(n, h, bc, rho, c2, dt, mode=None, rho_face=None) -> Solver:
+    """Python spelling of hp_setup (hp_setup_two_density when rho_face, the density of the face
+    coefficients at time level n+1, is given; rho is then the density of the mass term)."""
+    return Solver(n, h, bc, rho, c2, dt, mode, rho_face)

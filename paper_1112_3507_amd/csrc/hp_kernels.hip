@@ -175,7 +175,11 @@ __device__ __forceinline__ void for_faces(const Geo<T>& g, int i, int j, int k, 
 // ------------------------------------------------------------------------------------------
 // coefficient setup
 
-__global__ __launch_bounds__(kBlock) void k_setup_coef(const double* __restrict__ rho,
+// m = 1 / (rho_mass c2) (the mass term with the density of time level n) and the face density
+// rho_face (time level n+1; the same array as rho_mass in the one-density form), with the
+// Lax-Milgram check that all three are positive and finite
+__global__ __launch_bounds__(kBlock) void k_setup_coef(const double* __restrict__ rho_mass,
+                                                       const double* __restrict__ rho_face,
                                                        const double* __restrict__ c2,
                                                        double* __restrict__ rho_out,
                                                        double* __restrict__ m,
@@ -184,25 +188,52 @@ __global__ __launch_bounds__(kBlock) void k_setup_coef(const double* __restrict_
                                                        int* bad) {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
-    double r = rho[a], c = c2[a];
-    bool ok = (r > 0.0) && (c > 0.0) && isfinite(r) && isfinite(c);
+    double rm = rho_mass[a], rf = rho_face[a], c = c2[a];
+    bool ok = (rm > 0.0) && (rf > 0.0) && (c > 0.0) && isfinite(rm) && isfinite(rf) && isfinite(c);
     if (!ok) {
         atomicOr(bad, 1);
-        r = 1.0;
+        rm = 1.0;
+        rf = 1.0;
         c = 1.0;
     }
-    double mm = 1.0 / (r * c);
-    rho_out[a] = r;
+    double mm = 1.0 / (rm * c);
+    rho_out[a] = rf;
     m[a] = mm;
-    rho32[a] = (float)r;
+    rho32[a] = (float)rf;
     m32[a] = (float)mm;
 }
 
-void launch_setup_coef(const double* rho, const double* c2, double* rho_out, double* m,
-                       float* rho32, float* m32, int64_t n, int* bad, hipStream_t s) {
+void launch_setup_coef(const double* rho_mass, const double* rho_face, const double* c2, double* rho_out,
+                       double* m, float* rho32, float* m32, int64_t n, int* bad, hipStream_t s) {
     int blocks = (int)((n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_setup_coef, dim3(blocks), dim3(kBlock), 0, s, rho, c2, rho_out, m,
+    hipLaunchKernelGGL(k_setup_coef, dim3(blocks), dim3(kBlock), 0, s, rho_mass, rho_face, c2, rho_out, m,
                        rho32, m32, n, bad);
+}
+
+// Inhomogeneous Neumann data on boundary `side` of axis d: b_a += coef q_f for the cell a next to
+// each boundary face f, q the prescribed outward normal flux (coef = dt^2 / h_d). One thread per
+// face; q is indexed over the plane of the other two axes, lower axis fastest. Natural layout.
+__global__ __launch_bounds__(kBlock) void k_neumann_rhs(int nx, int ny, int nz, int d, int side, double coef,
+                                                        const double* __restrict__ q,
+                                                        double* __restrict__ b) {
+    const int n[3] = {nx, ny, nz};
+    const int e0 = d == 0 ? 1 : 0, e1 = d == 2 ? 1 : 2;
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= (int64_t)n[e0] * n[e1]) return;
+    int c[3];
+    c[d] = side ? n[d] - 1 : 0;
+    c[e0] = (int)(f % n[e0]);
+    c[e1] = (int)(f / n[e0]);
+    const int64_t a = c[0] + (int64_t)nx * (c[1] + (int64_t)ny * c[2]);
+    b[a] += coef * q[f];
+}
+
+void launch_neumann_rhs(int nx, int ny, int nz, int d, int side, double coef, const double* q, double* b,
+                        hipStream_t s) {
+    const int n[3] = {nx, ny, nz};
+    const int64_t nf = (int64_t)n[d == 0 ? 1 : 0] * n[d == 2 ? 1 : 2];
+    hipLaunchKernelGGL(k_neumann_rhs, dim3((unsigned)((nf + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       nx, ny, nz, d, side, coef, q, b);
 }
 
 // mean over the children of each coarse cell

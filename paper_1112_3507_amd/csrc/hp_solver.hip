@@ -399,15 +399,18 @@ void relayout0(hp_handle* H, const T* src, T* dst, int to_split) {
 
 // ---- coefficients of every level ----
 
-int load_coefficients(hp_handle* H, const double* rho, const double* c2, double dt) {
-    if (!rho || !c2) return fail(HP_EINVAL, "rho and c2 must be non-null device pointers");
+// rho_mass: the density of the mass term m = 1/(rho c2) (time level n); rho_face: the density of
+// the face coefficients (time level n+1); the one-density form passes the same array for both
+int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_face, const double* c2,
+                      double dt) {
+    if (!rho_mass || !rho_face || !c2) return fail(HP_EINVAL, "rho and c2 must be non-null device pointers");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HP_EINVAL, "dt must be positive and finite");
     H->dt = dt;
     LevelData& F = H->lv[0];
     for (auto& L : H->lv) L.split = 0;  // every array below is recomputed in natural order
     *H->host_flag = 0;
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
-    launch_setup_coef(rho, c2, F.rho, F.m, F.rho32, F.m32, F.N, H->flag, H->stream);
+    launch_setup_coef(rho_mass, rho_face, c2, F.rho, F.m, F.rho32, F.m32, F.N, H->flag, H->stream);
     CHK(check_launch());
     HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
@@ -1028,6 +1031,11 @@ const char* hp_last_error(void) { return g_err.c_str(); }
 
 int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt, const hp_bc* bc,
              hp_handle** out) {
+    return hp_setup_two_density(grid, rho, rho, c2, dt, bc, out);
+}
+
+int hp_setup_two_density(const hp_grid* grid, const double* rho_n, const double* rho_np1, const double* c2,
+                         double dt, const hp_bc* bc, hp_handle** out) {
     g_err.clear();
     if (!grid || !bc || !out) return fail(HP_EINVAL, "grid, bc and out must be non-null");
     *out = nullptr;
@@ -1045,7 +1053,7 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
     }
     if (N >= (int64_t)1 << 31) return fail(HP_EINVAL, "grid has too many cells (limit 2^31 - 1)");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HP_EINVAL, "dt must be positive and finite");
-    if (!rho || !c2) return fail(HP_EINVAL, "rho and c2 must be non-null");
+    if (!rho_n || !rho_np1 || !c2) return fail(HP_EINVAL, "rho and c2 must be non-null");
 
     hp_handle* H = new hp_handle();
     H->grid = *grid;
@@ -1135,7 +1143,7 @@ int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt
     if (hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), H->stream) != hipSuccess)
         return bail(fail(HP_EHIP, "hipMemsetAsync failed"));
     H->want_split = split_allowed(H) ? 1 : 0;
-    if ((rc = load_coefficients(H, rho, c2, dt))) return bail(rc);
+    if ((rc = load_coefficients(H, rho_n, rho_np1, c2, dt))) return bail(rc);
     H->stats.levels = (int)H->lv.size();
     *out = H;
     return HP_OK;
@@ -1221,9 +1229,26 @@ int hp_get_option(const hp_handle* H, int key, double* v) {
 }
 
 int hp_update_coefficients(hp_handle* H, const double* rho, const double* c2, double dt) {
+    return hp_update_coefficients_two_density(H, rho, rho, c2, dt);
+}
+
+int hp_update_coefficients_two_density(hp_handle* H, const double* rho_n, const double* rho_np1,
+                                       const double* c2, double dt) {
     if (!H) return fail(HP_EINVAL, "null handle");
     g_err.clear();
-    return load_coefficients(H, rho, c2, dt);
+    return load_coefficients(H, rho_n, rho_np1, c2, dt);
+}
+
+int hp_neumann_rhs(hp_handle* H, int axis, int side, const double* q, double* rhs) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (!q || !rhs) return fail(HP_EINVAL, "null vector");
+    if (axis < 0 || axis > 2 || (side != 0 && side != 1)) return fail(HP_EINVAL, "axis must be 0..2, side 0 or 1");
+    const int bcs[3] = {H->bc.x, H->bc.y, H->bc.z};
+    if (bcs[axis] != HP_BC_NEUMANN) return fail(HP_EINVAL, "Neumann data needs a Neumann axis");
+    const LevelData& F = H->lv[0];
+    launch_neumann_rhs(F.n[0], F.n[1], F.n[2], axis, side, H->dt * H->dt / F.h[axis], q, rhs, H->stream);
+    return check_launch();
 }
 
 int hp_get_stats(const hp_handle* H, hp_stats* out) {

@@ -29,9 +29,12 @@ class Problem:
     n: tuple          # (nx, ny, nz)
     h: tuple          # (hx, hy, hz)
     bc: tuple         # (bcx, bcy, bcz)
-    rho: np.ndarray   # (nz, ny, nx) float64
+    rho: np.ndarray   # (nz, ny, nx) float64; with two densities: rho^n (the mass term's)
     c2: np.ndarray    # (nz, ny, nx) float64
     dt: float
+    rho_face: np.ndarray | None = None  # rho^{n+1} (the face coefficients'); None: same as rho
+    f: np.ndarray | None = None         # a given right-hand side (before boundary data)
+    neumann: dict | None = None         # {(axis, side): prescribed outward normal flux per face}
 
     @property
     def shape(self):
@@ -144,3 +147,48 @@ def config1(mach: float = 0.01, n: int = 256, seed: int = 0, noise: float = 0.01
 def semiconvection_mu(z):
     """Mean-molecular-weight step mu(z) = 1 + 0.1 tanh((z - 0.5) / 0.02)."""
     return 1.0 + 0.1 * np.tanh((np.asarray(z) - 0.5) / 0.02)
+
+
+def with_density_change(p: Problem, seed: int, change: float = 0.01) -> Problem:
+    """Two densities on the grid of `p`: rho^n = p.rho and rho^{n+1} = rho^n (1 + change U),
+    U uniform(-1, 1) per cell (PCG64, `seed`), standing in for the density after one explicit
+    step (eqs. cpoiss and kappapoiss take rho^n in the mass term and rho^{n+1} in kappa)."""
+    rng = np.random.default_rng(seed)
+    rf = p.rho * (1.0 + change * rng.uniform(-1.0, 1.0, size=p.rho.shape))
+    return Problem(p.name + "_two_density", p.n, p.h, p.bc, p.rho, p.c2, p.dt, rho_face=rf)
+
+
+STABILITY_CASES = ("unperturbed", "f", "kappa", "c")
+
+
+def stability_problem(nx: int, case: str, seed: int = 0, ny: int | None = None,
+                      amplitude: float = 1e-2) -> Problem:
+    """The stability problem of Section 2 (Table perturbtest): -Laplace(phi) + phi = 0 on the
+    unit square, Neumann in x with outward normal derivatives -e^0 at x = 0 and e^1 at x = 1,
+    periodic in y; exact solution phi = e^x. As the dt^2-scaled operator: dt = 1, rho^n = 1,
+    c2 = 1 (m = c~ = 1), rho^{n+1} = 1 (kappa = 1), f = 0, on nx x ny x 1 cells of size 1/nx.
+    The boundary data are the prescribed outward normal fluxes kappa dphi/dn of the unperturbed
+    problem (kappa = 1), which a perturbation of kappa leaves unchanged.
+
+    case: "unperturbed"; "f", "kappa" or "c" add random perturbations of amplitude `amplitude`
+    (uniform(-1, 1) per cell, PCG64 `seed`) to f, to kappa (rho^{n+1} = 1 / (1 + a U)) or to
+    c~ (c2 = 1 / (1 + a U), so m = 1 + a U)."""
+    if case not in STABILITY_CASES:
+        raise ValueError("unknown case %r" % case)
+    ny = nx if ny is None else ny
+    h = 1.0 / nx
+    shape = (1, ny, nx)
+    u = np.random.default_rng(seed).uniform(-1.0, 1.0, size=shape)
+    rho = np.ones(shape)
+    rf = np.ones(shape)
+    c2 = np.ones(shape)
+    f = np.zeros(shape)
+    if case == "kappa":
+        rf = 1.0 / (1.0 + amplitude * u)
+    elif case == "c":
+        c2 = 1.0 / (1.0 + amplitude * u)
+    elif case == "f":
+        f = amplitude * u
+    neu = {(0, 0): np.full((1, ny), -np.exp(0.0)), (0, 1): np.full((1, ny), np.exp(1.0))}
+    return Problem("stability_%d_%s" % (nx, case), (nx, ny, 1), (h, h, h), (NEUMANN, PERIODIC, NEUMANN),
+                   rho, c2, 1.0, rho_face=rf, f=f, neumann=neu)
