@@ -238,6 +238,24 @@ int hp_residual(hp_handle* h, const double* rhs, const double* p, double* r, dou
  * HP_EINVAL. */
 int hp_dot(hp_handle* h, const double* x, const double* y, long long n, double* out);
 
+/*
+ * For callers that cannot allocate (code under stream capture, tight serving loops): the same
+ * deterministic dot product as hp_dot, bitwise, with no handle and no allocation of any kind.
+ *   x, y     device FP64 vectors of n entries (may be NULL when n = 0); read only.
+ *   n        >= 0. The first reduction stage writes one partial sum per workgroup (at most 2048,
+ *            one per 1024 entries, for any n) into a 16 KiB static device array of the library,
+ *            one per GPU, held until the process ends; lengths needing more are HP_EINVAL.
+ *   result   device pointer to one FP64 value (caller-owned) that receives <x, y>.
+ *   stream   hipStream_t the two kernels are enqueued on (NULL: the null stream); the call
+ *            returns without synchronising.
+ * Every call on a GPU uses that GPU's one static array: calls that overlap on one GPU (on
+ * different streams or host threads without ordering between them) race and may return wrong
+ * sums. Errors: HP_EINVAL (null result, null x or y with n > 0, n < 0), HP_EHIP; the message is
+ * in hp_noalloc_last_error().
+ */
+int hp_dot_noalloc(const double* x, const double* y, long long n, double* result, void* stream);
+const char* hp_noalloc_last_error(void);
+
 /* ---- Learned warm start / preconditioner -------------------------------------------------
  * A small 3D U-Net (levels n, n/2, n/4 with 16/32/64 channels, 3x3x3 convolutions padded
  * periodically in x, y and with zeros in z, 2x2x2 mean pooling, nearest upsampling, skip

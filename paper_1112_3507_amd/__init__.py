@@ -38,6 +38,7 @@ EXPORTS = [
     "hp_nn_set_params", "hp_nn_get_params", "hp_nn_get_grad", "hp_nn_set_output_scale",
     "hp_nn_forward", "hp_nn_train_step", "hp_nn_forward_raw", "hp_nn_loss_grad_raw", "hp_nn_adam",
     "hp_attach_net", "hp_warm_start", "hp_nn_train_step_anorm",
+    "hp_dot_noalloc", "hp_noalloc_last_error",
     "hp_setup_two_density", "hp_update_coefficients_two_density", "hp_neumann_rhs",
 ]
 
@@ -131,6 +132,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                 "hp_warm_start": (ip, [H, dp, dp, dp]),
                 "hp_nn_train_step_anorm": (ip, [H, vp, dp, dp, dp, ctypes.c_float,
                                                 ctypes.POINTER(ctypes.c_double)]),
+                "hp_dot_noalloc": (ip, [dp, dp, ctypes.c_longlong, dp, vp]),
+                "hp_noalloc_last_error": (ctypes.c_char_p, []),
                 "hp_setup_two_density": (ip, [ctypes.POINTER(Grid), dp, dp, dp, ctypes.c_double,
                                               ctypes.POINTER(BC), ctypes.POINTER(ctypes.c_void_p)]),
                 "hp_update_coefficients_two_density": (ip, [H, dp, dp, dp, ctypes.c_double]),
@@ -339,6 +342,21 @@ class Solver:
         _check(self._lib.hp_warm_start(self._h, self._vec(rhs, 0),
                                        self._vec(p_prev, 0) if p_prev is not None else None,
                                        self._vec(x, 0)))
+
+
+def dot_noalloc(x, y, result, stream=None):
+    """hp_dot_noalloc: result[0] = <x, y> (device FP64 tensors; result has one entry), enqueued on
+    `stream` (default: torch's current stream) without allocating or synchronising."""
+    torch = _torch()
+    lib = load_library()
+    d = torch.cuda.current_device()
+    n = x.numel()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.hp_dot_noalloc(_ptr(x, "f64", n, d) if n else None, _ptr(y, "f64", n, d) if n else None,
+                            n, _ptr(result, "f64", 1, d), ctypes.c_void_p(st.cuda_stream))
+    if rc != OK:
+        msg = lib.hp_noalloc_last_error()
+        raise HPError(rc, msg.decode() if msg else "")
 
 
 def num_params() -> int:
