@@ -184,6 +184,67 @@ int hp_get_stats(const hp_handle* h, hp_stats* out);
 /* Thread-local message of the last error ("" if none). */
 const char* hp_last_error(void);
 
+/* ---- The steps either side of the solve (Section 2, "The Algorithm") ---------------------------
+ * Natural-layout FP64 cell arrays of the handle's grid (nx*ny*nz entries each, device pointers,
+ * caller-owned). A momentum argument is three consecutive cell arrays: the x, y and z components.
+ * Boundaries are the handle's: periodic axes wrap; at a closed (Neumann) boundary the interface
+ * velocity is zero and the interface pressure is the adjacent cell's (eq. vonNeumannBC); an axis
+ * of one cell has no gradient or divergence. dt is the handle's. Stream-ordered, no sync.
+ */
+
+/* Fields that form the right-hand side. */
+typedef struct {
+    const double* rho_n;     /* density at time n */
+    const double* c2_n;      /* squared sound speed at time n */
+    const double* p_n;       /* pressure at time n */
+    const double* mom_n;     /* (rho u)^n, 3 cell arrays */
+    const double* rho_np1;   /* density at time n+1 (after the explicit step) */
+    const double* mom_star;  /* (rho u)* after the explicit step, 3 cell arrays */
+    const double* visc;      /* NULL, or per cell the group u.div(tau) - div(u.tau) + div(K grad T) at time
+                                n (viscous stress and heat conduction of the explicit part) */
+    const double* temp_n;    /* NULL for one component (eq. fpoiss); for two (eq. fpoiss2) the
+                                temperature T^n, with conc_n, rkc_n and r_gas: */
+    const double* conc_n;    /* mass fraction c^n */
+    const double* rkc_n;     /* rho^n kappa_c per cell (interface value: mean of the two cells) */
+    double r_gas;            /* gas constant R_gas */
+} hp_rhs_fields;
+
+/*
+ * Steps (iv)-(v): the right-hand side of the pressure equation, b = dt^2 f with f of eq. fpoiss
+ * (eq. fpoiss2 when temp_n is given), in the scaling of hp_solve:
+ *
+ *   b = m (P^n - dt u^n . grad P^n) - dt div u* - (2 dt / 3)(m / rho^n) G
+ *       - (3 dt / 4) m R_gas T^n div(rho^n kappa_c grad c^n),     m = 1 / (rho^n c2^n),
+ *
+ * u^n = (rho u)^n / rho^n; grad P^n from the interface pressure of eq. pbnd (weights rho^n) and the
+ * central difference of eq. nablaP; div u* from the interface velocities of eq. step1 applied to
+ * (rho u)* and rho^{n+1}. rhs must not alias an input. Errors: HP_EINVAL (null handle, fields,
+ * rhs or required field), HP_EHIP.
+ */
+int hp_pressure_rhs(hp_handle* h, const hp_rhs_fields* f, double* rhs);
+
+/* Fields of the update after the solve. */
+typedef struct {
+    const double* p;         /* predicted pressure P^{n+1} (the solution of hp_solve) */
+    const double* rho_np1;   /* density at time n+1 */
+    const double* mom_star;  /* (rho u)*, 3 cell arrays */
+    const double* e_star;    /* total energy e* after the explicit step */
+    double* mom_out;         /* out: (rho u)^{n+1}, 3 cell arrays */
+    double* uface_out;       /* out: interface velocities u^{n+1} on the high side of every cell
+                                along x, y, z (3 cell arrays; 0 at a closed high end) */
+    double* e_out;           /* out: total energy e^{n+1} */
+} hp_update_fields;
+
+/*
+ * Steps (vii)-(ix): momentum (rho u)^{n+1} = (rho u)* - dt grad P (eqs. momupdate, pbnd and
+ * nablaP with rho^{n+1}); interface velocities u^{n+1}_{i+1/2} = u*_{i+1/2}
+ * - dt (P_{i+1} - P_i) / h * 2 / (rho^{n+1}_{i+1} + rho^{n+1}_i) (step (viii), u* by eq. step1);
+ * energy e^{n+1} = e* - dt (P div u^{n+1} + u^{n+1} . grad P) (eq. enupdate, div from the new
+ * interface velocities, u^{n+1} = (rho u)^{n+1} / rho^{n+1}). Outputs must not alias inputs or each
+ * other. Errors: HP_EINVAL (null pointer, aliasing), HP_EHIP.
+ */
+int hp_pressure_update(hp_handle* h, const hp_update_fields* f);
+
 /* ---- Building blocks of the solve, exposed for verification and composition ------------------
  * Levels are numbered 0 (fine) .. hp_num_levels()-1 (coarsest). Vectors of level l are device
  * arrays of that level's cell count; FP32 variants ("_f32") act on the FP32 copies of the

@@ -40,6 +40,7 @@ EXPORTS = [
     "hp_attach_net", "hp_warm_start", "hp_nn_train_step_anorm",
     "hp_dot_noalloc", "hp_noalloc_last_error",
     "hp_setup_two_density", "hp_update_coefficients_two_density", "hp_neumann_rhs",
+    "hp_pressure_rhs", "hp_pressure_update",
 ]
 
 
@@ -68,6 +69,16 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RhsFields(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("rho_n", "c2_n", "p_n", "mom_n", "rho_np1", "mom_star",
+                                                "visc", "temp_n", "conc_n", "rkc_n")] + [("r_gas", ctypes.c_double)]
+
+
+class UpdateFields(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("p", "rho_np1", "mom_star", "e_star", "mom_out", "uface_out",
+                                                "e_out")]
 
 
 _lock = threading.Lock()
@@ -138,6 +149,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                               ctypes.POINTER(BC), ctypes.POINTER(ctypes.c_void_p)]),
                 "hp_update_coefficients_two_density": (ip, [H, dp, dp, dp, ctypes.c_double]),
                 "hp_neumann_rhs": (ip, [H, ip, ip, dp, dp]),
+                "hp_pressure_rhs": (ip, [H, ctypes.POINTER(RhsFields), dp]),
+                "hp_pressure_update": (ip, [H, ctypes.POINTER(UpdateFields)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -255,6 +268,27 @@ class Solver:
         nf = self.n[others[0]] * self.n[others[1]]
         _check(self._lib.hp_neumann_rhs(self._h, int(axis), int(side), _ptr(q, "f64", nf, self.device),
                                         _ptr(rhs, "f64", self.ncells, self.device)))
+
+    # -- the steps either side of the solve --
+    def pressure_rhs(self, rho_n, c2_n, p_n, mom_n, rho_np1, mom_star, rhs, visc=None, temp_n=None,
+                     conc_n=None, rkc_n=None, r_gas=1.0):
+        """hp_pressure_rhs: rhs = dt^2 f of the pressure equation from the fields of time n and
+        the explicit step (momenta are (3, nz, ny, nx) tensors)."""
+        c, d = self.ncells, self.device
+        opt = lambda t: _ptr(t, "f64", c, d) if t is not None else None
+        f = RhsFields(_ptr(rho_n, "f64", c, d), _ptr(c2_n, "f64", c, d), _ptr(p_n, "f64", c, d),
+                      _ptr(mom_n, "f64", 3 * c, d), _ptr(rho_np1, "f64", c, d),
+                      _ptr(mom_star, "f64", 3 * c, d), opt(visc), opt(temp_n), opt(conc_n), opt(rkc_n),
+                      float(r_gas))
+        _check(self._lib.hp_pressure_rhs(self._h, ctypes.byref(f), _ptr(rhs, "f64", c, d)))
+
+    def pressure_update(self, p, rho_np1, mom_star, e_star, mom_out, uface_out, e_out):
+        """hp_pressure_update: momentum, interface velocities and energy after the solve."""
+        c, d = self.ncells, self.device
+        f = UpdateFields(_ptr(p, "f64", c, d), _ptr(rho_np1, "f64", c, d), _ptr(mom_star, "f64", 3 * c, d),
+                         _ptr(e_star, "f64", c, d), _ptr(mom_out, "f64", 3 * c, d),
+                         _ptr(uface_out, "f64", 3 * c, d), _ptr(e_out, "f64", c, d))
+        _check(self._lib.hp_pressure_update(self._h, ctypes.byref(f)))
 
     # -- the solve --
     def solve(self, rhs, p, tol: float = 1e-10, check: bool = True) -> dict:

@@ -194,6 +194,12 @@ void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hip
 // scal[slot] = value (stream-ordered, graph-safe)
 void launch_set_scalar(double* scal, int slot, double value, hipStream_t s);
 
+// ---- steps either side of the solve (hp_hydro.hip); natural-layout FP64 cell arrays ----
+int hydro_launch_rhs(const int n[3], const int bc[3], const double h[3], double dt, const hp_rhs_fields* f,
+                     double* rhs, hipStream_t s);
+int hydro_launch_update(const int n[3], const int bc[3], const double h[3], double dt,
+                        const hp_update_fields* f, hipStream_t s);
+
 // ---- learned stage (hp_nn.hip) ----
 int nn_grid(const hp_net* net, int* nx, int* ny, int* nz);
 // z = s * out_scale * net(r / s, log rho, -log(rho m), p_prev / s), s = RMS(r); p_prev may be null

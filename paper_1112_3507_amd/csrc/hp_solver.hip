@@ -1513,6 +1513,44 @@ int hp_nn_train_step_anorm(hp_handle* H, hp_net* net, const double* b, const dou
     return check_launch();
 }
 
+int hp_pressure_rhs(hp_handle* H, const hp_rhs_fields* f, double* rhs) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (!f || !rhs || !f->rho_n || !f->c2_n || !f->p_n || !f->mom_n || !f->rho_np1 || !f->mom_star)
+        return fail(HP_EINVAL, "null field");
+    if (f->temp_n && (!f->conc_n || !f->rkc_n)) return fail(HP_EINVAL, "two components need conc_n and rkc_n");
+    const double* ins[] = {f->rho_n, f->c2_n, f->p_n, f->mom_n, f->rho_np1, f->mom_star, f->visc, f->temp_n,
+                           f->conc_n, f->rkc_n};
+    for (const double* q : ins)
+        if (q == rhs) return fail(HP_EINVAL, "rhs must not alias an input");
+    const LevelData& F = H->lv[0];
+    const int bcs[3] = {H->bc.x, H->bc.y, H->bc.z};
+    if (hydro_launch_rhs(F.n, bcs, F.h, H->dt, f, rhs, H->stream) != HP_OK) return check_launch();
+    return check_launch();
+}
+
+int hp_pressure_update(hp_handle* H, const hp_update_fields* f) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (!f || !f->p || !f->rho_np1 || !f->mom_star || !f->e_star || !f->mom_out || !f->uface_out || !f->e_out)
+        return fail(HP_EINVAL, "null field");
+    const LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    // inputs and outputs as byte ranges (momenta span three cell arrays): no output may overlap
+    // any other array of the call
+    struct R { const char* lo; const char* hi; };
+    auto rng = [&](const double* q, int arrays) { return R{(const char*)q, (const char*)(q + arrays * N)}; };
+    const R arr[] = {rng(f->p, 1), rng(f->rho_np1, 1), rng(f->mom_star, 3), rng(f->e_star, 1),
+                     rng(f->mom_out, 3), rng(f->uface_out, 3), rng(f->e_out, 1)};
+    for (int o = 4; o < 7; ++o)
+        for (int q = 0; q < 7; ++q)
+            if (q != o && arr[o].lo < arr[q].hi && arr[q].lo < arr[o].hi)
+                return fail(HP_EINVAL, "outputs must not alias inputs or each other");
+    const int bcs[3] = {H->bc.x, H->bc.y, H->bc.z};
+    if (hydro_launch_update(F.n, bcs, F.h, H->dt, f, H->stream) != HP_OK) return check_launch();
+    return check_launch();
+}
+
 int hp_dot(hp_handle* H, const double* x, const double* y, long long n, double* out) {
     if (!H || !out || (n > 0 && (!x || !y))) return fail(HP_EINVAL, "null argument");
     if (n < 0 || reduce_blocks_vec(n) > H->partial_cap) return fail(HP_EINVAL, "bad length");

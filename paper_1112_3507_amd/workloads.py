@@ -192,3 +192,60 @@ def stability_problem(nx: int, case: str, seed: int = 0, ny: int | None = None,
     neu = {(0, 0): np.full((1, ny), -np.exp(0.0)), (0, 1): np.full((1, ny), np.exp(1.0))}
     return Problem("stability_%d_%s" % (nx, case), (nx, ny, 1), (h, h, h), (NEUMANN, PERIODIC, NEUMANN),
                    rho, c2, 1.0, rho_face=rf, f=f, neumann=neu)
+
+
+@dataclass
+class HydroState:
+    """The fields either side of one pressure solve (arrays (nz, ny, nx); momenta (3, nz, ny, nx)
+    with x, y, z components)."""
+    p: Problem                  # grid, boundaries, dt; p.rho = rho^n, p.c2 = c2^n, p.rho_face = rho^{n+1}
+    p_n: np.ndarray             # pressure P^n
+    mom_n: np.ndarray           # (rho u)^n
+    mom_star: np.ndarray        # (rho u)* after the explicit step
+    e_star: np.ndarray          # total energy e* after the explicit step
+    visc: np.ndarray            # viscous / heat-conduction group of eq. fpoiss at time n
+    temp_n: np.ndarray          # temperature T^n (two-component term of eq. fpoiss2)
+    conc_n: np.ndarray          # helium mass fraction c^n
+    rkc_n: np.ndarray           # rho^n kappa_c
+    r_gas: float = 1.0
+
+
+def hydro_state(n, mach: float, seed: int = 0) -> HydroState:
+    """A seeded stand-in for the state of the stratified box at one time step: the polytrope of
+    `polytrope` (rho^n, c2^n; P^n = rho T = T^2.5 with T = 1 + 9z before noise), rho^{n+1} with a
+    1% change, a smooth random velocity of magnitude ~Ma (sum of low Fourier modes) vanishing at
+    the closed z ends, (rho u)^n = rho^n u, (rho u)* = (rho u)^n plus 1% of noise, e* = P / (gamma - 1)
+    + rho |u|^2 / 2 (gamma = 5/3), a viscous group of size ~Ma^2, and for the two-component term
+    T = 1 + 9z, a helium mass fraction step c = 0.25 + 0.05 tanh((z - 0.5) / 0.02) and
+    rho kappa_c = 1e-3 rho. All draws PCG64 from `seed`."""
+    nx, ny, nz = (int(v) for v in n)
+    base = polytrope(n, mach, seed=seed)
+    rng = np.random.default_rng(seed + 7919)
+    rho_n = base.rho
+    rho_np1 = rho_n * (1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=rho_n.shape))
+    h = base.h[2]
+    x = (np.arange(nx) + 0.5) * base.h[0]
+    y = (np.arange(ny) + 0.5) * base.h[1]
+    z = z_centres(nz, h)
+    T = 1.0 + 9.0 * z
+    p_n = np.broadcast_to((T ** 2.5)[:, None, None], rho_n.shape).copy()
+    p_n *= 1.0 + 1e-4 * rng.uniform(-1.0, 1.0, size=p_n.shape)
+    Lx, Ly = nx * base.h[0], ny * base.h[1]
+    u = np.zeros((3,) + rho_n.shape)
+    for _ in range(6):
+        kx, ky = rng.integers(-3, 4, size=2)
+        kz = rng.integers(1, 4)
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=3)
+        amp = rng.standard_normal(3) * mach
+        hx = np.cos(2 * np.pi * (kx * x[None, :] / Lx + ky * y[:, None] / Ly) + ph[0])[None]
+        u[0] += amp[0] * hx * np.cos(np.pi * kz * z + ph[1])[:, None, None]
+        u[1] += amp[1] * hx * np.cos(np.pi * kz * z + ph[2])[:, None, None]
+        u[2] += amp[2] * hx * np.sin(np.pi * kz * z)[:, None, None]
+    mom_n = rho_n[None] * u
+    mom_star = mom_n * (1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=mom_n.shape))
+    e_star = p_n / (5.0 / 3.0 - 1.0) + 0.5 * rho_np1 * np.sum(u * u, axis=0)
+    visc = mach ** 2 * rng.standard_normal(rho_n.shape)
+    temp = np.broadcast_to(T[:, None, None], rho_n.shape).copy()
+    conc = np.broadcast_to((0.25 + 0.05 * np.tanh((z - 0.5) / 0.02))[:, None, None], rho_n.shape).copy()
+    p = Problem(base.name + "_hydro", base.n, base.h, base.bc, rho_n, base.c2, base.dt, rho_face=rho_np1)
+    return HydroState(p, p_n, mom_n, mom_star, e_star, visc, temp, conc, 1e-3 * rho_n)
