@@ -702,6 +702,11 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
     *its = 0;
     double rr_prev = 1.0, ratio = 1.0;
     bool ahead = false;
+    // squared residual norms of the last iterations: the inner solve stops when the residual has
+    // fallen by less than 2 over four iterations (FP32 cannot resolve the operator any further,
+    // e.g. when its condition number approaches 1/u_32); the outer refinement then sees whether
+    // the correction helped and falls back to FP64 MG-PCG if not
+    double hist[4] = {0.0, 0.0, 0.0, 0.0};
     while (*its < budget) {
         // r -= alpha q; x += alpha p is deferred to the next direction update (or the end); as in
         // pcg64 the update rides on the next pre-smoothing when the next direction runs ahead
@@ -727,7 +732,9 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite inner residual");
         ratio = rr_prev > 0.0 ? rr / rr_prev : 1.0;
         rr_prev = rr;
-        if (std::sqrt(rr) <= eta || *its >= budget) break;
+        const bool stalled = *its > 4 && rr > 0.25 * hist[*its % 4];
+        hist[*its % 4] = rr;
+        if (std::sqrt(rr) <= eta || *its >= budget || stalled) break;
         if (!ahead) next_direction32(H);
     }
     if (*its > 0 && !ahead) launch_axpy_alpha<float>(H->x32, H->p32, N, H->scal, s);
