@@ -108,8 +108,8 @@ def roofline(solver, rhs, x, n_cells, dev, warmup):
     """Roofline of the dominant finest-level kernel, measured live: the solver's own HIP-event
     timing (on its stream; the events are attached to the dispatches themselves) of every CG
     operator apply and every post-smoothing half sweep on the finest level inside FP64 solves of
-    the benchmark's right-hand sides; a plain device copy of 1 GiB (beyond the 256 MB last-level
-    cache) as the measured streaming reference."""
+    the benchmark's right-hand sides; the library's streaming copy of 1 GiB (beyond the 256 MB
+    last-level cache) as the measured streaming reference."""
     import torch
     import paper_1112_3507_amd as hp
     solver.set_option(hp.OPT_KERNEL_TIMING, 1)
@@ -123,9 +123,11 @@ def roofline(solver, rhs, x, n_cells, dev, warmup):
         acc["apply"][1] += st["timed_applies"]
     solver.set_option(hp.OPT_KERNEL_TIMING, 0)
     times = {k: v[0] / max(v[1], 1) for k, v in acc.items()}
-    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    src = torch.rand(1 << 27, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
-    copy_ms = kernel_time_ms(lambda: dst.copy_(src), reps=20)
+    # the library's streaming copy (16-byte non-temporal loads and stores), 1 GiB each way
+    copy_ms = kernel_time_ms(lambda: hp.stream_copy(src, dst), reps=20)
+    assert torch.equal(src, dst)
     del src, dst
     # the dominant kernel takes the largest share of the solve: the half sweep (two launches per
     # CG iteration, the kernel with the largest total time in the rocprofv3 summary) ahead of the
@@ -247,6 +249,119 @@ def training_leg(dev, steps=10):
     return {"grid": [128, 128, 128], "ms_per_step": round(ms, 3), "steps_timed": steps}
 
 
+def semiconvection_leg(dev, steps=20, seed=7, n=(1024, 1024, 512)):
+    """The two-component sequence: the 1024 x 1024 x 512 box [0,2]^2 x [0,1] (h = 1/512), T = 1 + 9z,
+    the mean-molecular-weight step mu(z), rho = T^1.5 mu (1 +- 1%), c2 = (T / mu)(1 +- 1%) (seed 7),
+    Ma = 0.001, and `steps` consecutive solves whose coefficients are carried one step further
+    each time by a seeded divergence-free horizontal velocity (|u|max = Ma, one cell per step,
+    semi-Lagrangian bilinear interpolation, periodic in x and y). Solve n: rhs m_n p_{n-1} - dt D_n
+    (D a seeded zero-mean field carried along; p is the pressure perturbation about the hydrostatic
+    background, p_0 = 0), from p_{n-1}; the coefficient update (hp_update_coefficients) and the
+    solve are timed per step, for the mixed-precision form and for FP64 MG-PCG (iteration cap 300).
+    Input generation (the advection) is plain torch arithmetic outside the timing."""
+    import numpy as np
+    import torch
+    import paper_1112_3507_amd as hp
+    from paper_1112_3507_amd import workloads as wl
+    nx, ny, nz = n
+    log("bench: semiconvection inputs %s" % (n,))
+    p = wl.polytrope(n, 0.001, seed=seed, mu=wl.semiconvection_mu)
+    h, dt = p.h[0], p.dt
+    rho0 = torch.from_numpy(p.rho).to(dev)
+    c20 = torch.from_numpy(p.c2).to(dev)
+    del p
+    z = (torch.arange(nz, device=dev, dtype=torch.float64) + 0.5) * h
+    rng = np.random.default_rng(seed + 1)
+    D0 = torch.from_numpy(rng.standard_normal((nz, ny, nx))).to(dev)
+    D0 -= D0.mean()
+    # streamfunction psi = g(z) sum_q a_q cos(2 pi (kx x + ky y) / 2 + phi_q): u = (d psi/dy, -d psi/dx, 0)
+    x = (torch.arange(nx, device=dev, dtype=torch.float64) + 0.5) * h
+    y = (torch.arange(ny, device=dev, dtype=torch.float64) + 0.5) * h
+    ux = torch.zeros((ny, nx), device=dev, dtype=torch.float64)
+    uy = torch.zeros_like(ux)
+    for _ in range(6):
+        kx, ky = rng.integers(-2, 3, size=2)
+        if kx == 0 and ky == 0:
+            kx = 1
+        a, ph = rng.standard_normal(), rng.uniform(0, 2 * np.pi)
+        arg = 2 * np.pi * (kx * x[None, :] + ky * y[:, None]) / 2.0 + ph
+        ux += -a * np.pi * ky * torch.sin(arg)
+        uy += a * np.pi * kx * torch.sin(arg)
+    gz = 1.0 + 0.5 * torch.cos(np.pi * z)
+    scale = 0.001 / float(torch.sqrt(ux * ux + uy * uy).max() * gz.max())
+    # departure points in cell units, their cells and bilinear weights (the velocity is steady)
+    sx = (ux[None] * gz[:, None, None] * (scale * dt / h))
+    sy = (uy[None] * gz[:, None, None] * (scale * dt / h))
+    del ux, uy
+    ii = torch.arange(nx, device=dev, dtype=torch.float64).view(1, 1, nx)
+    jj = torch.arange(ny, device=dev, dtype=torch.float64).view(1, ny, 1)
+    xd, yd = ii - sx, jj - sy
+    del sx, sy
+    fx, fy = torch.floor(xd), torch.floor(yd)
+    wx, wy = xd - fx, yd - fy
+    del xd, yd
+    i0 = torch.remainder(fx.long(), nx)
+    j0 = torch.remainder(fy.long(), ny)
+    del fx, fy
+    kk = (torch.arange(nz, device=dev, dtype=torch.int64) * (nx * ny)).view(nz, 1, 1)
+    r0 = kk + j0 * nx
+    r1 = kk + torch.remainder(j0 + 1, ny) * nx
+    c1 = torch.remainder(i0 + 1, nx)
+    taps = (r0 + i0, r0 + c1, r1 + i0, r1 + c1)
+    del r0, r1, c1, j0, i0, kk
+
+    def advect(f):
+        v = f.view(-1)
+        a = torch.take(v, taps[0]) * (1 - wx) + torch.take(v, taps[1]) * wx
+        b = torch.take(v, taps[2]) * (1 - wx) + torch.take(v, taps[3]) * wx
+        return a * (1 - wy) + b * wy
+
+    out = {}
+    for name, mode in (("mixed_ir", hp.MODE_MIXED_IR), ("fp64_mgpcg", hp.MODE_FP64_MGPCG)):
+        log("bench: semiconvection %s, %d steps" % (name, steps))
+        rho, c2, D = rho0.clone(), c20.clone(), D0.clone()
+        x = torch.zeros_like(rho0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = hp.setup(n, (h, h, h), (hp.PERIODIC, hp.PERIODIC, hp.NEUMANN), rho, c2, dt, mode)
+        s.set_option(hp.OPT_MAX_ITER, 300)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        upd, sol, its, res, conv = [], [], [], [], []
+        for step in range(steps):
+            rho, c2, D = advect(rho), advect(c2), advect(D)
+            b = x / (rho * c2) - dt * D
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.update_coefficients(rho, c2, dt)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = s.solve(b, x, tol=TOL, check=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            upd.append(1e3 * (t1 - t0))
+            sol.append(1e3 * (t2 - t1))
+            its.append(st["iterations"])
+            res.append(st["rel_residual"])
+            conv.append(bool(st["converged"]))
+            log("bench: semiconvection %s step %d: update %.1f ms, solve %.1f ms, %d iterations, "
+                "residual %.2e" % (name, step, upd[-1], sol[-1], its[-1], res[-1]))
+            del b
+        s.close()
+        per = [a + b for a, b in zip(upd, sol)]
+        out[name] = {"solves_per_s_incl_update": round(1e3 * steps / sum(per), 3),
+                     "update_ms_median": round(sorted(upd)[steps // 2], 3),
+                     "solve_ms_median": round(sorted(sol)[steps // 2], 3),
+                     "setup_ms": round(setup_ms, 1), "iterations": its,
+                     "max_rel_residual": max(res), "all_converged": all(conv)}
+        del rho, c2, D, x
+    out["grid"] = list(n)
+    out["steps"] = steps
+    out["speedup_mixed_vs_fp64"] = round(out["mixed_ir"]["solves_per_s_incl_update"]
+                                         / out["fp64_mgpcg"]["solves_per_s_incl_update"], 3)
+    return out
+
+
 def host_cpu():
     """CPU model name and the number of host threads the process may use."""
     model = "unknown"
@@ -318,6 +433,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the Ma=0.001 forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-semiconvection", action="store_true",
+                    help="skip the 1024x1024x512 two-component sequence")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -428,6 +545,10 @@ def main():
             var["learned_fcg"] = lv["fcg"]
             result["learned_training"] = lv["training"]
         del rho3, c23
+
+    if not args.no_semiconvection:
+        result["semiconvection_1024x1024x512"] = semiconvection_leg(dev)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")

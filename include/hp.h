@@ -317,6 +317,15 @@ int hp_dot(hp_handle* h, const double* x, const double* y, long long n, double* 
 int hp_dot_noalloc(const double* x, const double* y, long long n, double* result, void* stream);
 const char* hp_noalloc_last_error(void);
 
+/*
+ * dst = src for n doubles with 16-byte non-temporal loads and stores: the plain streaming pass
+ * against which the benchmark states measured bandwidth (it is no step of the solve). Device
+ * pointers, 16-byte aligned, not overlapping; enqueued on `stream` (a hipStream_t, NULL: the null
+ * stream) without synchronising. Errors: HP_EINVAL (null pointer with n > 0, n < 0, misaligned
+ * or overlapping buffers), HP_EHIP.
+ */
+int hp_stream_copy(const double* src, double* dst, long long n, void* stream);
+
 /* ---- Learned warm start / preconditioner -------------------------------------------------
  * A small 3D U-Net (levels n, n/2, n/4 with 16/32/64 channels, 3x3x3 convolutions padded
  * periodically in x, y and with zeros in z, 2x2x2 mean pooling, nearest upsampling, skip

@@ -40,7 +40,7 @@ EXPORTS = [
     "hp_attach_net", "hp_warm_start", "hp_nn_train_step_anorm",
     "hp_dot_noalloc", "hp_noalloc_last_error",
     "hp_setup_two_density", "hp_update_coefficients_two_density", "hp_neumann_rhs",
-    "hp_pressure_rhs", "hp_pressure_update",
+    "hp_pressure_rhs", "hp_pressure_update", "hp_stream_copy",
 ]
 
 
@@ -151,6 +151,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                 "hp_neumann_rhs": (ip, [H, ip, ip, dp, dp]),
                 "hp_pressure_rhs": (ip, [H, ctypes.POINTER(RhsFields), dp]),
                 "hp_pressure_update": (ip, [H, ctypes.POINTER(UpdateFields)]),
+                "hp_stream_copy": (ip, [dp, dp, ctypes.c_longlong, vp]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -391,6 +392,17 @@ def dot_noalloc(x, y, result, stream=None):
     if rc != OK:
         msg = lib.hp_noalloc_last_error()
         raise HPError(rc, msg.decode() if msg else "")
+
+
+def stream_copy(src, dst, stream=None):
+    """hp_stream_copy: dst = src (device FP64 tensors of equal size) on `stream` (default: torch's
+    current stream)."""
+    torch = _torch()
+    d = torch.cuda.current_device()
+    n = src.numel()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load_library().hp_stream_copy(_ptr(src, "f64", n, d), _ptr(dst, "f64", n, d), n,
+                                         ctypes.c_void_p(st.cuda_stream)))
 
 
 def num_params() -> int:

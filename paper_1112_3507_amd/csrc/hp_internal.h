@@ -172,6 +172,8 @@ void launch_cast_scale_f32(const double* src, float* dst, double scale, int64_t 
 void launch_axpy_from_f32(double* x, const float* d, double scale, int64_t n, hipStream_t s);
 template <typename T>
 void launch_fill(T* x, T v, int64_t n, hipStream_t s);
+// dst = src with 16-byte non-temporal loads and stores (16-byte aligned pointers)
+void launch_stream_copy(const double* src, double* dst, int64_t n, hipStream_t s);
 template <typename T>
 void launch_copy(const T* src, T* dst, int64_t n, hipStream_t s);
 // flag nonzero if any entry is not finite

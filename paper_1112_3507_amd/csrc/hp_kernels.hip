@@ -357,11 +357,10 @@ __device__ __forceinline__ void ztile(const ZTiles& t, int& bx, int& by, int& bz
     bz = (int)(L / ((unsigned)t.tx * t.ty));
 }
 
-// Workgroups of `rows` waves, one x row of xw columns per wave; z chunks of at least kmin planes.
-#ifndef HP_ZMIN
-#define HP_ZMIN 4
-#endif
-static ZTiles ztiles(int nx, int ny, int nz, int xw, int kmin = HP_ZMIN, int rows = 4) {
+// Workgroups of `rows` waves, one x row of xw columns per wave; z chunks of at least kmin planes
+// (4: chunks of 2 or 8 planes were measured slower at 256^3).
+constexpr int kZMin = 4;
+static ZTiles ztiles(int nx, int ny, int nz, int xw, int kmin = kZMin, int rows = 4) {
     ZTiles t;
     t.tx = (nx + xw - 1) / xw;
     t.ty = (ny + rows - 1) / rows;
@@ -633,10 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
 }
 
 // ---- red-black split layout (finest level) ----
-#ifndef HP_ZS_ROWS
-#define HP_ZS_ROWS 4
-#endif
-constexpr int kRowsS = HP_ZS_ROWS;     // x rows per workgroup of the split-layout kernels
+constexpr int kRowsS = 4;     // x rows per workgroup of the split-layout kernels
 // Waves per row of the split kernels: a row tile spans 64 XW half positions, two waves where
 // rows have more than 64 half positions (up to 256 cells: the whole row), else one.
 static inline int split_xw(int hx) { return hx > 64 ? 2 : 1; }
@@ -716,15 +712,11 @@ struct SplitCol {
 // rotate by renaming: a register move at the loop end would wait for loads still in flight.
 static_assert(kRowsS >= 2, "the split kernels need separate first and last rows");
 
-#ifndef HP_ZS_WG1
-#define HP_ZS_WG1 0
-#endif
-#ifndef HP_ZS_WG2
-#define HP_ZS_WG2 768
-#endif
+// Workgroups the split kernels aim for with two-wave rows (one-wave rows aim for a wave count).
+constexpr int kSplitWG2 = 768;
 // Tiles of the split kernels over hx = nx/2 half positions: 64 XW per tile, kRowsS rows, z chunks
-// of at least HP_ZMIN planes.  Two-wave rows (the finest level of 256^3 and up) take about
-// HP_ZS_WG2 workgroups, three per CU: at 256^3 the operator apply and the half sweeps ran
+// of at least kZMin planes.  Two-wave rows (the finest level of 256^3 and up) take about
+// kSplitWG2 workgroups, three per CU: at 256^3 the operator apply and the half sweeps ran
 // 2-4% faster with 768 than with 1024, and 10-20% slower with counts that do not split evenly
 // over the 32 CUs of an XCD (640, 704, 832, 896, 1152).  One-wave rows aim for about 8192 waves.
 static ZTiles split_tiles(int hx, int ny, int nz) {
@@ -733,14 +725,14 @@ static ZTiles split_tiles(int hx, int ny, int nz) {
     t.tx = (hx + tw - 1) / tw;
     t.ty = (ny + kRowsS - 1) / kRowsS;
     const int cols = t.tx * t.ty;
-    const int wg = xw == 2 ? HP_ZS_WG2 : HP_ZS_WG1;
+    const int wg = xw == 2 ? kSplitWG2 : 0;
     t.kz = nz;
     if (wg > 0) {
         const int want = std::max(1, std::min(nz, (wg + cols / 2) / cols));
-        t.kz = std::max((nz + want - 1) / want, std::min(HP_ZMIN, nz));
+        t.kz = std::max((nz + want - 1) / want, std::min(kZMin, nz));
     } else {
         const int target = 8192 / (xw * kRowsS);
-        while (t.kz > HP_ZMIN && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < target) t.kz = (t.kz + 1) / 2;
+        while (t.kz > kZMin && (int64_t)cols * ((nz + t.kz - 1) / t.kz) < target) t.kz = (t.kz + 1) / 2;
     }
     t.tz = (nz + t.kz - 1) / t.kz;
     return t;
@@ -2713,6 +2705,36 @@ __global__ __launch_bounds__(kBlock) void k_axpy_from_f32(double* __restrict__ x
 void launch_axpy_from_f32(double* x, const float* d, double scale, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_axpy_from_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
                        0, s, x, d, scale, n);
+}
+
+// Streaming copy (the measured bandwidth reference of the roofline figures): each thread moves
+// four 16-byte vectors, loads and stores non-temporal (nothing is reused), consecutive threads
+// on consecutive vectors; an odd last double is copied by thread 0 of workgroup 0.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const dbl2* __restrict__ src, dbl2* __restrict__ dst,
+                                                        int64_t nv, const double* __restrict__ tail_src,
+                                                        double* __restrict__ tail_dst) {
+    const int64_t base = (int64_t)blockIdx.x * (4 * kBlock) + threadIdx.x;
+    dbl2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock;
+        if (i < nv) v[u] = __builtin_nontemporal_load(&src[i]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock;
+        if (i < nv) __builtin_nontemporal_store(v[u], &dst[i]);
+    }
+    if (tail_src && blockIdx.x == 0 && threadIdx.x == 0) *tail_dst = *tail_src;
+}
+
+void launch_stream_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
+    const int64_t nv = n / 2;
+    const int64_t blocks = std::max<int64_t>(1, (nv + 4 * kBlock - 1) / (4 * kBlock));
+    const bool odd = n & 1;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(kBlock), 0, s, (const dbl2*)src, (dbl2*)dst,
+                       nv, odd ? src + n - 1 : nullptr, odd ? dst + n - 1 : nullptr);
 }
 
 template <typename T>

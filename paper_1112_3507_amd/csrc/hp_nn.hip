@@ -42,9 +42,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int BX = 16, BY = 4, BZ = 4;                 // output brick
 constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;  // input brick with halo
 constexpr int HV = HX * HY * HZ;                       // 648 halo voxels
-#ifndef HP_CONV_SPW2
-#define HP_CONV_SPW2 1
-#endif
 constexpr int NCONV = 10;
 constexpr int CIN[NCONV] = {4, 16, 16, 32, 32, 64, 96, 32, 48, 16};
 constexpr int COUT[NCONV] = {16, 16, 32, 32, 64, 64, 32, 32, 16, 16};
@@ -747,7 +744,7 @@ void conv_launch(hp_net* N, int l, const bf16_t* a, int ca, int a_up, const bf16
     const int cin = ca + cb;
     // two z-slices per wave for the 16-channel outputs (more products per staged brick)
     const int g = (cin % 32 == 0) ? 4 : ((cin % 16 == 0) ? 2 : 1);  // 16-byte groups per chunk voxel
-    const int spw = (ct == 1 && g <= 2 && HP_CONV_SPW2) ? 2 : 1;
+    const int spw = (ct == 1 && g <= 2) ? 2 : 1;
     const unsigned blocks = (unsigned)(((L.nx + BX - 1) / BX) * ((L.ny + BY - 1) / BY) *
                                        ((L.nz + 4 * spw - 1) / (4 * spw)));
 #define CONV_LAUNCH2(CTV, GV, SV)                                                                    \

@@ -1558,6 +1558,15 @@ int hp_pressure_update(hp_handle* H, const hp_update_fields* f) {
     return check_launch();
 }
 
+int hp_stream_copy(const double* src, double* dst, long long n, void* stream) {
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!src || !dst))) return fail(HP_EINVAL, "null pointer or negative length");
+    if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(HP_EINVAL, "pointers must be 16-byte aligned");
+    if (n > 0 && src < dst + n && dst < src + n) return fail(HP_EINVAL, "source and destination overlap");
+    launch_stream_copy(src, dst, (int64_t)n, (hipStream_t)stream);
+    return check_launch();
+}
+
 int hp_dot(hp_handle* H, const double* x, const double* y, long long n, double* out) {
     if (!H || !out || (n > 0 && (!x || !y))) return fail(HP_EINVAL, "null argument");
     if (n < 0 || reduce_blocks_vec(n) > H->partial_cap) return fail(HP_EINVAL, "bad length");

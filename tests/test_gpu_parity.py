@@ -546,3 +546,20 @@ def test_dot_exact_cancellation():
     with make(p) as s:
         got = s.dot(dev(x), dev(y))
     assert abs(got) <= 2000 * 2.0 ** -53 * float(np.sum(np.abs(x * y)))
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 2048, (1 << 20) + 3])
+def test_stream_copy(n):
+    """hp_stream_copy (the benchmark's bandwidth reference) copies every entry, odd tails too, and
+    refuses overlapping or misaligned buffers."""
+    src = torch.rand(max(n, 1), dtype=torch.float64, device=DEV)[:n]
+    dst = torch.full((max(n, 1),), -1.0, dtype=torch.float64, device=DEV)[:n]
+    hp.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    if n >= 8:
+        with pytest.raises(hp.HPError):
+            hp.stream_copy(src[: n - 2], src[2:])
+        buf = torch.zeros(n + 1, dtype=torch.float64, device=DEV)
+        with pytest.raises(hp.HPError):
+            hp.stream_copy(src[: n - 1], buf[1:n])
