@@ -362,6 +362,56 @@ def semiconvection_leg(dev, steps=20, seed=7, n=(1024, 1024, 512)):
     return out
 
 
+def gresho_leg(dev, n=256, steps=100):
+    """The Gresho-vortex Mach ladder of Section 5 with the semi-implicit GPU stepper (TVD-RK2,
+    the whole fractional step in each stage, hp_advect + hp_pressure_rhs + two-density solve +
+    hp_pressure_update + EOS): kinetic energy after `steps` steps relative to the start, time per
+    step and solve iterations, for (a) one common time step (the sound-speed step of Ma = 0.1:
+    acoustic Courant numbers 0.5, 4.5, 45), (b) each Mach number's own sound-speed step (Courant
+    number 0.5, the paper's setting), (c) Ma = 0.001 at four times its sound-speed step."""
+    import numpy as np
+    import torch
+    from paper_1112_3507_amd import workloads as wl
+    from paper_1112_3507_amd.stepper import SemiImplicitStepper
+    gamma = 5.0 / 3.0
+
+    def sound_dt(mach, cfl=0.5):
+        prob, rho, mom, e, P = wl.gresho(n, mach)
+        c = np.sqrt(gamma * P / rho).max()
+        umax = np.sqrt(np.sum(mom * mom, axis=0)).max() / rho.min()
+        return cfl * prob.h[0] / (umax + c)
+
+    def run(mach, dt):
+        prob, rho, mom, e, _ = wl.gresho(n, mach)
+        ke0 = 0.5 * float(np.sum(np.sum(mom * mom, axis=0) / rho))
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        st = SemiImplicitStepper(prob.n, prob.h, prob.bc, dt, gamma, t(rho), t(mom), t(e))
+        st.step()                      # warm-up step (not timed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps - 1):
+            st.step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / (steps - 1)
+        ke = 0.5 * float(torch.sum(torch.sum(st.mom * st.mom, dim=0) / st.rho))
+        its = [q["iterations"] for q in st.stats]
+        ok = all(q["converged"] for q in st.stats)
+        st.close()
+        return {"dt": dt, "ke_ratio": ke / ke0, "ms_per_step": round(ms, 3),
+                "iterations_mean": round(sum(its) / len(its), 2), "all_converged": ok}
+
+    out = {"grid": [n, n], "steps": steps}
+    dtc = sound_dt(0.1)
+    for mach in (0.1, 0.01, 0.001):
+        log("bench: gresho Ma=%g" % mach)
+        out["common_dt_Ma%g" % mach] = run(mach, dtc)
+        out["sound_dt_Ma%g" % mach] = run(mach, sound_dt(mach))
+    out["sound_dt_x4_Ma0.001"] = run(0.001, 4 * sound_dt(0.001))
+    ks = [out["common_dt_Ma%g" % m]["ke_ratio"] for m in (0.1, 0.01, 0.001)]
+    out["common_dt_ke_ratio_spread"] = max(ks) - min(ks)
+    return out
+
+
 def host_cpu():
     """CPU model name and the number of host threads the process may use."""
     model = "unknown"
@@ -435,6 +485,7 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-semiconvection", action="store_true",
                     help="skip the 1024x1024x512 two-component sequence")
+    ap.add_argument("--no-gresho", action="store_true", help="skip the Gresho-vortex Mach ladder")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -545,6 +596,9 @@ def main():
             var["learned_fcg"] = lv["fcg"]
             result["learned_training"] = lv["training"]
         del rho3, c23
+
+    if not args.no_gresho:
+        result["gresho_ladder"] = gresho_leg(dev)
 
     if not args.no_semiconvection:
         result["semiconvection_1024x1024x512"] = semiconvection_leg(dev)

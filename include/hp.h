@@ -245,6 +245,32 @@ typedef struct {
  */
 int hp_pressure_update(hp_handle* h, const hp_update_fields* f);
 
+/*
+ * Steps (i)-(iii) for inviscid flow, the explicit part of a time step: interface velocities of
+ * eq. step1; the modified advective flux q_face u_{i+1/2} of each conserved field (rho, the three
+ * momenta, e), with q_face reconstructed componentwise on the upwind side of the interface by
+ * second-order ENO (the smaller in magnitude of the two one-sided differences; the advective
+ * Jacobian has all eigenvalues u, so no characteristic projection is needed); and
+ * q* = q - dt div(flux) with the handle's dt, giving rho^{n+1}, (rho u)* and e*. Closed boundaries
+ * carry no flux and mirror the edge cell for the reconstruction; periodic axes wrap.
+ *   rho, e   cell arrays; mom: 3 cell arrays (x, y, z). Outputs likewise; no output may alias an
+ *            input or another output. Errors: HP_EINVAL, HP_EHIP.
+ */
+int hp_advect(hp_handle* h, const double* rho, const double* mom, const double* e, double* rho_out,
+              double* mom_out, double* e_out);
+
+/*
+ * Step (x), ideal gas: P = (gamma - 1)(e - |rho u|^2 / (2 rho)) and, if c2 is not NULL,
+ * c2 = gamma P / rho (the squared sound speed of eq. cpoiss). Cell arrays (mom: 3 arrays) of the
+ * handle's grid; gamma > 1. Errors: HP_EINVAL, HP_EHIP.
+ */
+int hp_eos_ideal(hp_handle* h, const double* rho, const double* mom, const double* e, double gamma,
+                 double* p, double* c2);
+
+/* y = a x + b y for device vectors of n entries (the Runge-Kutta averages of a time step), on the
+ * handle's stream. Errors: HP_EINVAL (null vector with n > 0, n < 0), HP_EHIP. */
+int hp_axpby(hp_handle* h, double a, const double* x, double b, double* y, long long n);
+
 /* ---- Building blocks of the solve, exposed for verification and composition ------------------
  * Levels are numbered 0 (fine) .. hp_num_levels()-1 (coarsest). Vectors of level l are device
  * arrays of that level's cell count; FP32 variants ("_f32") act on the FP32 copies of the

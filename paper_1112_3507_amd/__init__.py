@@ -40,7 +40,8 @@ EXPORTS = [
     "hp_attach_net", "hp_warm_start", "hp_nn_train_step_anorm",
     "hp_dot_noalloc", "hp_noalloc_last_error",
     "hp_setup_two_density", "hp_update_coefficients_two_density", "hp_neumann_rhs",
-    "hp_pressure_rhs", "hp_pressure_update", "hp_stream_copy",
+    "hp_pressure_rhs", "hp_pressure_update", "hp_stream_copy", "hp_advect", "hp_eos_ideal",
+    "hp_axpby",
 ]
 
 
@@ -152,6 +153,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                 "hp_pressure_rhs": (ip, [H, ctypes.POINTER(RhsFields), dp]),
                 "hp_pressure_update": (ip, [H, ctypes.POINTER(UpdateFields)]),
                 "hp_stream_copy": (ip, [dp, dp, ctypes.c_longlong, vp]),
+                "hp_advect": (ip, [H, dp, dp, dp, dp, dp, dp]),
+                "hp_eos_ideal": (ip, [H, dp, dp, dp, ctypes.c_double, dp, dp]),
+                "hp_axpby": (ip, [H, ctypes.c_double, dp, ctypes.c_double, dp, ctypes.c_longlong]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -290,6 +294,25 @@ class Solver:
                          _ptr(e_star, "f64", c, d), _ptr(mom_out, "f64", 3 * c, d),
                          _ptr(uface_out, "f64", 3 * c, d), _ptr(e_out, "f64", c, d))
         _check(self._lib.hp_pressure_update(self._h, ctypes.byref(f)))
+
+    def advect(self, rho, mom, e, rho_out, mom_out, e_out):
+        """hp_advect: rho^{n+1}, (rho u)*, e* of the explicit inviscid step (handle's dt)."""
+        c, d = self.ncells, self.device
+        _check(self._lib.hp_advect(self._h, _ptr(rho, "f64", c, d), _ptr(mom, "f64", 3 * c, d),
+                                   _ptr(e, "f64", c, d), _ptr(rho_out, "f64", c, d),
+                                   _ptr(mom_out, "f64", 3 * c, d), _ptr(e_out, "f64", c, d)))
+
+    def eos_ideal(self, rho, mom, e, gamma, p, c2=None):
+        """hp_eos_ideal: pressure (and squared sound speed) of an ideal gas."""
+        c, d = self.ncells, self.device
+        _check(self._lib.hp_eos_ideal(self._h, _ptr(rho, "f64", c, d), _ptr(mom, "f64", 3 * c, d),
+                                      _ptr(e, "f64", c, d), float(gamma), _ptr(p, "f64", c, d),
+                                      _ptr(c2, "f64", c, d) if c2 is not None else None))
+
+    def axpby(self, a, x, b, y):
+        """hp_axpby: y = a x + b y on the handle's stream."""
+        n, d = x.numel(), self.device
+        _check(self._lib.hp_axpby(self._h, float(a), _ptr(x, "f64", n, d), float(b), _ptr(y, "f64", n, d), n))
 
     # -- the solve --
     def solve(self, rhs, p, tol: float = 1e-10, check: bool = True) -> dict:

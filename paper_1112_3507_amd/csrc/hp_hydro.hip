@@ -150,9 +150,103 @@ __global__ __launch_bounds__(256) void k_pressure_update(HGeo g, UpdArgs A) {
     A.e_out[a] = A.e_star[a] - g.dt * (pa * divn + ug);
 }
 
+// ---- the explicit advective part (steps (i)-(iii)) and the equation of state ----
+
+// q at distance s (+-1, +-2) along axis d from coordinate c: wrapped on a periodic axis, the edge
+// cell repeated beyond a closed boundary (a zero-gradient mirror for the reconstruction)
+__device__ __forceinline__ int reach(const HGeo& g, int d, int c, int s) {
+    int q = c + s;
+    const int n = g.n[d];
+    if (g.per[d]) return ((q % n) + n) % n;
+    return q < 0 ? 0 : (q >= n ? n - 1 : q);
+}
+
+// second-order ENO: the smaller in magnitude of the two one-sided differences (ties: the second)
+__device__ __forceinline__ double eno_slope(double dm, double dp) { return fabs(dm) < fabs(dp) ? dm : dp; }
+
+// the value at the interface between cells q1 (low) and q2 (high), reconstructed on the upwind
+// side of the interface velocity u from the cells q0 .. q3 around it
+__device__ __forceinline__ double eno_face(double u, double q0, double q1, double q2, double q3) {
+    return u >= 0.0 ? q1 + 0.5 * eno_slope(q1 - q0, q2 - q1) : q2 - 0.5 * eno_slope(q2 - q1, q3 - q2);
+}
+
+struct AdvArgs {
+    const double *rho, *mom, *e;
+    double *rho_out, *mom_out, *e_out;
+    int64_t N;
+};
+
+// One thread per cell: for every axis the fluxes through the cell's low and high interfaces of the
+// five conserved fields (rho, three momenta, e), each interface velocity from eq. step1 and each
+// field value reconstructed on its upwind side; q* = q - dt div(flux).
+__global__ __launch_bounds__(256) void k_advect(HGeo g, AdvArgs A) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const int c[3] = {i, j, k};
+    const int64_t a = cell(g, i, j, k);
+    const double* q[5] = {A.rho, A.mom, A.mom + A.N, A.mom + 2 * A.N, A.e};
+    double div[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d) {
+        if (g.n[d] == 1) continue;
+        int64_t b[5];  // cells at -2 .. +2 along d
+        for (int s = -2; s <= 2; ++s) b[s + 2] = along(g, i, j, k, d, reach(g, d, c[d], s));
+        const double* md = A.mom + (int64_t)d * A.N;
+        // interface velocities of eq. step1; zero at a closed boundary
+        const bool hi = g.per[d] || c[d] < g.n[d] - 1, lo = g.per[d] || c[d] > 0;
+        const double uh = hi ? (md[a] + md[b[3]]) / (A.rho[a] + A.rho[b[3]]) : 0.0;
+        const double ul = lo ? (md[b[1]] + md[a]) / (A.rho[b[1]] + A.rho[a]) : 0.0;
+        for (int f = 0; f < 5; ++f) {
+            const double* qf = q[f];
+            const double v0 = qf[b[0]], v1 = qf[b[1]], v2 = qf[a], v3 = qf[b[3]], v4 = qf[b[4]];
+            const double fh = uh * eno_face(uh, v1, v2, v3, v4);
+            const double fl = ul * eno_face(ul, v0, v1, v2, v3);
+            div[f] += (fh - fl) / g.h[d];
+        }
+    }
+    A.rho_out[a] = A.rho[a] - g.dt * div[0];
+    for (int d = 0; d < 3; ++d) A.mom_out[(int64_t)d * A.N + a] = q[1 + d][a] - g.dt * div[1 + d];
+    A.e_out[a] = A.e[a] - g.dt * div[4];
+}
+
+// ideal gas: P = (gamma - 1)(e - |rho u|^2 / (2 rho)), c_s^2 = gamma P / rho
+__global__ __launch_bounds__(256) void k_eos(const double* __restrict__ rho, const double* __restrict__ mom,
+                                             const double* __restrict__ e, double gamma, double* __restrict__ p,
+                                             double* __restrict__ c2, int64_t N) {
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a >= N) return;
+    const double r = rho[a], mx = mom[a], my = mom[N + a], mz = mom[2 * N + a];
+    const double pa = (gamma - 1.0) * (e[a] - 0.5 * (mx * mx + my * my + mz * mz) / r);
+    p[a] = pa;
+    if (c2) c2[a] = gamma * pa / r;
+}
+
 }  // namespace
 
 namespace hp {
+
+int hydro_launch_advect(const int n[3], const int bc[3], const double h[3], double dt, const double* rho,
+                        const double* mom, const double* e, double* rho_out, double* mom_out, double* e_out,
+                        hipStream_t s) {
+    HGeo g;
+    for (int d = 0; d < 3; ++d) {
+        g.n[d] = n[d];
+        g.per[d] = (bc[d] == HP_BC_PERIODIC && n[d] >= 2);
+        g.h[d] = h[d];
+    }
+    g.dt = dt;
+    AdvArgs A{rho, mom, e, rho_out, mom_out, e_out, (int64_t)n[0] * n[1] * n[2]};
+    dim3 grid((unsigned)((n[0] + 63) / 64), (unsigned)((n[1] + 3) / 4), (unsigned)n[2]);
+    hipLaunchKernelGGL(k_advect, grid, dim3(256), 0, s, g, A);
+    return hipGetLastError() == hipSuccess ? HP_OK : HP_EHIP;
+}
+
+int hydro_launch_eos(int64_t N, const double* rho, const double* mom, const double* e, double gamma, double* p,
+                     double* c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_eos, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, rho, mom, e, gamma, p, c2, N);
+    return hipGetLastError() == hipSuccess ? HP_OK : HP_EHIP;
+}
 
 int hydro_launch_rhs(const int n[3], const int bc[3], const double h[3], double dt, const hp_rhs_fields* f,
                      double* rhs, hipStream_t s) {

@@ -201,6 +201,11 @@ int hydro_launch_rhs(const int n[3], const int bc[3], const double h[3], double 
                      double* rhs, hipStream_t s);
 int hydro_launch_update(const int n[3], const int bc[3], const double h[3], double dt,
                         const hp_update_fields* f, hipStream_t s);
+int hydro_launch_advect(const int n[3], const int bc[3], const double h[3], double dt, const double* rho,
+                        const double* mom, const double* e, double* rho_out, double* mom_out, double* e_out,
+                        hipStream_t s);
+int hydro_launch_eos(int64_t N, const double* rho, const double* mom, const double* e, double gamma, double* p,
+                     double* c2, hipStream_t s);
 
 // ---- learned stage (hp_nn.hip) ----
 int nn_grid(const hp_net* net, int* nx, int* ny, int* nz);

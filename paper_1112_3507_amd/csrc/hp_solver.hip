@@ -1558,6 +1558,44 @@ int hp_pressure_update(hp_handle* H, const hp_update_fields* f) {
     return check_launch();
 }
 
+int hp_advect(hp_handle* H, const double* rho, const double* mom, const double* e, double* rho_out,
+              double* mom_out, double* e_out) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (!rho || !mom || !e || !rho_out || !mom_out || !e_out) return fail(HP_EINVAL, "null field");
+    const LevelData& F = H->lv[0];
+    const int64_t N = F.N;
+    struct R { const char* lo; const char* hi; };
+    auto rng = [&](const double* q, int arrays) { return R{(const char*)q, (const char*)(q + arrays * N)}; };
+    const R arr[] = {rng(rho, 1), rng(mom, 3), rng(e, 1), rng(rho_out, 1), rng(mom_out, 3), rng(e_out, 1)};
+    for (int o = 3; o < 6; ++o)
+        for (int q = 0; q < 6; ++q)
+            if (q != o && arr[o].lo < arr[q].hi && arr[q].lo < arr[o].hi)
+                return fail(HP_EINVAL, "outputs must not alias inputs or each other");
+    const int bcs[3] = {H->bc.x, H->bc.y, H->bc.z};
+    if (hydro_launch_advect(F.n, bcs, F.h, H->dt, rho, mom, e, rho_out, mom_out, e_out, H->stream) != HP_OK)
+        return check_launch();
+    return check_launch();
+}
+
+int hp_eos_ideal(hp_handle* H, const double* rho, const double* mom, const double* e, double gamma, double* p,
+                 double* c2) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (!rho || !mom || !e || !p) return fail(HP_EINVAL, "null field");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(HP_EINVAL, "gamma must be > 1");
+    if (hydro_launch_eos(H->lv[0].N, rho, mom, e, gamma, p, c2, H->stream) != HP_OK) return check_launch();
+    return check_launch();
+}
+
+int hp_axpby(hp_handle* H, double a, const double* x, double b, double* y, long long n) {
+    if (!H) return fail(HP_EINVAL, "null handle");
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(HP_EINVAL, "null vector or negative length");
+    if (n > 0) launch_axpby(a, x, b, y, (int64_t)n, H->stream);
+    return check_launch();
+}
+
 int hp_stream_copy(const double* src, double* dst, long long n, void* stream) {
     g_err.clear();
     if (n < 0 || (n > 0 && (!src || !dst))) return fail(HP_EINVAL, "null pointer or negative length");

@@ -249,3 +249,34 @@ def hydro_state(n, mach: float, seed: int = 0) -> HydroState:
     conc = np.broadcast_to((0.25 + 0.05 * np.tanh((z - 0.5) / 0.02))[:, None, None], rho_n.shape).copy()
     p = Problem(base.name + "_hydro", base.n, base.h, base.bc, rho_n, base.c2, base.dt, rho_face=rho_np1)
     return HydroState(p, p_n, mom_n, mom_star, e_star, visc, temp, conc, 1e-3 * rho_n)
+
+
+def gresho(n: int, mach: float, gamma: float = 5.0 / 3.0):
+    """The Gresho vortex of Section 5 on the unit square, n x n x 1 cells, periodic in x and y
+    (the z axis has one cell). rho = 1; with r the distance from (0.5, 0.5) and theta its angle,
+    u_phi = 5r (r <= 0.2), 2 - 5r (0.2 <= r <= 0.4), 0 beyond; P = P0 + 12.5 r^2,
+    P0 + 12.5 r^2 + 4 (1 - 5r - ln 0.2 + ln r), P0 - 2 + 4 ln 2 in the same ranges,
+    P0 = rho / (gamma Ma^2). The velocity is the rotation u = u_phi (-sin theta, cos theta), whose
+    centrifugal force this pressure balances (the paper's text prints the x component without its
+    minus sign). Returns (Problem, rho, momentum (3, 1, n, n), total energy e, P)."""
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(c, c, indexing="xy")          # (ny, nx)
+    dx, dy = X - 0.5, Y - 0.5
+    r = np.sqrt(dx * dx + dy * dy)
+    th = np.arctan2(dy, dx)
+    uphi = np.where(r <= 0.2, 5.0 * r, np.where(r <= 0.4, 2.0 - 5.0 * r, 0.0))
+    p0 = 1.0 / (gamma * mach * mach)
+    rs = np.maximum(r, 1e-300)
+    P = np.where(r <= 0.2, p0 + 12.5 * r * r,
+                 np.where(r <= 0.4, p0 + 12.5 * r * r + 4.0 * (1.0 - 5.0 * r - np.log(0.2) + np.log(rs)),
+                          p0 - 2.0 + 4.0 * np.log(2.0)))
+    rho = np.ones((1, n, n))
+    mom = np.zeros((3, 1, n, n))
+    mom[0, 0] = -np.sin(th) * uphi
+    mom[1, 0] = np.cos(th) * uphi
+    P = P.reshape(1, n, n)
+    e = P / (gamma - 1.0) + 0.5 * np.sum(mom * mom, axis=0) / rho
+    prob = Problem("gresho_%d_Ma%g" % (n, mach), (n, n, 1), (h, h, h), (PERIODIC, PERIODIC, NEUMANN),
+                   rho, np.full(rho.shape, gamma * p0), 1.0)
+    return prob, rho, mom, e, P
