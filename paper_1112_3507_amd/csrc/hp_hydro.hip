@@ -19,10 +19,9 @@
 // velocity is zero and the interface pressure is the cell's own; an axis of one cell has no
 // gradient or divergence. The interface value of rho kappa_c is the mean of its two cells.
 //
-// Both passes are one thread per cell over natural-order FP64 arrays, bound by HBM bandwidth
-// (about 1 flop per byte): workgroups of 64 x 4 cells in x and y so that x neighbours come from
-// the same cache lines and y neighbours from rows the workgroup itself loads; z neighbours are
-// re-read from the caches.
+// Both passes walk z columns over natural-order FP64 arrays (HBM-bound, about 1 flop per byte):
+// workgroups of 64 x 4 columns in x and y so that x neighbours come from the same cache lines and
+// y neighbours from rows the workgroup itself loads; the z neighbours stay in registers.
 #include "hp.h"
 #include "hp_internal.h"
 
@@ -69,41 +68,145 @@ struct RhsArgs {
     double* b;
 };
 
-__global__ __launch_bounds__(256) void k_pressure_rhs(HGeo g, RhsArgs A) {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int k = blockIdx.z;
+// z planes per thread column in the two passes around the solve
+constexpr int kHZ = 16;
+
+// Column tile (64 x 4 columns, one chunk of kHZ planes) of this workgroup of a 1-D grid. The
+// hardware hands workgroup L to XCD L % 8; numbering the tiles so that each XCD takes one
+// contiguous range of them (whole x-y planes of chunks) keeps the y neighbour rows of a tile in
+// the L2 of the XCD that reads them.
+struct HTiles {
+    int tx, ty, tz;
+};
+
+__device__ __forceinline__ void htile(const HTiles& t, int& i, int& j, int& k0) {
+    const unsigned total = (unsigned)t.tx * t.ty * t.tz;
+    unsigned L = blockIdx.x;
+    if ((total & 7u) == 0) L = (L & 7u) * (total >> 3) + (L >> 3);
+    i = (int)(L % (unsigned)t.tx) * 64 + (threadIdx.x & 63);
+    j = (int)((L / (unsigned)t.tx) % (unsigned)t.ty) * 4 + (threadIdx.x >> 6);
+    k0 = (int)(L / ((unsigned)t.tx * t.ty)) * kHZ;
+}
+
+static HTiles htiles(const int n[3]) {
+    return HTiles{(n[0] + 63) / 64, (n[1] + 3) / 4, (n[2] + kHZ - 1) / kHZ};
+}
+
+// Neighbours of the cells of one axis, as the three values (low neighbour, cell, high neighbour)
+// of each array, and whether the two faces exist.
+struct Line {
+    bool lo, hi;
+    double p[3], rn[3], r1[3], ms[3], c[3], k[3];
+};
+
+// The contributions of one axis to the rhs (steps (iv)-(v)): u_d (grad P^n)_d, (div u*)_d and the
+// d-part of div(rho kappa_c grad c); ih = 1/h_d.
+__device__ __forceinline__ void rhs_axis(const Line& L, double ud, double ih, bool tc, double& adv, double& divu,
+                                         double& dc) {
+    const double phi = L.hi ? pbnd(L.p[1], L.rn[1], L.p[2], L.rn[2]) : L.p[1];
+    const double plo = L.lo ? pbnd(L.p[0], L.rn[0], L.p[1], L.rn[1]) : L.p[1];
+    adv += ud * ((phi - plo) * ih);
+    const double uhi = L.hi ? (L.ms[1] + L.ms[2]) / (L.r1[1] + L.r1[2]) : 0.0;
+    const double ulo = L.lo ? (L.ms[0] + L.ms[1]) / (L.r1[0] + L.r1[1]) : 0.0;
+    divu += (uhi - ulo) * ih;
+    if (tc) {
+        const double fhi = L.hi ? 0.5 * (L.k[1] + L.k[2]) * (L.c[2] - L.c[1]) * ih : 0.0;
+        const double flo = L.lo ? 0.5 * (L.k[0] + L.k[1]) * (L.c[1] - L.c[0]) * ih : 0.0;
+        dc += (fhi - flo) * ih;
+    }
+}
+
+// x or y neighbour line of cell a (coordinate c along axis d, stride st): the neighbours from
+// memory, the cell itself from the z ring Z; ms is the momentum component of axis d
+__device__ __forceinline__ void load_line(const HGeo& g, const RhsArgs& A, const double* ms, int d, int c, int64_t a,
+                                          int64_t st, bool tc, const Line& Z, Line& L) {
+    int tl, th;
+    L.lo = neighbour(g, d, c, -1, &tl);
+    L.hi = neighbour(g, d, c, 1, &th);
+    const int64_t bl = L.lo ? a + (int64_t)(tl - c) * st : a, bh = L.hi ? a + (int64_t)(th - c) * st : a;
+    L.p[1] = Z.p[1];
+    L.rn[1] = Z.rn[1];
+    L.r1[1] = Z.r1[1];
+    L.ms[1] = ms[a];
+    L.c[1] = Z.c[1];
+    L.k[1] = Z.k[1];
+    const int64_t idx[2] = {bl, bh};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int q = 2 * e;
+        L.p[q] = A.p_n[idx[e]];
+        L.rn[q] = A.rho_n[idx[e]];
+        L.r1[q] = A.rho_np1[idx[e]];
+        L.ms[q] = ms[idx[e]];
+        L.c[q] = tc ? A.conc_n[idx[e]] : 0.0;
+        L.k[q] = tc ? A.rkc_n[idx[e]] : 0.0;
+    }
+}
+
+// One thread per (x, y) column walking kHZ planes: the x and y neighbours come from memory (the
+// x ones from the same cache lines), the z neighbours of the six stencil arrays from a ring of
+// registers (each plane is loaded once per column).
+// TC: the two-component terms (temp_n, conc_n, rkc_n given).
+template <bool TC>
+__global__ __launch_bounds__(256) void k_pressure_rhs(HGeo g, HTiles t, RhsArgs A) {
+    int i, j, k0;
+    htile(t, i, j, k0);
     if (i >= g.n[0] || j >= g.n[1]) return;
-    const int c[3] = {i, j, k};
-    const int64_t a = cell(g, i, j, k);
-    const double rn = A.rho_n[a], r1 = A.rho_np1[a], pa = A.p_n[a];
-    const double m = 1.0 / (rn * A.c2_n[a]);
-    double adv = 0.0, divu = 0.0, dc = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        if (g.n[d] == 1) continue;
-        int th, tl;
-        const bool hi = neighbour(g, d, c[d], 1, &th), lo = neighbour(g, d, c[d], -1, &tl);
-        const int64_t bh = hi ? along(g, i, j, k, d, th) : a, bl = lo ? along(g, i, j, k, d, tl) : a;
-        const double* ms = A.mom_star + (int64_t)d * A.N;
-        // grad P^n (eqs. pbnd, nablaP with rho^n)
-        const double phi = hi ? pbnd(pa, rn, A.p_n[bh], A.rho_n[bh]) : pa;
-        const double plo = lo ? pbnd(A.p_n[bl], A.rho_n[bl], pa, rn) : pa;
-        adv += (A.mom_n[(int64_t)d * A.N + a] / rn) * ((phi - plo) / g.h[d]);
-        // div u*: interface velocities of eq. step1 with (rho u)* and rho^{n+1}
-        const double uhi = hi ? (ms[a] + ms[bh]) / (r1 + A.rho_np1[bh]) : 0.0;
-        const double ulo = lo ? (ms[bl] + ms[a]) / (A.rho_np1[bl] + r1) : 0.0;
-        divu += (uhi - ulo) / g.h[d];
-        if (A.temp_n) {  // div(rho kappa_c grad c), mean interface coefficient, no wall flux
-            const double ca = A.conc_n[a], ka = A.rkc_n[a];
-            const double fhi = hi ? 0.5 * (ka + A.rkc_n[bh]) * (A.conc_n[bh] - ca) / g.h[d] : 0.0;
-            const double flo = lo ? 0.5 * (A.rkc_n[bl] + ka) * (ca - A.conc_n[bl]) / g.h[d] : 0.0;
-            dc += (fhi - flo) / g.h[d];
+    const int nz = g.n[2];
+    const int k1 = min(k0 + kHZ, nz);
+    const int64_t sxy = (int64_t)g.n[0] * g.n[1];
+    constexpr bool tc = TC;
+    const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
+    const double* msz = A.mom_star + 2 * A.N;
+    const int64_t col = cell(g, i, j, 0);
+    // ring: z line values of planes k-1, k, k+1 (position 0, 1, 2)
+    Line Z;
+    auto load_plane = [&](int kp, int q) {
+        const int64_t a = col + (int64_t)kp * sxy;
+        Z.p[q] = A.p_n[a];
+        Z.rn[q] = A.rho_n[a];
+        Z.r1[q] = A.rho_np1[a];
+        Z.ms[q] = msz[a];
+        Z.c[q] = tc ? A.conc_n[a] : 0.0;
+        Z.k[q] = tc ? A.rkc_n[a] : 0.0;
+    };
+    int tz;
+    if (neighbour(g, 2, k0, -1, &tz)) load_plane(tz, 0);
+    load_plane(k0, 1);
+    for (int k = k0; k < k1; ++k) {
+        Z.lo = nz > 1 && neighbour(g, 2, k, -1, &tz);
+        Z.hi = nz > 1 && neighbour(g, 2, k, 1, &tz);
+        if (Z.hi) load_plane(tz, 2);
+        const int64_t a = col + (int64_t)k * sxy;
+        const double irn = 1.0 / Z.rn[1];
+        const double m = irn / A.c2_n[a];
+        double adv = 0.0, divu = 0.0, dc = 0.0;
+        if (g.n[0] > 1) {
+            Line L;
+            load_line(g, A, A.mom_star, 0, i, a, 1, tc, Z, L);
+            rhs_axis(L, A.mom_n[a] * irn, ih[0], tc, adv, divu, dc);
+        }
+        if (g.n[1] > 1) {
+            Line L;
+            load_line(g, A, A.mom_star + A.N, 1, j, a, g.n[0], tc, Z, L);
+            rhs_axis(L, A.mom_n[A.N + a] * irn, ih[1], tc, adv, divu, dc);
+        }
+        if (nz > 1) rhs_axis(Z, A.mom_n[2 * A.N + a] * irn, ih[2], tc, adv, divu, dc);
+        double b = m * (Z.p[1] - g.dt * adv) - g.dt * divu;
+        if (A.visc) b -= (2.0 * g.dt / 3.0) * (m * irn) * A.visc[a];
+        if (tc) b -= (3.0 * g.dt / 4.0) * m * A.r_gas * A.temp_n[a] * dc;
+        A.b[a] = b;
+        // the ring moves up one plane
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            Z.p[q] = Z.p[q + 1];
+            Z.rn[q] = Z.rn[q + 1];
+            Z.r1[q] = Z.r1[q + 1];
+            Z.ms[q] = Z.ms[q + 1];
+            Z.c[q] = Z.c[q + 1];
+            Z.k[q] = Z.k[q + 1];
         }
     }
-    double b = m * (pa - g.dt * adv) - g.dt * divu;
-    if (A.visc) b -= (2.0 * g.dt / 3.0) * (m / rn) * A.visc[a];
-    if (A.temp_n) b -= (3.0 * g.dt / 4.0) * m * A.r_gas * A.temp_n[a] * dc;
-    A.b[a] = b;
 }
 
 struct UpdArgs {
@@ -112,42 +215,76 @@ struct UpdArgs {
     int64_t N;
 };
 
-__global__ __launch_bounds__(256) void k_pressure_update(HGeo g, UpdArgs A) {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int k = blockIdx.z;
+// The updates of one axis (steps (vii)-(viii)): grad P with rho^{n+1}, the high interface
+// velocity u^{n+1} (returned through uf) and the axis' part of its divergence
+__device__ __forceinline__ double upd_axis(bool lo, bool hi, const double* p, const double* r, const double* ms,
+                                           double dt, double ih, double& uf, double& divn) {
+    const double phi = hi ? pbnd(p[1], r[1], p[2], r[2]) : p[1];
+    const double plo = lo ? pbnd(p[0], r[0], p[1], r[1]) : p[1];
+    uf = hi ? (ms[1] + ms[2]) / (r[1] + r[2]) - dt * (p[2] - p[1]) * ih * 2.0 / (r[2] + r[1]) : 0.0;
+    const double ul = lo ? (ms[0] + ms[1]) / (r[0] + r[1]) - dt * (p[1] - p[0]) * ih * 2.0 / (r[1] + r[0]) : 0.0;
+    divn += (uf - ul) * ih;
+    return (phi - plo) * ih;
+}
+
+__global__ __launch_bounds__(256) void k_pressure_update(HGeo g, HTiles t, UpdArgs A) {
+    int i, j, k0;
+    htile(t, i, j, k0);
     if (i >= g.n[0] || j >= g.n[1]) return;
-    const int c[3] = {i, j, k};
-    const int64_t a = cell(g, i, j, k);
-    const double pa = A.p[a], r1 = A.rho_np1[a];
-    double gp[3] = {0.0, 0.0, 0.0}, mom[3], divn = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        const double* ms = A.mom_star + (int64_t)d * A.N;
-        double uf = 0.0;
-        if (g.n[d] > 1) {
-            int th, tl;
-            const bool hi = neighbour(g, d, c[d], 1, &th), lo = neighbour(g, d, c[d], -1, &tl);
-            const int64_t bh = hi ? along(g, i, j, k, d, th) : a, bl = lo ? along(g, i, j, k, d, tl) : a;
-            const double ph = A.p[bh], pl = A.p[bl], rh = A.rho_np1[bh], rl = A.rho_np1[bl];
-            // step (vii): grad P with rho^{n+1}
-            const double phi = hi ? pbnd(pa, r1, ph, rh) : pa;
-            const double plo = lo ? pbnd(pl, rl, pa, r1) : pa;
-            gp[d] = (phi - plo) / g.h[d];
-            // step (viii): the interface velocity on the high side, and the one on the low side
-            // (the low neighbour's high interface) for the divergence
-            if (hi) uf = (ms[a] + ms[bh]) / (r1 + rh) - g.dt * (ph - pa) / g.h[d] * 2.0 / (rh + r1);
-            const double ul =
-                lo ? (ms[bl] + ms[a]) / (rl + r1) - g.dt * (pa - pl) / g.h[d] * 2.0 / (r1 + rl) : 0.0;
-            divn += (uf - ul) / g.h[d];
+    const int nz = g.n[2];
+    const int k1 = min(k0 + kHZ, nz);
+    const int64_t sxy = (int64_t)g.n[0] * g.n[1];
+    const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
+    const double* msz = A.mom_star + 2 * A.N;
+    const int64_t col = cell(g, i, j, 0);
+    double zp[3] = {0.0, 0.0, 0.0}, zr[3] = {1.0, 1.0, 1.0}, zm[3] = {0.0, 0.0, 0.0};
+    auto load_plane = [&](int kp, int q) {
+        const int64_t a = col + (int64_t)kp * sxy;
+        zp[q] = A.p[a];
+        zr[q] = A.rho_np1[a];
+        zm[q] = msz[a];
+    };
+    int tz;
+    if (neighbour(g, 2, k0, -1, &tz)) load_plane(tz, 0);
+    load_plane(k0, 1);
+    for (int k = k0; k < k1; ++k) {
+        const bool zlo = nz > 1 && neighbour(g, 2, k, -1, &tz);
+        const bool zhi = nz > 1 && neighbour(g, 2, k, 1, &tz);
+        if (zhi) load_plane(tz, 2);
+        const int64_t a = col + (int64_t)k * sxy;
+        const int c[2] = {i, j};
+        const int64_t st[2] = {1, g.n[0]};
+        double gp[3] = {0.0, 0.0, 0.0}, uf[3] = {0.0, 0.0, 0.0}, divn = 0.0;
+        for (int d = 0; d < 2; ++d) {
+            if (g.n[d] == 1) continue;
+            int tl, th;
+            const bool lo = neighbour(g, d, c[d], -1, &tl), hi = neighbour(g, d, c[d], 1, &th);
+            const int64_t bl = lo ? a + (int64_t)(tl - c[d]) * st[d] : a;
+            const int64_t bh = hi ? a + (int64_t)(th - c[d]) * st[d] : a;
+            const double* ms = A.mom_star + (int64_t)d * A.N;
+            const double pv[3] = {A.p[bl], zp[1], A.p[bh]};
+            const double rv[3] = {A.rho_np1[bl], zr[1], A.rho_np1[bh]};
+            const double mv[3] = {ms[bl], ms[a], ms[bh]};
+            gp[d] = upd_axis(lo, hi, pv, rv, mv, g.dt, ih[d], uf[d], divn);
         }
-        mom[d] = ms[a] - g.dt * gp[d];
-        A.mom_out[(int64_t)d * A.N + a] = mom[d];
-        A.uface_out[(int64_t)d * A.N + a] = uf;
+        if (nz > 1) gp[2] = upd_axis(zlo, zhi, zp, zr, zm, g.dt, ih[2], uf[2], divn);
+        // step (vii): momentum; step (ix): e^{n+1} = e* - dt (P div u^{n+1} + u^{n+1} . grad P)
+        const double ir = 1.0 / zr[1];
+        double ug = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double md = A.mom_star[(int64_t)d * A.N + a] - g.dt * gp[d];
+            A.mom_out[(int64_t)d * A.N + a] = md;
+            A.uface_out[(int64_t)d * A.N + a] = uf[d];
+            ug += (md * ir) * gp[d];
+        }
+        A.e_out[a] = A.e_star[a] - g.dt * (zp[1] * divn + ug);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            zp[q] = zp[q + 1];
+            zr[q] = zr[q + 1];
+            zm[q] = zm[q + 1];
+        }
     }
-    // step (ix): e^{n+1} = e* - dt (P div u^{n+1} + u^{n+1} . grad P)
-    double ug = 0.0;
-    for (int d = 0; d < 3; ++d) ug += (mom[d] / r1) * gp[d];
-    A.e_out[a] = A.e_star[a] - g.dt * (pa * divn + ug);
 }
 
 // ---- the explicit advective part (steps (i)-(iii)) and the equation of state ----
@@ -259,8 +396,12 @@ int hydro_launch_rhs(const int n[3], const int bc[3], const double h[3], double 
     g.dt = dt;
     RhsArgs A{f->rho_n, f->c2_n, f->p_n, f->mom_n, f->rho_np1, f->mom_star, f->visc, f->temp_n, f->conc_n,
               f->rkc_n, f->r_gas, (int64_t)n[0] * n[1] * n[2], rhs};
-    dim3 grid((unsigned)((n[0] + 63) / 64), (unsigned)((n[1] + 3) / 4), (unsigned)n[2]);
-    hipLaunchKernelGGL(k_pressure_rhs, grid, dim3(256), 0, s, g, A);
+    const HTiles t = htiles(n);
+    const dim3 grid((unsigned)t.tx * t.ty * t.tz);
+    if (f->temp_n)
+        hipLaunchKernelGGL(k_pressure_rhs<true>, grid, dim3(256), 0, s, g, t, A);
+    else
+        hipLaunchKernelGGL(k_pressure_rhs<false>, grid, dim3(256), 0, s, g, t, A);
     return hipGetLastError() == hipSuccess ? HP_OK : HP_EHIP;
 }
 
@@ -275,8 +416,8 @@ int hydro_launch_update(const int n[3], const int bc[3], const double h[3], doub
     g.dt = dt;
     UpdArgs A{f->p, f->rho_np1, f->mom_star, f->e_star, f->mom_out, f->uface_out, f->e_out,
               (int64_t)n[0] * n[1] * n[2]};
-    dim3 grid((unsigned)((n[0] + 63) / 64), (unsigned)((n[1] + 3) / 4), (unsigned)n[2]);
-    hipLaunchKernelGGL(k_pressure_update, grid, dim3(256), 0, s, g, A);
+    const HTiles t = htiles(n);
+    hipLaunchKernelGGL(k_pressure_update, dim3((unsigned)t.tx * t.ty * t.tz), dim3(256), 0, s, g, t, A);
     return hipGetLastError() == hipSuccess ? HP_OK : HP_EHIP;
 }
 
