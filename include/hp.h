@@ -369,8 +369,9 @@ typedef struct hp_net hp_net;
 
 long long hp_nn_num_params(void);
 
-/* Network workspace for an nx x ny x nz grid (each a multiple of 4); training != 0 also
- * allocates gradients and Adam state. Parameters start at zero. */
+/* Network workspace for an nx x ny x nz grid (each a multiple of 4, fewer than 2^31 cells in
+ * all, else HP_EINVAL); training != 0 also allocates gradients and Adam state. Parameters start
+ * at zero. */
 int hp_nn_create(int nx, int ny, int nz, int training, hp_net** out);
 void hp_nn_free(hp_net* net);
 int hp_nn_set_stream(hp_net* net, void* stream);

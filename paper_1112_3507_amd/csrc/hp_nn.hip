@@ -18,10 +18,14 @@
 // w_out[16], b_out; taps t = (dz+1)*9 + (dy+1)*3 + (dx+1).
 //
 // Convolution as a GEMM on the matrix cores: D[o][v] = sum_k W[o][k] X[k][v] with k = (tap, c).
-// A 256-thread workgroup owns a 16 x 4 x 4 brick of output voxels; the input brick with its
-// one-voxel halo (18 x 6 x 6) is staged in LDS one channel chunk at a time; every wave64 owns
-// one z-slice of the brick (four 16-voxel rows), and each K step of 32 feeds one MFMA per
-// 16-channel output tile and row. The backward-data pass is the same kernel with the weights
+// A 256-thread workgroup owns a 16 x 4 x (4 SPW) brick of output voxels; the input brick with its
+// one-voxel halo is staged in LDS one channel chunk at a time (each thread loading whole halo
+// voxels at indices fixed for the launch); every wave64 owns SPW z-slices of the brick (four
+// 16-voxel rows each). With one 16-channel output tile the weights of the chunk are staged in
+// LDS and held in registers, and the products run input row by input row, each B fragment read
+// once and fed to every output row it reaches (up to 9 products per LDS read); with several
+// tiles each K step of 32 feeds one MFMA per tile and row. ReLU, the bfloat16 rounding and (in
+// inference) the network head run in the epilogue. The backward-data pass is the same kernel with the weights
 // flipped in space and transposed in channels; the backward-weight pass contracts over voxels
 // with both operands transposed through LDS.
 #include "hp.h"
@@ -59,6 +63,14 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 
 __device__ __forceinline__ bf16x8 as_bf8(uint4 u) { return __builtin_bit_cast(bf16x8, u); }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// two floats to two bfloat16 (round to nearest even) in one word, low half first: one
+// v_cvt_pk_bf16_f32 on gfx950
+__device__ __forceinline__ unsigned pack_bf2(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -79,6 +91,9 @@ struct ConvArgs {
     int cout;
     int nx, ny, nz;
     int relu;
+    // non-null (one output tile only): the network head is applied in the epilogue and out is
+    // y[voxel] (FP32) = sum_c bf16(act[voxel][c]) head[c] + head[16]; act itself is not stored
+    const float* head;
 };
 
 // SPW z-slices per wave: the output brick is 16 x 4 x (4 SPW) voxels.
@@ -86,13 +101,17 @@ template <int CT, int G, int SPW, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
     constexpr int CC = 8 * G;                  // channels per LDS chunk
     constexpr int FZ = 4 * SPW, FHZ = FZ + 2, FHV = HX * HY * FHZ;
-    constexpr int NU = (FHV * G + 255) / 256;  // 16-byte staging loads per thread and chunk
+    constexpr int NV = (FHV + 255) / 256;      // halo voxels per thread (G 16-byte loads each)
     constexpr int NSTEPS = (27 * CC + 31) / 32;
     // one output tile (16 channels): its weights of the chunk are staged in LDS too
     constexpr bool WL = (CT == 1);
     constexpr int NWL = WL ? 16 * 27 * G : 0;  // 16-byte weight groups of the chunk
     constexpr int NUW = (NWL + 255) / 256;
-    __shared__ uint4 lds[FHV * G + NWL];  // one chunk of CC channels of the halo brick [+ weights]
+    // LDS layout: the halo brick as G planes [8-channel group][halo voxel], so the 16 lanes that
+    // read one B fragment row touch 16 consecutive 16-byte words; the weight rows at an odd
+    // stride of 16-byte words for the same reason on the A fragment
+    constexpr int WS = (27 * G) | 1;
+    __shared__ uint4 lds[FHV * G + (WL ? 16 * WS : 0)];
     const int cin = p.ca + p.cb;
     const int bxn = (p.nx + BX - 1) / BX, byn = (p.ny + BY - 1) / BY;
     const int bid = blockIdx.x;
@@ -103,11 +122,36 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
     const int li = lane & 15, grp = lane >> 4;
     const int anx = p.a_up ? p.nx >> 1 : p.nx, any = p.a_up ? p.ny >> 1 : p.ny;
     const int Ktot = 27 * cin;
+
+    // The thread's halo voxels (hv = tid + 256 i): their voxel index in the full-resolution
+    // tensor b and in tensor a (half resolution when upsampled), -1 outside the grid (zero
+    // padding in z; a brick wider than the grid reaches past the periodic image in x or y,
+    // and those voxels only feed outputs outside the grid). Fixed for the whole launch.
+    int vb[NV], va[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int hv = tid + 256 * i;
+        const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+        int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        const int gz = z0 + hz - 1;
+        gx = gx < 0 ? gx + p.nx : (gx >= p.nx ? gx - p.nx : gx);
+        gy = gy < 0 ? gy + p.ny : (gy >= p.ny ? gy - p.ny : gy);
+        const bool in = hv < FHV && gz >= 0 && gz < p.nz && gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny;
+        vb[i] = in ? (gz * p.ny + gy) * p.nx + gx : -1;
+        va[i] = !in ? -1 : (p.a_up ? ((gz >> 1) * any + (gy >> 1)) * anx + (gx >> 1) : vb[i]);
+    }
+    // accumulators start from the bias: this lane's outputs are channels ct*16 + 4 grp + e
     f32x4 acc[4 * SPW][CT];  // row r of slice sl at 4 sl + r
 #pragma unroll
-    for (int r = 0; r < 4 * SPW; ++r)
+    for (int ct = 0; ct < CT; ++ct) {
+        f32x4 b0 = {0.f, 0.f, 0.f, 0.f};
+        if (p.bias) {
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[r][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int e = 0; e < 4; ++e) b0[e] = p.bias[ct * 16 + 4 * grp + e];
+        }
+#pragma unroll
+        for (int r = 0; r < 4 * SPW; ++r) acc[r][ct] = b0;
+    }
     // weight fragment of K step s: 8 consecutive k of output row ct*16 + li
     auto wload = [&](int c0, int s, uint4* w) {
         const int kk = s * 32 + grp * 8;
@@ -119,44 +163,32 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
     };
 
     for (int c0 = 0; c0 < cin; c0 += CC) {
-        // stage the chunk: all loads of a thread in flight before its LDS stores
-        uint4 v[NU];
+        // stage the chunk: all loads of a thread in flight before its LDS stores; a thread takes
+        // whole halo voxels (the chunk's CC channels are G consecutive 16-byte words in memory)
+        const bool from_a = c0 < p.ca;
+        const bf16_t* base = from_a ? p.a + c0 : p.b + (c0 - p.ca);
+        const int cstride = from_a ? p.ca : p.cb;
+        uint4 v[NV][G];
 #pragma unroll
-        for (int i = 0; i < NU; ++i) {
-            const int u = tid + 256 * i;
-            v[i] = uint4{0u, 0u, 0u, 0u};
-            if (u < FHV * G) {
-                const int hv = u / G, cg = u - hv * G;
-                const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-                int gx = x0 + hx - 1, gy = y0 + hy - 1;
-                const int gz = z0 + hz - 1;
-                gx = gx < 0 ? gx + p.nx : (gx >= p.nx ? gx - p.nx : gx);
-                gy = gy < 0 ? gy + p.ny : (gy >= p.ny ? gy - p.ny : gy);
-                const int ch = c0 + cg * 8;
-                // a brick wider than the grid reaches past the periodic image: those voxels only
-                // feed outputs outside the grid and stay zero
-                if (gz >= 0 && gz < p.nz && gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny) {
-                    if (ch < p.ca) {
-                        int ax = gx, ay = gy, az = gz;
-                        if (p.a_up) { ax >>= 1; ay >>= 1; az >>= 1; }
-                        const int64_t vox = ((int64_t)az * any + ay) * anx + ax;
-                        v[i] = *(const uint4*)(p.a + vox * p.ca + ch);
-                    } else {
-                        const int64_t vox = ((int64_t)gz * p.ny + gy) * p.nx + gx;
-                        v[i] = *(const uint4*)(p.b + vox * p.cb + (ch - p.ca));
-                    }
-                }
+        for (int i = 0; i < NV; ++i) {
+            // outside the grid: a harmless load of voxel 0, replaced by zeros
+            const int idx = from_a ? va[i] : vb[i];
+            const uint4* src = (const uint4*)(base + (int64_t)(idx < 0 ? 0 : idx) * cstride);
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const uint4 t = src[q];
+                v[i][q] = idx >= 0 ? t : uint4{0u, 0u, 0u, 0u};
             }
         }
         uint4 wcur[CT], wnext[CT];
         uint4 wv[NUW > 0 ? NUW : 1];
         if (WL) {
-            // weight row o, tap, 8-channel group of the chunk -> lds[FHV G + o 27 G + tap G + group]
+            // weight row o, tap, 8-channel group of the chunk -> lds[FHV G + o WS + tap G + group]
 #pragma unroll
             for (int i = 0; i < NUW; ++i) {
                 const int u = tid + 256 * i;
                 wv[i] = uint4{0u, 0u, 0u, 0u};
-                if (u < NWL) {
+                if ((i + 1) * 256 <= NWL || u < NWL) {
                     const int o = u / (27 * G), kq = u - o * (27 * G);
                     const int tap = kq / G, c8 = kq - tap * G;
                     wv[i] = *(const uint4*)(p.w + (int64_t)o * Ktot + tap * cin + c0 + c8 * 8);
@@ -167,74 +199,123 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
         }
         __syncthreads();  // the previous chunk's reads of lds are done
 #pragma unroll
-        for (int i = 0; i < NU; ++i) {
-            const int u = tid + 256 * i;
-            if (u < FHV * G) lds[u] = v[i];
+        for (int i = 0; i < NV; ++i) {
+            const int hv = tid + 256 * i;
+            if ((i + 1) * 256 <= FHV || hv < FHV) {
+#pragma unroll
+                for (int q = 0; q < G; ++q) lds[q * FHV + hv] = v[i][q];
+            }
         }
         if (WL) {
 #pragma unroll
             for (int i = 0; i < NUW; ++i) {
                 const int u = tid + 256 * i;
-                if (u < NWL) lds[FHV * G + u] = wv[i];
+                if ((i + 1) * 256 <= NWL || u < NWL) lds[FHV * G + (u / (27 * G)) * WS + u % (27 * G)] = wv[i];
             }
         }
         __syncthreads();
+        if constexpr (WL) {
+            // One output tile: the products are taken input row by input row, so that each B
+            // fragment read from LDS feeds every output row that needs it (up to 9). A K step holds
+            // TPS taps of one (dz, dy) pair, neighbouring in dx, times the CC channels of the
+            // chunk; its A fragments (weights) stay in registers for the whole chunk. Taps past
+            // dx = 2 have zero weights (a quarter or a third of the products when TPS > 1).
+            constexpr int TPS = 32 / CC;             // taps per K step (1, 2 or 4)
+            constexpr int NT = (3 + TPS - 1) / TPS;  // K steps per (dz, dy)
+            const int tin = (grp * 8) / CC, cg = ((grp * 8) % CC) >> 3;
+            bf16x8 aw[9][NT];
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int dx = t * TPS + tin;
+                    const uint4 w = lds[FHV * G + li * WS + (q * 3 + (dx < 3 ? dx : 2)) * G + cg];
+                    aw[q][t] = as_bf8(dx < 3 ? w : uint4{0u, 0u, 0u, 0u});
+                }
+#pragma unroll
+            for (int iz = 0; iz < SPW + 2; ++iz)
+#pragma unroll
+                for (int iy = 0; iy < HY; ++iy)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        // past dx = 2 the A side is zero; B reads the dx = 2 voxel (finite)
+                        const int dx = t * TPS + tin;
+                        const int hv = ((wave * SPW + iz) * HY + iy) * HX + li + (dx < 3 ? dx : 2);
+                        const bf16x8 bf = as_bf8(lds[cg * FHV + hv]);
+#pragma unroll
+                        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                            for (int dy = 0; dy < 3; ++dy) {
+                                const int sl = iz - dz, r = iy - dy;
+                                if (sl < 0 || sl >= SPW || r < 0 || r >= 4) continue;
+                                acc[sl * 4 + r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    aw[dz * 3 + dy][t], bf, acc[sl * 4 + r][0], 0, 0, 0);
+                            }
+                    }
+        } else {
+            // several output tiles: K step by K step, each B fragment feeding CT products
 #pragma unroll 2
-        for (int s = 0; s < NSTEPS; ++s) {
-            // next step's weights in flight while this step's products run
-            if (!WL && s + 1 < NSTEPS) wload(c0, s + 1, wnext);
-            const int kk = s * 32 + grp * 8;
-            const int tap = kk / CC, c = kk - tap * CC;
-            const bool kv = tap < 27;
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-            bf16x8 af[CT];
-            if (WL) {
-                af[0] = as_bf8(kv ? lds[FHV * G + li * (27 * G) + (kk >> 3)] : uint4{0u, 0u, 0u, 0u});
-            } else {
+            for (int s = 0; s < NSTEPS; ++s) {
+                // next step's weights in flight while this step's products run
+                if (s + 1 < NSTEPS) wload(c0, s + 1, wnext);
+                const int kk = s * 32 + grp * 8;
+                const int tap = kk / CC, c = kk - tap * CC;
+                const bool kv = tap < 27;
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                bf16x8 af[CT];
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) af[ct] = as_bf8(wcur[ct]);
-            }
 #pragma unroll
-            for (int sr = 0; sr < 4 * SPW; ++sr) {
-                const int sl = sr >> 2, r = sr & 3;
-                uint4 xv = {0u, 0u, 0u, 0u};
-                if (kv) {
-                    const int hv = ((wave * SPW + sl + dz) * HY + (r + dy)) * HX + (li + dx);
-                    xv = lds[hv * G + (c >> 3)];
+                for (int sr = 0; sr < 4 * SPW; ++sr) {
+                    const int sl = sr >> 2, r = sr & 3;
+                    uint4 xv = {0u, 0u, 0u, 0u};
+                    if (kv) {
+                        const int hv = ((wave * SPW + sl + dz) * HY + (r + dy)) * HX + (li + dx);
+                        xv = lds[(c >> 3) * FHV + hv];
+                    }
+                    const bf16x8 bf = as_bf8(xv);
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct)
+                        acc[sr][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bf, acc[sr][ct], 0, 0, 0);
                 }
-                const bf16x8 bf = as_bf8(xv);
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct)
-                    acc[sr][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ct], bf, acc[sr][ct], 0, 0, 0);
-            }
-            if (!WL) {
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) wcur[ct] = wnext[ct];
             }
         }
     }
-    // epilogue: this lane holds D[o = ct*16 + 4*grp + e][voxel li of row r of slice sl]
+    // epilogue: this lane holds D[o = ct*16 + 4*grp + e][voxel li of row r of slice sl] (bias
+    // included); a brick inside the grid needs no bounds checks
+    const bool full = x0 + BX <= p.nx && y0 + BY <= p.ny && z0 + FZ <= p.nz;
+    const float lo = p.relu ? 0.f : -INFINITY;
     const int gx = x0 + li;
 #pragma unroll
     for (int sr = 0; sr < 4 * SPW; ++sr) {
         const int gz = z0 + wave * SPW + (sr >> 2), gy = y0 + (sr & 3);
-        if (gx >= p.nx || gy >= p.ny || gz >= p.nz) continue;
+        if (!full && (gx >= p.nx || gy >= p.ny || gz >= p.nz)) continue;
         const int64_t vox = ((int64_t)gz * p.ny + gy) * p.nx + gx;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             const int o = ct * 16 + 4 * grp;
             float v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[e] = acc[sr][ct][e] + (p.bias ? p.bias[o + e] : 0.f);
-                if (p.relu) v[e] = fmaxf(v[e], 0.f);
+            for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[sr][ct][e], lo);
+            if (CT == 1 && p.head) {
+                // the activation as it would be stored (bfloat16), dotted with the head weights;
+                // the four lanes of a voxel hold channels 4 grp .. 4 grp + 3
+                const unsigned q0 = pack_bf2(v[0], v[1]), q1 = pack_bf2(v[2], v[3]);
+                float part = __uint_as_float(q0 << 16) * p.head[o] + __uint_as_float(q0 & 0xffff0000u) * p.head[o + 1] +
+                             __uint_as_float(q1 << 16) * p.head[o + 2] + __uint_as_float(q1 & 0xffff0000u) * p.head[o + 3];
+                part += __shfl_xor(part, 16, 64);
+                part += __shfl_xor(part, 32, 64);
+                if (grp == 0) ((float*)p.out)[vox] = part + p.head[HEAD];
+                continue;
             }
             if (OUT_F32) {
                 *(float4*)((float*)p.out + vox * p.cout + o) = make_float4(v[0], v[1], v[2], v[3]);
             } else {
                 uint2 pk;
-                pk.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-                pk.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+                pk.x = pack_bf2(v[0], v[1]);
+                pk.y = pack_bf2(v[2], v[3]);
                 *(uint2*)((bf16_t*)p.out + vox * p.cout + o) = pk;
             }
         }
@@ -432,22 +513,36 @@ __global__ void k_sum_partials(const double* partial, int n, double* out) {
     if (threadIdx.x == 0) *out = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// 2x2x2 mean (bf16 in/out), coarse dims (cx, cy, cz), c channels
+// 2x2x2 mean (bf16 in/out), coarse dims (cx, cy, cz), c channels (a multiple of 8): one thread
+// per coarse voxel and 8-channel group, 16-byte loads
 __global__ void k_pool(const bf16_t* __restrict__ in, bf16_t* __restrict__ out, int cx, int cy,
                        int cz, int c) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)cx * cy * cz * c;
+    const int cg = c >> 3;
+    const int64_t total = (int64_t)cx * cy * cz * cg;
     if (idx >= total) return;
-    const int ch = (int)(idx % c);
-    const int64_t v = idx / c;
+    const int g = (int)(idx % cg);
+    const int64_t v = idx / cg;
     const int x = (int)(v % cx), y = (int)((v / cx) % cy), z = (int)(v / ((int64_t)cx * cy));
     const int fx = 2 * cx, fy = 2 * cy;
-    float s = 0.f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int64_t fv = ((int64_t)(2 * z + (q >> 2)) * fy + (2 * y + ((q >> 1) & 1))) * fx + (2 * x + (q & 1));
-        s += bf2f(in[fv * c + ch]);
+        const uint4 w = *(const uint4*)(in + fv * c + 8 * g);
+        const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            s[2 * e] += __uint_as_float(u[e] << 16);
+            s[2 * e + 1] += __uint_as_float(u[e] & 0xffff0000u);
+        }
     }
-    out[idx] = f2bf(s * 0.125f);
+    uint4 r;
+    r.x = pack_bf2(s[0] * 0.125f, s[1] * 0.125f);
+    r.y = pack_bf2(s[2] * 0.125f, s[3] * 0.125f);
+    r.z = pack_bf2(s[4] * 0.125f, s[5] * 0.125f);
+    r.w = pack_bf2(s[6] * 0.125f, s[7] * 0.125f);
+    *(uint4*)(out + v * c + 8 * g) = r;
 }
 
 // gradient of pool: g_fine[v][c] += g_coarse[v/2][c] / 8   (FP32)
@@ -737,12 +832,14 @@ int check() {
 }
 
 void conv_launch(hp_net* N, int l, const bf16_t* a, int ca, int a_up, const bf16_t* b, int cb,
-                 const bf16_t* w, const float* bias, void* out, int cout, int relu, bool out_f32) {
+                 const bf16_t* w, const float* bias, void* out, int cout, int relu, bool out_f32,
+                 const float* head = nullptr) {
     const Level& L = N->lv[level_of_conv(l)];
-    ConvArgs p{a, ca, a_up, b, cb, w, bias, out, cout, L.nx, L.ny, L.nz, relu};
+    ConvArgs p{a, ca, a_up, b, cb, w, bias, out, cout, L.nx, L.ny, L.nz, relu, head};
     const int ct = cout / 16;
     const int cin = ca + cb;
-    // two z-slices per wave for the 16-channel outputs (more products per staged brick)
+    // two z-slices per wave for the 16-channel outputs (more products per staged brick; four
+    // were slower: the larger brick leaves room for fewer workgroups per CU)
     const int g = (cin % 32 == 0) ? 4 : ((cin % 16 == 0) ? 2 : 1);  // 16-byte groups per chunk voxel
     const int spw = (ct == 1 && g <= 2) ? 2 : 1;
     const unsigned blocks = (unsigned)(((L.nx + BX - 1) / BX) * ((L.ny + BY - 1) / BY) *
@@ -809,21 +906,27 @@ int forward_net(hp_net* N) {
     for (int l = 0; l < NCONV; ++l) {
         if (l == 2) {
             const Level& L = N->lv[1];
-            hipLaunchKernelGGL(k_pool, dim3(nblk(L.nv * 16)), dim3(256), 0, N->stream, N->act[1], N->p1,
+            hipLaunchKernelGGL(k_pool, dim3(nblk(L.nv * 2)), dim3(256), 0, N->stream, N->act[1], N->p1,
                                L.nx, L.ny, L.nz, 16);
         }
         if (l == 4) {
             const Level& L = N->lv[2];
-            hipLaunchKernelGGL(k_pool, dim3(nblk(L.nv * 32)), dim3(256), 0, N->stream, N->act[3], N->p2,
+            hipLaunchKernelGGL(k_pool, dim3(nblk(L.nv * 4)), dim3(256), 0, N->stream, N->act[3], N->p2,
                                L.nx, L.ny, L.nz, 32);
         }
         ConvIn in = conv_inputs(N, l);
+        // without training the last layer's activation is only needed by the head, which then
+        // runs in that convolution's epilogue
+        const bool fuse_head = l == NCONV - 1 && !N->training;
         conv_launch(N, l, in.a, in.ca, in.a_up, in.b, in.cb, N->wf[l], N->theta + N->boff[l],
-                    N->act[l], COUT[l], 1, false);
+                    fuse_head ? (void*)N->y : (void*)N->act[l], COUT[l], 1, false,
+                    fuse_head ? N->theta + N->hoff : nullptr);
     }
-    const Level& L = N->lv[0];
-    hipLaunchKernelGGL(k_head, dim3(nblk(L.nv)), dim3(256), 0, N->stream, N->act[9],
-                       N->theta + N->hoff, N->y, L.nv);
+    if (N->training) {
+        const Level& L = N->lv[0];
+        hipLaunchKernelGGL(k_head, dim3(nblk(L.nv)), dim3(256), 0, N->stream, N->act[9],
+                           N->theta + N->hoff, N->y, L.nv);
+    }
     return check();
 }
 
@@ -900,6 +1003,9 @@ int hp_nn_create(int nx, int ny, int nz, int training, hp_net** out) {
     *out = nullptr;
     if (nx < 4 || ny < 4 || nz < 4 || nx % 4 || ny % 4 || nz % 4)
         return nfail(HP_EINVAL, "network grid sizes must be multiples of 4 (got %d x %d x %d)", nx, ny, nz);
+    // the convolutions index voxels with 32-bit integers
+    if ((int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return nfail(HP_EINVAL, "network grid of %d x %d x %d cells exceeds 2^31 - 1 cells", nx, ny, nz);
     hp_net* N = new hp_net();
     N->training = training ? 1 : 0;
     for (int q = 0; q < 3; ++q) {
