@@ -57,7 +57,8 @@ enum {
     HP_EHIP = -4,        /* HIP runtime error (message kept) */
     HP_ENAN = -5,        /* non-finite right-hand side or iterate */
     HP_ENOCONV = -6,     /* iteration cap reached; p holds the last iterate, stats are filled */
-    HP_EBREAKDOWN = -7   /* p^T A p <= 0 in CG (cannot happen for valid SPD input) */
+    HP_EBREAKDOWN = -7,  /* p^T A p <= 0 in CG (cannot happen for valid SPD input) */
+    HP_EIO = -8          /* a checkpoint file cannot be opened, read or written, or is not one */
 };
 
 /* Solver modes (HP_OPT_MODE). */
@@ -382,6 +383,15 @@ int hp_nn_set_params(hp_net* net, const float* params);
 int hp_nn_get_params(hp_net* net, float* params);
 int hp_nn_get_grad(hp_net* net, float* grad);
 int hp_nn_set_output_scale(hp_net* net, double out_scale);
+
+/* Checkpoints: the parameters and the output scale in one binary file (little-endian: the 8
+ * bytes "HPNET01\0", int64 parameter count, float64 output scale, the parameters as float32).
+ * hp_nn_save writes the network's current ones (synchronises its stream); hp_nn_load replaces
+ * them (any grid: the parameters do not depend on it) and leaves the network unchanged when it
+ * rejects the file. HP_EIO for a file that cannot be opened, read or written, a wrong magic or a parameter
+ * count other than hp_nn_num_params(); HP_EINVAL for null arguments. */
+int hp_nn_save(hp_net* net, const char* path);
+int hp_nn_load(hp_net* net, const char* path);
 
 /* x = s * out_scale * net(b/s, log rho, log c2, p_prev/s); p_prev may be NULL (zeros).
  * All device FP64 cell arrays. */

@@ -23,9 +23,9 @@ OPT_INNER_TOL, OPT_MAX_OUTER, OPT_COARSEST_MAX = 5, 6, 7
 OPT_LAYOUT = 8  # finest-level storage inside the handle: 1 red-black split, 0 natural
 OPT_KERNEL_TIMING = 9  # 1: time finest-level sweeps and applies inside FP64 solves
 
-OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENAN, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENAN, ENOCONV, EBREAKDOWN, EIO = 0, -1, -2, -3, -4, -5, -6, -7, -8
 _CODE_NAMES = {EINVAL: "HP_EINVAL", EDOMAIN: "HP_EDOMAIN", ENOMEM: "HP_ENOMEM", EHIP: "HP_EHIP",
-               ENAN: "HP_ENAN", ENOCONV: "HP_ENOCONV", EBREAKDOWN: "HP_EBREAKDOWN"}
+               ENAN: "HP_ENAN", ENOCONV: "HP_ENOCONV", EBREAKDOWN: "HP_EBREAKDOWN", EIO: "HP_EIO"}
 
 # every symbol include/hp.h declares
 EXPORTS = [
@@ -36,6 +36,7 @@ EXPORTS = [
     "hp_coarse_solve_f32", "hp_precond", "hp_precond_f32", "hp_residual", "hp_dot",
     "hp_nn_num_params", "hp_nn_create", "hp_nn_free", "hp_nn_set_stream", "hp_nn_last_error",
     "hp_nn_set_params", "hp_nn_get_params", "hp_nn_get_grad", "hp_nn_set_output_scale",
+    "hp_nn_save", "hp_nn_load",
     "hp_nn_forward", "hp_nn_train_step", "hp_nn_forward_raw", "hp_nn_loss_grad_raw", "hp_nn_adam",
     "hp_attach_net", "hp_warm_start", "hp_nn_train_step_anorm",
     "hp_dot_noalloc", "hp_noalloc_last_error",
@@ -134,6 +135,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                 "hp_nn_get_params": (ip, [vp, vp]),
                 "hp_nn_get_grad": (ip, [vp, vp]),
                 "hp_nn_set_output_scale": (ip, [vp, ctypes.c_double]),
+                "hp_nn_save": (ip, [vp, ctypes.c_char_p]),
+                "hp_nn_load": (ip, [vp, ctypes.c_char_p]),
                 "hp_nn_forward": (ip, [vp, dp, dp, dp, dp, dp]),
                 "hp_nn_train_step": (ip, [vp, dp, dp, dp, dp, dp, ctypes.c_float,
                                           ctypes.POINTER(ctypes.c_double)]),
@@ -484,6 +487,14 @@ class Net:
 
     def set_output_scale(self, s: float):
         _check_nn(self._lib.hp_nn_set_output_scale(self._h, float(s)))
+
+    def save(self, path: str):
+        """Write the parameters and the output scale to a checkpoint file (hp_nn_save)."""
+        _check_nn(self._lib.hp_nn_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Replace the parameters and the output scale from a checkpoint file (hp_nn_load)."""
+        _check_nn(self._lib.hp_nn_load(self._h, os.fsencode(path)))
 
     def forward(self, b, rho, c2, p_prev, x):
         n = self.ncells

@@ -34,6 +34,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -1089,6 +1090,55 @@ int hp_nn_get_grad(hp_net* N, float* grad) {
     if (hipMemcpyAsync(grad, N->grad, N->nparam * sizeof(float), hipMemcpyDeviceToDevice, N->stream) != hipSuccess)
         return nfail(HP_EHIP, "gradient copy failed");
     return HP_OK;
+}
+
+static const char kCkptMagic[8] = {'H', 'P', 'N', 'E', 'T', '0', '1', '\0'};
+
+int hp_nn_save(hp_net* N, const char* path) {
+    g_nn_err.clear();
+    if (!N || !path) return nfail(HP_EINVAL, "null argument");
+    std::vector<float> host((size_t)N->nparam);
+    if (hipMemcpyAsync(host.data(), N->theta, N->nparam * sizeof(float), hipMemcpyDeviceToHost, N->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(N->stream) != hipSuccess)
+        return nfail(HP_EHIP, "parameter copy failed");
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return nfail(HP_EIO, "cannot open %s for writing", path);
+    const int64_t count = N->nparam;
+    const double scale = N->out_scale;
+    bool ok = std::fwrite(kCkptMagic, 1, 8, f) == 8 && std::fwrite(&count, sizeof count, 1, f) == 1 &&
+              std::fwrite(&scale, sizeof scale, 1, f) == 1 &&
+              std::fwrite(host.data(), sizeof(float), host.size(), f) == host.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? HP_OK : nfail(HP_EIO, "cannot write %s", path);
+}
+
+int hp_nn_load(hp_net* N, const char* path) {
+    g_nn_err.clear();
+    if (!N || !path) return nfail(HP_EINVAL, "null argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return nfail(HP_EIO, "cannot open %s", path);
+    char magic[8];
+    int64_t count = -1;
+    double scale = 0.0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kCkptMagic, 8) == 0 &&
+              std::fread(&count, sizeof count, 1, f) == 1 && std::fread(&scale, sizeof scale, 1, f) == 1;
+    if (!ok || count != N->nparam) {
+        std::fclose(f);
+        return nfail(HP_EIO, "%s is not a checkpoint of this network (%lld parameters expected)", path,
+                     (long long)N->nparam);
+    }
+    std::vector<float> host((size_t)count);
+    ok = std::fread(host.data(), sizeof(float), host.size(), f) == host.size();
+    std::fclose(f);
+    if (!ok) return nfail(HP_EIO, "%s is truncated", path);
+    if (!(scale > 0.0) || !std::isfinite(scale)) return nfail(HP_EIO, "%s holds an invalid output scale", path);
+    if (hipMemcpyAsync(N->theta, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, N->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(N->stream) != hipSuccess)
+        return nfail(HP_EHIP, "parameter copy failed");
+    N->out_scale = scale;
+    return pack_weights(N);
 }
 
 int hp_nn_set_output_scale(hp_net* N, double s) {

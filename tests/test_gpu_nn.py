@@ -390,3 +390,52 @@ def test_train_then_attach_then_learned_solve():
     assert st["converged"] and st["rel_residual"] <= 1e-10
     assert np.linalg.norm(x.cpu().numpy() - xref) / np.linalg.norm(xref) <= 1e-9
     net.close()
+
+
+def test_checkpoint_save_load_roundtrip(tmp_path):
+    """hp_nn_save / hp_nn_load: the file holds the documented layout (read back here with numpy),
+    a load on a network of another grid restores the parameters and output scale exactly (the
+    forwards of saver and loader agree bit for bit), and a wrong magic, a wrong count or a
+    truncated file give HP_EIO and leave the network as it was."""
+    theta, inp, _ = _inputs(11)
+    a = hp.Net(N3, training=False)
+    a.set_params(torch.from_numpy(theta).to(DEV))
+    a.set_output_scale(2.5e-4)
+    path = str(tmp_path / "net.ckpt")
+    a.save(path)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"HPNET01\x00"
+    count = int(np.frombuffer(raw[8:16], dtype="<i8")[0])
+    scale = float(np.frombuffer(raw[16:24], dtype="<f8")[0])
+    params = np.frombuffer(raw[24:], dtype="<f4")
+    assert count == nn.num_params() == params.size and scale == 2.5e-4
+    assert np.array_equal(params, theta)
+
+    b = hp.Net((32, 32, 32), training=False)
+    b.load(path)
+    assert np.array_equal(b.get_params().cpu().numpy(), theta)
+    c = hp.Net(N3, training=False)
+    c.load(path)
+    ya = torch.empty(SHAPE, dtype=torch.float32, device=DEV)
+    yc = torch.empty_like(ya)
+    a.forward_raw(_dev_inp(inp), ya)
+    c.forward_raw(_dev_inp(inp), yc)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yc)
+
+    before = b.get_params().cpu().numpy().copy()
+    bad = {"magic": b"HPNET02\x00" + raw[8:],
+           "count": raw[:8] + np.array([count - 1], dtype="<i8").tobytes() + raw[16:],
+           "truncated": raw[:-4]}
+    for name, blob in bad.items():
+        q = tmp_path / ("bad_" + name)
+        q.write_bytes(blob)
+        with pytest.raises(hp.HPError) as ei:
+            b.load(str(q))
+        assert ei.value.code == hp.EIO, name
+    with pytest.raises(hp.HPError) as ei:
+        b.load(str(tmp_path / "missing"))
+    assert ei.value.code == hp.EIO
+    assert np.array_equal(b.get_params().cpu().numpy(), before)
+    for n_ in (a, b, c):
+        n_.close()
