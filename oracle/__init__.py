@@ -13,6 +13,10 @@ With two densities (eqs. cpoiss and kappapoiss: rho^n in the mass term, rho^{n+1
 functions take ``rho`` as rho^n and ``rho_face`` as rho^{n+1}: m_a = 1 / (rho^n_a c2_a) and
 w_f = dt^2 (2 / (rho^{n+1}_a + rho^{n+1}_b)) / h_d^2. ``rho_face=None`` means rho^{n+1} = rho^n.
 
+``face_rule=1`` replaces the face factor 2 / (rho_a + rho_b) by the mean of kappa = 1/rho of the
+two cells, (1/rho_a + 1/rho_b) / 2 (the other reading of eq. kappapoiss); the default 0 is the
+factor of the face-velocity update.
+
 Arrays are cell-centred, shaped (nz, ny, nx) in C order (x fastest). ``bc`` holds one entry per
 axis (x, y, z): 0 = periodic, 1 = homogeneous Neumann.
 
@@ -75,14 +79,16 @@ def _load():
             i64_p = P(ctypes.c_int64)
             lib.or_ncells.restype = ctypes.c_int64
             lib.or_ncells.argtypes = [P(_Grid)]
-            lib.or_assemble2.restype = ctypes.c_int64
-            lib.or_assemble2.argtypes = [P(_Grid), d_p, d_p, d_p, ctypes.c_double, i64_p, i64_p, d_p]
+            lib.or_assemble3.restype = ctypes.c_int64
+            lib.or_assemble3.argtypes = [P(_Grid), d_p, d_p, d_p, ctypes.c_double, ctypes.c_int,
+                                         i64_p, i64_p, d_p]
             lib.or_spmv.restype = None
             lib.or_spmv.argtypes = [ctypes.c_int64, i64_p, i64_p, d_p, d_p, d_p]
             lib.or_dot.restype = ctypes.c_double
             lib.or_dot.argtypes = [ctypes.c_int64, d_p, d_p]
-            lib.or_residual_mf2.restype = None
-            lib.or_residual_mf2.argtypes = [P(_Grid), d_p, d_p, d_p, ctypes.c_double, d_p, d_p, d_p]
+            lib.or_residual_mf3.restype = None
+            lib.or_residual_mf3.argtypes = [P(_Grid), d_p, d_p, d_p, ctypes.c_double, ctypes.c_int,
+                                            d_p, d_p, d_p]
             lib.or_neumann_rhs.restype = None
             lib.or_neumann_rhs.argtypes = [P(_Grid), ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                            d_p, d_p]
@@ -148,7 +154,13 @@ class CSR:
         return self.to_scipy().toarray()
 
 
-def assemble(n, h, bc, rho, c2, dt, rho_face=None) -> CSR:
+def _rule(face_rule) -> int:
+    if face_rule not in (0, 1):
+        raise ValueError("face_rule must be 0 or 1")
+    return int(face_rule)
+
+
+def assemble(n, h, bc, rho, c2, dt, rho_face=None, face_rule=0) -> CSR:
     """Assemble A (see module docstring) by looping over faces; duplicate faces are summed."""
     lib = _load()
     g = _grid(n, h, bc)
@@ -159,12 +171,12 @@ def assemble(n, h, bc, rho, c2, dt, rho_face=None) -> CSR:
     rowptr = np.zeros(N + 1, dtype=np.int64)
     colind = np.zeros(7 * N, dtype=np.int64)
     val = np.zeros(7 * N, dtype=np.float64)
-    nnz = lib.or_assemble2(ctypes.byref(g), _dptr(rho), _dptr(rf), _dptr(c2), float(dt),
-                           _iptr(rowptr), _iptr(colind), _dptr(val))
+    nnz = lib.or_assemble3(ctypes.byref(g), _dptr(rho), _dptr(rf), _dptr(c2), float(dt),
+                           _rule(face_rule), _iptr(rowptr), _iptr(colind), _dptr(val))
     return CSR(rowptr, colind[:nnz].copy(), val[:nnz].copy())
 
 
-def residual(n, h, bc, rho, c2, dt, x, b, rho_face=None) -> np.ndarray:
+def residual(n, h, bc, rho, c2, dt, x, b, rho_face=None, face_rule=0) -> np.ndarray:
     """Matrix-free r = b - A x (same face definition, no CSR; any size that fits in memory)."""
     lib = _load()
     g = _grid(n, h, bc)
@@ -172,8 +184,8 @@ def residual(n, h, bc, rho, c2, dt, x, b, rho_face=None) -> np.ndarray:
     rho, c2, x, b = _f64(rho, N), _f64(c2, N), _f64(x, N), _f64(b, N)
     rf = rho if rho_face is None else _f64(rho_face, N)
     r = np.empty(N, dtype=np.float64)
-    lib.or_residual_mf2(ctypes.byref(g), _dptr(rho), _dptr(rf), _dptr(c2), float(dt), _dptr(x),
-                        _dptr(b), _dptr(r))
+    lib.or_residual_mf3(ctypes.byref(g), _dptr(rho), _dptr(rf), _dptr(c2), float(dt),
+                        _rule(face_rule), _dptr(x), _dptr(b), _dptr(r))
     return r
 
 
@@ -234,18 +246,18 @@ def pcg_fixed(A: CSR, b, iters: int) -> float:
 
 
 def solve(n, h, bc, rho, c2, dt, b, x0=None, tol=1e-10, maxiter=1_000_000, stag_window=0,
-          coef_cap=0, rho_face=None):
+          coef_cap=0, rho_face=None, face_rule=0):
     """Assemble and solve A x = b with Jacobi-PCG. Returns (x shaped like b, stats)."""
     shape = np.shape(b)
-    A = assemble(n, h, bc, rho, c2, dt, rho_face)
+    A = assemble(n, h, bc, rho, c2, dt, rho_face, face_rule)
     x, st = pcg(A, b, x0, tol, maxiter, stag_window, coef_cap)
     return x.reshape(shape), st
 
 
-def reference_solve(n, h, bc, rho, c2, dt, b, maxiter=1_000_000, rho_face=None):
+def reference_solve(n, h, bc, rho, c2, dt, b, maxiter=1_000_000, rho_face=None, face_rule=0):
     """Reference solution for parity: tol 1e-13 or stagnation of the true residual."""
     return solve(n, h, bc, rho, c2, dt, b, tol=1e-13, maxiter=maxiter, stag_window=50,
-                 rho_face=rho_face)
+                 rho_face=rho_face, face_rule=face_rule)
 
 
 def lanczos_extremes(alpha: np.ndarray, beta: np.ndarray):

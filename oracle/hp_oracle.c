@@ -22,8 +22,12 @@
  * Section 5 grid description): cell a = (i, j, k), centre ((i+1/2) hx, (j+1/2) hy, (k+1/2) hz).
  * For every pair of cells (a, b) adjacent along axis d there is a face f with
  *
- *     kappa_f = 2 / (rho_a + rho_b)        (the face factor of the face-velocity update,
- *                                           step (viii) of the fractional-step algorithm)
+ *     kappa_f = 2 / (rho_a + rho_b)        (face rule 0, the default: the face factor of the
+ *                                           face-velocity update, step (viii) of the
+ *                                           fractional-step algorithm)
+ *     kappa_f = (1/rho_a + 1/rho_b) / 2    (face rule 1: the mean of kappa = 1/rho of the two
+ *                                           cells, the other reading of eq. kappapoiss; the "3"
+ *                                           entry points take the rule)
  *     w_f     = dt^2 kappa_f / h_d^2
  *
  * Interior faces join cells whose index along d differs by one. On a periodic axis with n >= 2
@@ -85,6 +89,11 @@ static int64_t or_neighbor(const or_grid* g, int i, int j, int k, int d, int s) 
 
 int or_version(void) { return 1; }
 
+/* kappa at the face between cells of (face) densities ra and rb under face rule `rule` */
+static double or_face_kappa(double ra, double rb, int rule) {
+    return rule == 1 ? 0.5 * (1.0 / ra + 1.0 / rb) : 2.0 / (ra + rb);
+}
+
 /* Number of rows = cells. */
 int64_t or_ncells(const or_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
 
@@ -93,8 +102,9 @@ int64_t or_ncells(const or_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2
  * rowptr has ncells+1 entries; colind/val must hold 7*ncells entries.
  * Returns the number of nonzeros.
  */
-int64_t or_assemble2(const or_grid* g, const double* rho_mass, const double* rho_face,
-                     const double* c2, double dt, int64_t* rowptr, int64_t* colind, double* val) {
+int64_t or_assemble3(const or_grid* g, const double* rho_mass, const double* rho_face,
+                     const double* c2, double dt, int rule, int64_t* rowptr, int64_t* colind,
+                     double* val) {
     int64_t N = or_ncells(g);
     /* first pass: count distinct columns per row */
     int64_t* cnt = (int64_t*)calloc((size_t)N, sizeof(int64_t));
@@ -137,7 +147,7 @@ int64_t or_assemble2(const or_grid* g, const double* rho_mass, const double* rho
             for (int s = -1; s <= 1; s += 2) {
                 int64_t b = or_neighbor(g, i, j, k, d, s);
                 if (b < 0) continue;
-                double kappa = 2.0 / (rho_face[a] + rho_face[b]);
+                double kappa = or_face_kappa(rho_face[a], rho_face[b], rule);
                 double w = dt2 * kappa / (g->h[d] * g->h[d]);
                 vals[0] += w; /* diagonal */
                 int q;
@@ -172,9 +182,14 @@ int64_t or_assemble2(const or_grid* g, const double* rho_mass, const double* rho
     return rowptr[N];
 }
 
+int64_t or_assemble2(const or_grid* g, const double* rho_mass, const double* rho_face,
+                     const double* c2, double dt, int64_t* rowptr, int64_t* colind, double* val) {
+    return or_assemble3(g, rho_mass, rho_face, c2, dt, 0, rowptr, colind, val);
+}
+
 int64_t or_assemble(const or_grid* g, const double* rho, const double* c2, double dt,
                     int64_t* rowptr, int64_t* colind, double* val) {
-    return or_assemble2(g, rho, rho, c2, dt, rowptr, colind, val);
+    return or_assemble3(g, rho, rho, c2, dt, 0, rowptr, colind, val);
 }
 
 /* y = A x (CSR) */
@@ -209,8 +224,9 @@ double or_dot(int64_t N, const double* x, const double* y) {
  * Matrix-free residual r = b - A x straight from the face definition (no CSR), for sizes where
  * the CSR matrix does not fit. Used to certify a solution returned by another solver.
  */
-void or_residual_mf2(const or_grid* g, const double* rho_mass, const double* rho_face,
-                     const double* c2, double dt, const double* x, const double* b, double* r) {
+void or_residual_mf3(const or_grid* g, const double* rho_mass, const double* rho_face,
+                     const double* c2, double dt, int rule, const double* x, const double* b,
+                     double* r) {
     int64_t N = or_ncells(g);
     double dt2 = dt * dt;
 #pragma omp parallel for schedule(static)
@@ -223,16 +239,21 @@ void or_residual_mf2(const or_grid* g, const double* rho_mass, const double* rho
             for (int s = -1; s <= 1; s += 2) {
                 int64_t nb = or_neighbor(g, i, j, k, d, s);
                 if (nb < 0) continue;
-                double w = dt2 * (2.0 / (rho_face[a] + rho_face[nb])) / (g->h[d] * g->h[d]);
+                double w = dt2 * or_face_kappa(rho_face[a], rho_face[nb], rule) / (g->h[d] * g->h[d]);
                 ax += w * (x[a] - x[nb]);
             }
         r[a] = b[a] - ax;
     }
 }
 
+void or_residual_mf2(const or_grid* g, const double* rho_mass, const double* rho_face,
+                     const double* c2, double dt, const double* x, const double* b, double* r) {
+    or_residual_mf3(g, rho_mass, rho_face, c2, dt, 0, x, b, r);
+}
+
 void or_residual_mf(const or_grid* g, const double* rho, const double* c2, double dt,
                     const double* x, const double* b, double* r) {
-    or_residual_mf2(g, rho, rho, c2, dt, x, b, r);
+    or_residual_mf3(g, rho, rho, c2, dt, 0, x, b, r);
 }
 
 /*

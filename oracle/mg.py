@@ -45,6 +45,7 @@ class Level:
     dt: float
     coarsened: tuple = (False, False, False)   # relative to the previous (finer) level
     extra: dict = field(default_factory=dict)
+    face_rule: int = 0  # 0: kappa_f = 2 / (rho_a + rho_b); 1: kappa_f = (1/rho_a + 1/rho_b) / 2
 
     @property
     def shape(self):
@@ -59,15 +60,18 @@ def can_coarsen(n: int, bc: int) -> bool:
     return True
 
 
-def build_hierarchy(n, h, bc, rho, c2, dt, coarsest_max: int = 512, rho_face=None):
+def build_hierarchy(n, h, bc, rho, c2, dt, coarsest_max: int = 512, rho_face=None, face_rule=0):
     """Levels from the fine coefficients. Level.rho is the density of the face coefficients and
     Level.m the mass term; with two densities (eqs. cpoiss and kappapoiss) rho is rho^n
-    (m = 1 / (rho^n c2)) and rho_face is rho^{n+1} (None: the same as rho)."""
+    (m = 1 / (rho^n c2)) and rho_face is rho^{n+1} (None: the same as rho). Every level takes
+    the face rule `face_rule` (see Level)."""
+    if face_rule not in (0, 1):
+        raise ValueError("face_rule must be 0 or 1")
     rho = np.asarray(rho, dtype=np.float64).reshape(n[2], n[1], n[0])
     c2 = np.asarray(c2, dtype=np.float64).reshape(n[2], n[1], n[0])
     rf = rho if rho_face is None else np.asarray(rho_face, dtype=np.float64).reshape(n[2], n[1], n[0])
     levels = [Level(tuple(n), tuple(float(v) for v in h), tuple(bc), rf, 1.0 / (rho * c2),
-                    float(dt))]
+                    float(dt), face_rule=int(face_rule))]
     while True:
         L = levels[-1]
         ncell = L.n[0] * L.n[1] * L.n[2]
@@ -77,7 +81,7 @@ def build_hierarchy(n, h, bc, rho, c2, dt, coarsest_max: int = 512, rho_face=Non
         nn = tuple(L.n[d] // 2 if flags[d] else L.n[d] for d in range(3))
         hh = tuple(L.h[d] * 2 if flags[d] else L.h[d] for d in range(3))
         levels.append(Level(nn, hh, L.bc, child_mean(L.rho, flags), child_mean(L.m, flags),
-                            L.dt, flags))
+                            L.dt, flags, face_rule=L.face_rule))
     return levels
 
 
@@ -112,7 +116,8 @@ def _neighbors(L: Level):
                 shape[ax] = nd
                 mask = np.broadcast_to(valid.reshape(shape), idx.shape)
             rho_b = rho.reshape(-1)[nb]
-            w = L.dt ** 2 * (2.0 / (rho + rho_b)) / (L.h[d] ** 2)
+            kappa = 0.5 * (1.0 / rho + 1.0 / rho_b) if L.face_rule == 1 else 2.0 / (rho + rho_b)
+            w = L.dt ** 2 * kappa / (L.h[d] ** 2)
             out.append((mask, nb, np.where(mask, w, 0.0)))
     return out
 
