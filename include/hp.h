@@ -85,7 +85,14 @@ enum {
                                  and every axis coarsened at least once), 0 = natural order.
                                  Vectors passed through this API are always in natural order;
                                  setting 1 where the grid does not allow it is HP_EINVAL */,
-    HP_OPT_KERNEL_TIMING = 9  /* 1: time finest-level kernels inside FP64 solves (hp_stats); 0 */
+    HP_OPT_KERNEL_TIMING = 9, /* 1: time finest-level kernels inside FP64 solves (hp_stats); 0 */
+    HP_OPT_FACE_RULE = 10     /* value of kappa = 1/rho on a face between cells a and b (Section 2,
+                                 eq. kappapoiss; the paper leaves it to the discretisation):
+                                 0 (default) 2 / (rho_a + rho_b), the factor of the face-velocity
+                                 update of step (viii); 1 (1/rho_a + 1/rho_b) / 2, the mean of the
+                                 two cells' kappa. Applies to every level, the smoother and the
+                                 coarsest solve; may be changed between solves (recomputes the
+                                 rule-dependent setup, no allocation) */
 };
 
 /* Statistics of the last hp_solve. */

@@ -22,6 +22,7 @@ OPT_MODE, OPT_MAX_ITER, OPT_NU_PRE, OPT_NU_POST = 1, 2, 3, 4
 OPT_INNER_TOL, OPT_MAX_OUTER, OPT_COARSEST_MAX = 5, 6, 7
 OPT_LAYOUT = 8  # finest-level storage inside the handle: 1 red-black split, 0 natural
 OPT_KERNEL_TIMING = 9  # 1: time finest-level sweeps and applies inside FP64 solves
+OPT_FACE_RULE = 10  # face value of kappa: 0 = 2/(rho_a + rho_b) (default), 1 = (1/rho_a + 1/rho_b)/2
 
 OK, EINVAL, EDOMAIN, ENOMEM, EHIP, ENAN, ENOCONV, EBREAKDOWN, EIO = 0, -1, -2, -3, -4, -5, -6, -7, -8
 _CODE_NAMES = {EINVAL: "HP_EINVAL", EDOMAIN: "HP_EDOMAIN", ENOMEM: "HP_ENOMEM", EHIP: "HP_EHIP",

@@ -50,6 +50,8 @@ struct Geo {
     T cx, cy, cz;          // dt^2 / h_d^2
     int split;             // 1: arrays of this level use the red-black split layout
     int rev = 0;           // 1: z-march tiles in reverse order (see ztile)
+    int frule = 0;         // face rule (HP_OPT_FACE_RULE): 0 kappa_f = 2/(rho_a + rho_b),
+                           // 1 kappa_f = (1/rho_a + 1/rho_b)/2
 };
 
 // Red-black split layout (finest level, nx even): each x row of nx cells holds its nx/2 red

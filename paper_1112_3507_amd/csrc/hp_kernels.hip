@@ -48,10 +48,26 @@ __device__ __forceinline__ double fast_rcp(double x) {
 }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <typename T>
+// kappa = 1/rho at the face between cells of face densities ra and rb. FR = 0 (the default): the
+// factor 2 / (ra + rb) of the face-velocity update (step (viii)); FR = 1: the mean of the two
+// cells' kappa, (1/ra + 1/rb) / 2.
+template <int FR, typename T>
 __device__ __forceinline__ T face_kappa(T ra, T rb) {
+    if constexpr (FR == 1) return T(0.5) * (fast_rcp(ra) + fast_rcp(rb));
     return T(2) * fast_rcp(ra + rb);
 }
+
+// the face rule of a launch as the compile-time constant FRV of the statement it runs
+#define WITH_FACE_RULE(rule, ...)      \
+    do {                               \
+        if (rule) {                    \
+            constexpr int FRV = 1;     \
+            __VA_ARGS__;               \
+        } else {                       \
+            constexpr int FRV = 0;     \
+            __VA_ARGS__;               \
+        }                              \
+    } while (0)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -291,12 +307,16 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, Geo<float
     int a = i + g.nx * (j + g.ny * k);
     double ra = rho[a];
     double d = m[a];
-    for_faces(g, i, j, k, a, [&](int nb, double c) { d += c * face_kappa(ra, rho[nb]); });
+    for_faces(g, i, j, k, a, [&](int nb, double c) {
+        d += c * (g.frule ? face_kappa<1>(ra, rho[nb]) : face_kappa<0>(ra, rho[nb]));
+    });
     dinv[a] = 1.0 / d;
     if (dinv32) {
         float ra32 = rho32[a];
         float d32 = m32[a];
-        for_faces(g32, i, j, k, a, [&](int nb, float c) { d32 += c * face_kappa(ra32, rho32[nb]); });
+        for_faces(g32, i, j, k, a, [&](int nb, float c) {
+            d32 += c * (g32.frule ? face_kappa<1>(ra32, rho32[nb]) : face_kappa<0>(ra32, rho32[nb]));
+        });
         dinv32[a] = 1.0f / d32;
     }
 }
@@ -311,7 +331,7 @@ void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const doubl
 // ------------------------------------------------------------------------------------------
 // operator apply / residual
 
-template <typename T, int MODE>
+template <typename T, int MODE, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_apply(Geo<T> g, const T* __restrict__ rho,
                                                   const T* __restrict__ m,
                                                   const T* __restrict__ x,
@@ -326,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo<T> g, const T* __restrict_
         T ra = rho[a], xa = x[a];
         T acc = m[a] * xa;
         for_faces(g, i, j, k, a,
-                  [&](int nb, T c) { acc += c * face_kappa(ra, rho[nb]) * (xa - x[nb]); });
+                  [&](int nb, T c) { acc += c * face_kappa<FR>(ra, rho[nb]) * (xa - x[nb]); });
         if (MODE >= 2) acc = b[a] - acc;
         y[a] = acc;
         if (MODE == 1) part = (double)xa * (double)acc;
@@ -428,7 +448,7 @@ __device__ __forceinline__ int zoff(int k, int s, int nz, int pz, int sz, bool& 
 
 // Software-pipelined z march: all loads of plane k+1 are issued before plane k is computed
 // (unconditionally, with clamped addresses), so each wave keeps two planes of loads in flight.
-template <typename T, int MODE>
+template <typename T, int MODE, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
                                                      const T* __restrict__ m,
@@ -453,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
         int op = zoff(k0, 1, g.nz, g.pz, sz, hp);
         T xc = x[a], rc = rho[a];
         T xm = x[a + om];
-        T wzm = hm ? g.cz * face_kappa(rc, rho[a + om]) : T(0);
+        T wzm = hm ? g.cz * face_kappa<FR>(rc, rho[a + om]) : T(0);
         T xn = x[a + op], rn = rho[a + op];
         T czp = hp ? g.cz : T(0);
         T xv[4], rv[4], mv, bv = T(0);
@@ -482,9 +502,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
             // plane k
             T acc = mv * xc;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc += ft.c[q] * face_kappa(rc, rv[q]) * (xc - xv[q]);
+            for (int q = 0; q < 4; ++q) acc += ft.c[q] * face_kappa<FR>(rc, rv[q]) * (xc - xv[q]);
             acc += wzm * (xc - xm);
-            const T wzp = czp * face_kappa(rc, rn);
+            const T wzp = czp * face_kappa<FR>(rc, rn);
             acc += wzp * (xc - xn);
             if (MODE >= 2) acc = bv - acc;
             y[a] = acc;
@@ -535,7 +555,7 @@ __device__ __forceinline__ void stp(T* __restrict__ p, T v0, T v1) {
 // Operator apply over cell pairs: the same z march and face order as k_apply_zm, with half the
 // memory instructions (pair loads for the cell, its y and z neighbours, m and b; two scalar
 // loads for the outer x neighbours) and the pair's shared x face weighted once.
-template <typename T, int MODE>
+template <typename T, int MODE, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
                                                      const T* __restrict__ m,
@@ -564,8 +584,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
         Pair<T> xc = ldp(x + a), rc = ldp(rho + a);
         const Pair<T> xm0 = ldp(x + a + om), rm0 = ldp(rho + a + om);
         Pair<T> xm = xm0;
-        T wzm0 = hm ? g.cz * face_kappa(rc.v0, rm0.v0) : T(0);
-        T wzm1 = hm ? g.cz * face_kappa(rc.v1, rm0.v1) : T(0);
+        T wzm0 = hm ? g.cz * face_kappa<FR>(rc.v0, rm0.v0) : T(0);
+        T wzm1 = hm ? g.cz * face_kappa<FR>(rc.v1, rm0.v1) : T(0);
         Pair<T> xn = ldp(x + a + op), rn = ldp(rho + a + op);
         T czp = hp ? g.cz : T(0);
         T xl = x[a + oxl], xr = x[a + oxr], rl = rho[a + oxl], rr = rho[a + oxr];
@@ -588,21 +608,21 @@ __global__ __launch_bounds__(kBlock) void k_apply_zp(Geo<T> g, ZTiles zt,
             if (MODE >= 2) bvn = ldp(b + an);
             const Pair<T> xnn = ldp(x + an + opn), rnn = ldp(rho + an + opn);
             // plane k
-            const T wx = g.cx * face_kappa(rc.v0, rc.v1);
-            const T wzp0 = czp * face_kappa(rc.v0, rn.v0);
-            const T wzp1 = czp * face_kappa(rc.v1, rn.v1);
+            const T wx = g.cx * face_kappa<FR>(rc.v0, rc.v1);
+            const T wzp0 = czp * face_kappa<FR>(rc.v0, rn.v0);
+            const T wzp1 = czp * face_kappa<FR>(rc.v1, rn.v1);
             T acc0 = mv.v0 * xc.v0;
-            acc0 += cxl * face_kappa(rc.v0, rl) * (xc.v0 - xl);
+            acc0 += cxl * face_kappa<FR>(rc.v0, rl) * (xc.v0 - xl);
             acc0 += wx * (xc.v0 - xc.v1);
-            acc0 += cym * face_kappa(rc.v0, rym.v0) * (xc.v0 - xym.v0);
-            acc0 += cyp * face_kappa(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
+            acc0 += cym * face_kappa<FR>(rc.v0, rym.v0) * (xc.v0 - xym.v0);
+            acc0 += cyp * face_kappa<FR>(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
             acc0 += wzm0 * (xc.v0 - xm.v0);
             acc0 += wzp0 * (xc.v0 - xn.v0);
             T acc1 = mv.v1 * xc.v1;
             acc1 += wx * (xc.v1 - xc.v0);
-            acc1 += cxr * face_kappa(rc.v1, rr) * (xc.v1 - xr);
-            acc1 += cym * face_kappa(rc.v1, rym.v1) * (xc.v1 - xym.v1);
-            acc1 += cyp * face_kappa(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
+            acc1 += cxr * face_kappa<FR>(rc.v1, rr) * (xc.v1 - xr);
+            acc1 += cym * face_kappa<FR>(rc.v1, rym.v1) * (xc.v1 - xym.v1);
+            acc1 += cyp * face_kappa<FR>(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
             acc1 += wzm1 * (xc.v1 - xm.v1);
             acc1 += wzp1 * (xc.v1 - xn.v1);
             if (MODE >= 2) {
@@ -805,7 +825,7 @@ __device__ __forceinline__ Pair<T> pos(const HalfPair<T>& h, int par) {
 // Operator apply in the split layout: the pair march of k_apply_zp with each pair read from the
 // two halves of its row; pairs of x and rho of the current plane are exchanged through LDS. The
 // column pairs of x (planes k-1 .. k+2) and rho (k .. k+2) form the register rings.
-template <typename T, int MODE, bool FULL, int XW>
+template <typename T, int MODE, bool FULL, int XW, int FR = 0>
 __global__ __launch_bounds__(64 * XW * kRowsS) void k_apply_zs(Geo<T> g, ZTiles zt,
                                                      const T* __restrict__ rho,
                                                      const T* __restrict__ m,
@@ -910,21 +930,21 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_apply_zs(Geo<T> g, ZTiles 
         const Pair<T> mv = pos(c.mh, p);
         // plane k
         const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
-        const T wx = g.cx * face_kappa(rc.v0, rc.v1);
-        const T wzp0 = czp * face_kappa(rc.v0, rn.v0);
-        const T wzp1 = czp * face_kappa(rc.v1, rn.v1);
+        const T wx = g.cx * face_kappa<FR>(rc.v0, rc.v1);
+        const T wzp0 = czp * face_kappa<FR>(rc.v0, rn.v0);
+        const T wzp1 = czp * face_kappa<FR>(rc.v1, rn.v1);
         T acc0 = mv.v0 * xc.v0;
-        acc0 += ((t > 0 || g.px) ? g.cx : T(0)) * face_kappa(rc.v0, rl) * (xc.v0 - xl);
+        acc0 += ((t > 0 || g.px) ? g.cx : T(0)) * face_kappa<FR>(rc.v0, rl) * (xc.v0 - xl);
         acc0 += wx * (xc.v0 - xc.v1);
-        acc0 += sc.cym * face_kappa(rc.v0, rym.v0) * (xc.v0 - xym.v0);
-        acc0 += sc.cyp * face_kappa(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
+        acc0 += sc.cym * face_kappa<FR>(rc.v0, rym.v0) * (xc.v0 - xym.v0);
+        acc0 += sc.cyp * face_kappa<FR>(rc.v0, ryp.v0) * (xc.v0 - xyp.v0);
         acc0 += wzm0 * (xc.v0 - xm.v0);
         acc0 += wzp0 * (xc.v0 - xn.v0);
         T acc1 = mv.v1 * xc.v1;
         acc1 += wx * (xc.v1 - xc.v0);
-        acc1 += ((t < hx - 1 || g.px) ? g.cx : T(0)) * face_kappa(rc.v1, rr) * (xc.v1 - xr);
-        acc1 += sc.cym * face_kappa(rc.v1, rym.v1) * (xc.v1 - xym.v1);
-        acc1 += sc.cyp * face_kappa(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
+        acc1 += ((t < hx - 1 || g.px) ? g.cx : T(0)) * face_kappa<FR>(rc.v1, rr) * (xc.v1 - xr);
+        acc1 += sc.cym * face_kappa<FR>(rc.v1, rym.v1) * (xc.v1 - xym.v1);
+        acc1 += sc.cyp * face_kappa<FR>(rc.v1, ryp.v1) * (xc.v1 - xyp.v1);
         acc1 += wzm1 * (xc.v1 - xm.v1);
         acc1 += wzp1 * (xc.v1 - xn.v1);
         if (MODE >= 2) {
@@ -956,8 +976,8 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_apply_zs(Geo<T> g, ZTiles 
         R2 = ldh(rho, rbp, hx, t);
         const Pair<T> rc = pos(R1, p0), rm = pos(R0, p0 ^ 1);
         const T czm0 = (k0 > 0 || g.pz) ? g.cz : T(0);
-        wzm0 = czm0 * face_kappa(rc.v0, rm.v0);
-        wzm1 = czm0 * face_kappa(rc.v1, rm.v1);
+        wzm0 = czm0 * face_kappa<FR>(rc.v0, rm.v0);
+        wzm1 = czm0 * face_kappa<FR>(rc.v1, rm.v1);
     }
     Own A, B;
     load_own(k0, A);
@@ -984,7 +1004,7 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_apply_zs(Geo<T> g, ZTiles 
 // cells of colour c only. ZG (with RESID, colour red): z holds the zero-guess pre-smoothing,
 // whose red values are r dinv, so r - (m + sum w) z vanishes on red cells and t = sum_f w_f z_nb
 // (r and m are not read).
-template <typename T, bool DOT, bool RESID, bool ZG, bool FULL, int XW>
+template <typename T, bool DOT, bool RESID, bool ZG, bool FULL, int XW, int FR = 0>
 __global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
                                                     const T* __restrict__ m,
@@ -1072,20 +1092,20 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles z
         const T ra = c.ra;
         const T czm = (k > 0 || g.pz) ? g.cz : T(0);
         const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
-        const T wp = g.cx * face_kappa(ra, roc);                    // pair partner
+        const T wp = g.cx * face_kappa<FR>(ra, roc);                    // pair partner
         const T cxo = ((e ? t < hx - 1 : t > 0) || g.px) ? g.cx : T(0);  // outer x face factor
-        const T we = cxo * face_kappa(ra, rx);                      // outer x neighbour
+        const T we = cxo * face_kappa<FR>(ra, rx);                      // outer x neighbour
         const T w0 = e ? wp : we, v0 = e ? zoc : zx;
         const T w1 = e ? we : wp, v1 = e ? zx : zoc;
         T sw = w0, swz = w0 * v0;
         sw += w1;
         swz += w1 * v1;
-        const T wy0 = sc.cym * face_kappa(ra, ry0), wy1 = sc.cyp * face_kappa(ra, ry1);
+        const T wy0 = sc.cym * face_kappa<FR>(ra, ry0), wy1 = sc.cyp * face_kappa<FR>(ra, ry1);
         sw += wy0;
         swz += wy0 * zy0;
         sw += wy1;
         swz += wy1 * zy1;
-        const T wzm = czm * face_kappa(ra, rom), wzp = czp * face_kappa(ra, ron);
+        const T wzm = czm * face_kappa<FR>(ra, rom), wzp = czp * face_kappa<FR>(ra, ron);
         sw += wzm + wzp;
         swz += wzm * zom + wzp * zon;
         if (L.act) {
@@ -1132,7 +1152,7 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_rbgs_zs(Geo<T> g, ZTiles z
 // r' = r - alpha q (alpha = scal[S_ALPHA]), writes r' to rn (a second array: other workgroups
 // read r around their tiles meanwhile) and reduces ||r'||^2 over its cells into partials, with
 // the breakdown flag copied by workgroup 0 (as r -= alpha q does).
-template <typename T, bool FULL, int XW, bool UPD>
+template <typename T, bool FULL, int XW, bool UPD, int FR = 0>
 __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTiles zt,
                                                          const T* __restrict__ rho,
                                                          const T* __restrict__ dinv,
@@ -1242,14 +1262,14 @@ __global__ __launch_bounds__(64 * XW * kRowsS) void k_presmooth_zs(Geo<T> g, ZTi
         const T rbr = c.rho;
         const T czm = (k > 0 || g.pz) ? g.cz : T(0);
         const T czp = (k < g.nz - 1 || g.pz) ? g.cz : T(0);
-        const T wp = g.cx * face_kappa(rbr, cc.rho);
+        const T wp = g.cx * face_kappa<FR>(rbr, cc.rho);
         const T cxo = ((e ? t < hx - 1 : t > 0) || g.px) ? g.cx : T(0);
-        const T we = cxo * face_kappa(rbr, rx);
+        const T we = cxo * face_kappa<FR>(rbr, rx);
         T swq = (e ? wp : we) * (e ? qc : qx);
         swq += (e ? we : wp) * (e ? qx : qc);
-        swq += sc.cym * face_kappa(rbr, ry0) * qy0;
-        swq += sc.cyp * face_kappa(rbr, ry1) * qy1;
-        const T wzm = czm * face_kappa(rbr, cm.rho), wzp = czp * face_kappa(rbr, cn.rho);
+        swq += sc.cym * face_kappa<FR>(rbr, ry0) * qy0;
+        swq += sc.cyp * face_kappa<FR>(rbr, ry1) * qy1;
+        const T wzm = czm * face_kappa<FR>(rbr, cm.rho), wzp = czp * face_kappa<FR>(rbr, cn.rho);
         swq += wzm * qm + wzp * qn;
         if (L.act) {
             // the red values are next read by the prolongation after the coarse levels; the
@@ -1323,13 +1343,16 @@ static void launch_apply_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, con
     const dim3 grid(zt.tx * zt.ty * zt.tz), block = split_block(hx);
     switch (split_shape(hx)) {
         case SPLIT_FULL1:
-            launch_split(k_apply_zs<T, MODE, true, 1>, grid, block, s, g, zt, rho, m, x, b, y, partials);
+            WITH_FACE_RULE(g.frule,
+                launch_split(k_apply_zs<T, MODE, true, 1, FRV>, grid, block, s, g, zt, rho, m, x, b, y, partials));
             break;
         case SPLIT_FULL2:
-            launch_split(k_apply_zs<T, MODE, true, 2>, grid, block, s, g, zt, rho, m, x, b, y, partials);
+            WITH_FACE_RULE(g.frule,
+                launch_split(k_apply_zs<T, MODE, true, 2, FRV>, grid, block, s, g, zt, rho, m, x, b, y, partials));
             break;
         default:
-            launch_split(k_apply_zs<T, MODE, false, 2>, grid, block, s, g, zt, rho, m, x, b, y, partials);
+            WITH_FACE_RULE(g.frule,
+                launch_split(k_apply_zs<T, MODE, false, 2, FRV>, grid, block, s, g, zt, rho, m, x, b, y, partials));
             break;
     }
 }
@@ -1340,16 +1363,19 @@ static void launch_rbgs_zs(const Geo<T>& g, const ZTiles& zt, const T* rho, cons
     const dim3 grid(zt.tx * zt.ty * zt.tz), block = split_block(hx);
     switch (split_shape(hx)) {
         case SPLIT_FULL1:
-            launch_split(k_rbgs_zs<T, DOT, RESID, ZG, true, 1>, grid, block, s, g, zt, rho, m, r, z, colour,
-                         partials, tout);
+            WITH_FACE_RULE(g.frule,
+                launch_split(k_rbgs_zs<T, DOT, RESID, ZG, true, 1, FRV>, grid, block, s, g, zt, rho, m, r, z, colour,
+                         partials, tout));
             break;
         case SPLIT_FULL2:
-            launch_split(k_rbgs_zs<T, DOT, RESID, ZG, true, 2>, grid, block, s, g, zt, rho, m, r, z, colour,
-                         partials, tout);
+            WITH_FACE_RULE(g.frule,
+                launch_split(k_rbgs_zs<T, DOT, RESID, ZG, true, 2, FRV>, grid, block, s, g, zt, rho, m, r, z, colour,
+                         partials, tout));
             break;
         default:
-            launch_split(k_rbgs_zs<T, DOT, RESID, ZG, false, 2>, grid, block, s, g, zt, rho, m, r, z, colour,
-                         partials, tout);
+            WITH_FACE_RULE(g.frule,
+                launch_split(k_rbgs_zs<T, DOT, RESID, ZG, false, 2, FRV>, grid, block, s, g, zt, rho, m, r, z, colour,
+                         partials, tout));
             break;
     }
 }
@@ -1361,16 +1387,19 @@ static void launch_presmooth_zs(const Geo<T>& g, const ZTiles& zt, const T* rho,
     const dim3 grid(zt.tx * zt.ty * zt.tz), block = split_block(hx);
     switch (split_shape(hx)) {
         case SPLIT_FULL1:
-            hipLaunchKernelGGL((k_presmooth_zs<T, true, 1, UPD>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
-                               rn, rc);
+            WITH_FACE_RULE(g.frule,
+                hipLaunchKernelGGL((k_presmooth_zs<T, true, 1, UPD, FRV>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
+                               rn, rc));
             break;
         case SPLIT_FULL2:
-            hipLaunchKernelGGL((k_presmooth_zs<T, true, 2, UPD>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
-                               rn, rc);
+            WITH_FACE_RULE(g.frule,
+                hipLaunchKernelGGL((k_presmooth_zs<T, true, 2, UPD, FRV>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
+                               rn, rc));
             break;
         default:
-            hipLaunchKernelGGL((k_presmooth_zs<T, false, 2, UPD>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
-                               rn, rc);
+            WITH_FACE_RULE(g.frule,
+                hipLaunchKernelGGL((k_presmooth_zs<T, false, 2, UPD, FRV>), grid, block, 0, s, g, zt, rho, dinv, r, z, q,
+                               rn, rc));
             break;
     }
 }
@@ -1428,32 +1457,32 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
         zt.rev = g.rev;
         nb = zt.tx * zt.ty * zt.tz;
         dim3 grid(nb), block(kBlock);
-        switch (mode) {
-            case 0: hipLaunchKernelGGL((k_apply_zp<T, 0>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            case 1: hipLaunchKernelGGL((k_apply_zp<T, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            case 2: hipLaunchKernelGGL((k_apply_zp<T, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            default: hipLaunchKernelGGL((k_apply_zp<T, 3>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-        }
+        WITH_FACE_RULE(g.frule, switch (mode) {
+            case 0: hipLaunchKernelGGL((k_apply_zp<T, 0, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 1: hipLaunchKernelGGL((k_apply_zp<T, 1, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 2: hipLaunchKernelGGL((k_apply_zp<T, 2, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            default: hipLaunchKernelGGL((k_apply_zp<T, 3, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+        });
     } else if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 64);
         zt.rev = g.rev;
         nb = zt.tx * zt.ty * zt.tz;
         dim3 grid(nb), block(kBlock);
-        switch (mode) {
-            case 0: hipLaunchKernelGGL((k_apply_zm<T, 0>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            case 1: hipLaunchKernelGGL((k_apply_zm<T, 1>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            case 2: hipLaunchKernelGGL((k_apply_zm<T, 2>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-            default: hipLaunchKernelGGL((k_apply_zm<T, 3>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
-        }
+        WITH_FACE_RULE(g.frule, switch (mode) {
+            case 0: hipLaunchKernelGGL((k_apply_zm<T, 0, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 1: hipLaunchKernelGGL((k_apply_zm<T, 1, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            case 2: hipLaunchKernelGGL((k_apply_zm<T, 2, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+            default: hipLaunchKernelGGL((k_apply_zm<T, 3, FRV>), grid, block, 0, s, g, zt, rho, m, x, b, y, rc.partials); break;
+        });
     } else {
         Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
         nb = sh.grid.x * sh.grid.y * sh.grid.z;
-        switch (mode) {
-            case 0: hipLaunchKernelGGL((k_apply<T, 0>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
-            case 1: hipLaunchKernelGGL((k_apply<T, 1>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
-            case 2: hipLaunchKernelGGL((k_apply<T, 2>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
-            default: hipLaunchKernelGGL((k_apply<T, 3>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
-        }
+        WITH_FACE_RULE(g.frule, switch (mode) {
+            case 0: hipLaunchKernelGGL((k_apply<T, 0, FRV>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+            case 1: hipLaunchKernelGGL((k_apply<T, 1, FRV>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+            case 2: hipLaunchKernelGGL((k_apply<T, 2, FRV>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+            default: hipLaunchKernelGGL((k_apply<T, 3, FRV>), sh.grid, sh.block, 0, s, g, rho, m, x, b, y, rc); break;
+        });
     }
     if (mode == 1 || mode == 3) finalize(rc, nb, s);
 }
@@ -1461,7 +1490,7 @@ void launch_apply(const Geo<T>& g, const T* rho, const T* m, const T* x, const T
 // ------------------------------------------------------------------------------------------
 // red-black Gauss-Seidel
 
-template <typename T>
+template <typename T, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_rbgs(Geo<T> g, const T* __restrict__ rho,
                                                  const T* __restrict__ m,
                                                  const T* __restrict__ r, T* __restrict__ z,
@@ -1476,7 +1505,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(Geo<T> g, const T* __restrict__
     T ra = rho[a];
     T sw = T(0), swz = T(0);
     for_faces(g, i, j, k, a, [&](int nb, T c) {
-        T w = c * face_kappa(ra, rho[nb]);
+        T w = c * face_kappa<FR>(ra, rho[nb]);
         sw += w;
         swz += w * z[nb];
     });
@@ -1484,7 +1513,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(Geo<T> g, const T* __restrict__
 }
 
 // First red half sweep from z = 0: red cells r/D, black cells 0 (writes every cell).
-template <typename T>
+template <typename T, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_rbgs_zero(Geo<T> g, const T* __restrict__ rho,
                                                       const T* __restrict__ m,
                                                       const T* __restrict__ r,
@@ -1500,7 +1529,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zero(Geo<T> g, const T* __restr
     }
     T ra = rho[a];
     T sw = T(0);
-    for_faces(g, i, j, k, a, [&](int nb, T c) { sw += c * face_kappa(ra, rho[nb]); });
+    for_faces(g, i, j, k, a, [&](int nb, T c) { sw += c * face_kappa<FR>(ra, rho[nb]); });
     z[a] = r[a] / (m[a] + sw);
 }
 
@@ -1515,7 +1544,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zero(Geo<T> g, const T* __restr
 // unchanged by the sweep), one partial per workgroup.
 // RESID: instead of updating z, write the residual t = r - A z of the cells of `colour` to `t`
 // and 0 for the other colour (exact right after a Gauss-Seidel half sweep of the other colour).
-template <typename T, bool ZERO, bool DOT, bool RESID = false>
+template <typename T, bool ZERO, bool DOT, bool RESID, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
                                                     const T* __restrict__ rho,
                                                     const T* __restrict__ m,
@@ -1593,12 +1622,12 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
         T sw = T(0), swz = T(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const T w = cf[q] * face_kappa(ra, rv[q]);
+            const T w = cf[q] * face_kappa<FR>(ra, rv[q]);
             sw += w;
             swz += w * zv[q];
         }
-        const T wzm = czm * face_kappa(ra, sel ? rm1 : rm0);
-        const T wzp = czp * face_kappa(ra, sel ? rn1 : rn0);
+        const T wzm = czm * face_kappa<FR>(ra, sel ? rm1 : rm0);
+        const T wzp = czp * face_kappa<FR>(ra, sel ? rn1 : rn0);
         sw += wzm + wzp;
         swz += wzm * (sel ? zm1 : zm0) + wzp * (sel ? zn1 : zn0);
         if (RESID) {
@@ -1645,7 +1674,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs_zm(Geo<T> g, ZTiles zt,
 // directly: z_black = dinv_b (r_b + sum_f w_f r_nb dinv_nb). Each thread owns a cell pair; the
 // red-neighbour values q = r dinv of the pairs one plane up and down are kept in registers.
 // Same result as the zero-guess red sweep followed by a black sweep.
-template <typename T>
+template <typename T, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_presmooth_zm(Geo<T> g, ZTiles zt,
                                                          const T* __restrict__ rho,
                                                          const T* __restrict__ dinv,
@@ -1698,12 +1727,12 @@ __global__ __launch_bounds__(kBlock) void k_presmooth_zm(Geo<T> g, ZTiles zt,
         T sw = T(0), swq = T(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const T w = cf[q] * face_kappa(rb, rho[ab + o[q]]);
+            const T w = cf[q] * face_kappa<FR>(rb, rho[ab + o[q]]);
             sw += w;
             swq += w * (r[ab + o[q]] * dinv[ab + o[q]]);
         }
-        const T wzm = czm * face_kappa(rb, blk ? rm1 : rm0);
-        const T wzp = czp * face_kappa(rb, blk ? rn1 : rn0);
+        const T wzm = czm * face_kappa<FR>(rb, blk ? rm1 : rm0);
+        const T wzp = czp * face_kappa<FR>(rb, blk ? rn1 : rn0);
         swq += wzm * (blk ? qm1 : qm0) + wzp * (blk ? qn1 : qn0);
         const T zb = (r[ab] + swq) * dinv[ab];
         if (red == 0 || d1) z[a + red] = red ? qc1 : qc0;
@@ -1738,14 +1767,15 @@ bool launch_resid_red(const Geo<T>& g, const T* rho, const T* m, const T* r, con
     if (!use_zm(g.nx, g.ny, g.nz)) return false;
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
     zt.rev = g.rev;
-    hipLaunchKernelGGL((k_rbgs_zm<T, false, false, true>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
-                       s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t);
+    WITH_FACE_RULE(g.frule,
+        hipLaunchKernelGGL((k_rbgs_zm<T, false, false, true, FRV>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
+                       s, g, zt, rho, m, r, const_cast<T*>(z), 0, nullptr, t));
     return true;
 }
 
 // Zero-guess pre-smoothing in one pass over the cells of a level too small for the z march:
 // red cells z = r dinv, black cells dinv (r + sum_f w_f (r dinv)_nb) (their neighbours are red).
-template <typename T>
+template <typename T, int FR = 0>
 __global__ __launch_bounds__(kBlock) void k_presmooth(Geo<T> g, const T* __restrict__ rho,
                                                       const T* __restrict__ dinv, const T* __restrict__ r,
                                                       T* __restrict__ z) {
@@ -1760,7 +1790,7 @@ __global__ __launch_bounds__(kBlock) void k_presmooth(Geo<T> g, const T* __restr
     }
     const T ra = rho[a];
     T swq = T(0);
-    for_faces(g, i, j, k, a, [&](int nb, T c) { swq += c * face_kappa(ra, rho[nb]) * (r[nb] * dinv[nb]); });
+    for_faces(g, i, j, k, a, [&](int nb, T c) { swq += c * face_kappa<FR>(ra, rho[nb]) * (r[nb] * dinv[nb]); });
     z[a] = (r[a] + swq) * dinv[a];
 }
 
@@ -1774,13 +1804,15 @@ bool launch_presmooth(const Geo<T>& g, const T* rho, const T* dinv, const T* r, 
     }
     if (!use_zm(g.nx, g.ny, g.nz)) {
         const Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
-        hipLaunchKernelGGL((k_presmooth<T>), sh.grid, sh.block, 0, s, g, rho, dinv, r, z);
+        WITH_FACE_RULE(g.frule,
+            hipLaunchKernelGGL((k_presmooth<T, FRV>), sh.grid, sh.block, 0, s, g, rho, dinv, r, z));
         return true;
     }
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
     zt.rev = g.rev;
-    hipLaunchKernelGGL((k_presmooth_zm<T>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt, rho,
-                       dinv, r, z);
+    WITH_FACE_RULE(g.frule,
+        hipLaunchKernelGGL((k_presmooth_zm<T, FRV>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0, s, g, zt, rho,
+                       dinv, r, z));
     return true;
 }
 
@@ -1796,12 +1828,14 @@ void launch_rbgs(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z, in
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
         zt.rev = g.rev;
-        hipLaunchKernelGGL((k_rbgs_zm<T, false, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
-                           s, g, zt, rho, m, r, z, colour, nullptr);
+        WITH_FACE_RULE(g.frule,
+            hipLaunchKernelGGL((k_rbgs_zm<T, false, false, false, FRV>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
+                           s, g, zt, rho, m, r, z, colour, nullptr));
         return;
     }
     Shape3 sh = cells_shape((g.nx + 1) / 2, g.ny, g.nz);
-    hipLaunchKernelGGL((k_rbgs<T>), sh.grid, sh.block, 0, s, g, rho, m, r, z, colour);
+    WITH_FACE_RULE(g.frule,
+        hipLaunchKernelGGL((k_rbgs<T, FRV>), sh.grid, sh.block, 0, s, g, rho, m, r, z, colour));
 }
 
 // Split layout: the half sweep of `colour` reducing <r, z> over its own cells into partials
@@ -1830,8 +1864,9 @@ bool launch_rbgs_dot(const Geo<T>& g, const T* rho, const T* m, const T* r, T* z
     ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
     zt.rev = g.rev;
     const int nb = zt.tx * zt.ty * zt.tz;
-    hipLaunchKernelGGL((k_rbgs_zm<T, false, true>), dim3(nb), dim3(kBlock), 0, s, g, zt, rho, m, r, z,
-                       colour, rc.partials);
+    WITH_FACE_RULE(g.frule,
+        hipLaunchKernelGGL((k_rbgs_zm<T, false, true, false, FRV>), dim3(nb), dim3(kBlock), 0, s, g, zt, rho, m, r, z,
+                       colour, rc.partials));
     finalize(rc, nb, s);
     return true;
 }
@@ -1847,12 +1882,14 @@ void launch_rbgs_zero(const Geo<T>& g, const T* rho, const T* m, const T* r, T* 
     if (use_zm(g.nx, g.ny, g.nz)) {
         ZTiles zt = ztiles(g.nx, g.ny, g.nz, 128);
         zt.rev = g.rev;
-        hipLaunchKernelGGL((k_rbgs_zm<T, true, false>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
-                           s, g, zt, rho, m, r, z, 0, nullptr);
+        WITH_FACE_RULE(g.frule,
+            hipLaunchKernelGGL((k_rbgs_zm<T, true, false, false, FRV>), dim3(zt.tx * zt.ty * zt.tz), dim3(kBlock), 0,
+                           s, g, zt, rho, m, r, z, 0, nullptr));
         return;
     }
     Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
-    hipLaunchKernelGGL((k_rbgs_zero<T>), sh.grid, sh.block, 0, s, g, rho, m, r, z);
+    WITH_FACE_RULE(g.frule,
+        hipLaunchKernelGGL((k_rbgs_zero<T, FRV>), sh.grid, sh.block, 0, s, g, rho, m, r, z));
 }
 
 // ------------------------------------------------------------------------------------------

@@ -110,6 +110,7 @@ struct hp_handle {
     double inner_tol = 1e-5;
     int max_outer = 20;
     int coarsest_max = 512;
+    int face_rule = 0;  // HP_OPT_FACE_RULE
     hp_stats stats{};
     // kernel timing inside solves: event pool and the (class, first event) of each timed launch
     int timing = 0;
@@ -148,6 +149,7 @@ Geo<T> geo(const hp_handle* H, const LevelData& L) {
     g.cy = (T)(dt2 / (L.h[1] * L.h[1]));
     g.cz = (T)(dt2 / (L.h[2] * L.h[2]));
     g.split = L.split;
+    g.frule = H->face_rule;
     return g;
 }
 
@@ -256,7 +258,9 @@ int build_coarse_inverse(hp_handle* H) {
                         }
                         cc[d] = t;
                         int b = cc[0] + nx * (cc[1] + ny * cc[2]);
-                        double w = dt2 / (C.h[d] * C.h[d]) * (2.0 / (rho[a] + rho[b]));
+                        const double kappa = H->face_rule == 1 ? 0.5 * (1.0 / rho[a] + 1.0 / rho[b])
+                                                               : 2.0 / (rho[a] + rho[b]);
+                        double w = dt2 / (C.h[d] * C.h[d]) * kappa;
                         A[(size_t)a * n + a] += w;
                         A[(size_t)a * n + b] -= w;
                     }
@@ -1207,6 +1211,22 @@ int hp_set_option(hp_handle* H, int key, double v) {
             if (v != 0.0 && v != 1.0) return fail(HP_EINVAL, "kernel timing must be 0 or 1");
             H->timing = (int)v;
             return HP_OK;
+        case HP_OPT_FACE_RULE: {
+            if (v != 0.0 && v != 1.0) return fail(HP_EINVAL, "face rule must be 0 or 1");
+            if ((int)v == H->face_rule) return HP_OK;
+            H->face_rule = (int)v;
+            // the rule enters the Jacobi diagonals of every level and the coarsest inverse:
+            // recomputed in natural order, then the layout is restored
+            const int was_split = H->lv[0].split;
+            int rc = set_layout(H, 0);
+            if (rc) return rc;
+            for (auto& L : H->lv)
+                launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
+                                   L.dinv32, H->stream);
+            CHK(check_launch());
+            CHK(build_coarse_inverse(H));
+            return was_split ? set_layout(H, 1) : HP_OK;
+        }
         case HP_OPT_LAYOUT: {
             if (v != 0.0 && v != 1.0) return fail(HP_EINVAL, "layout must be 0 (natural) or 1 (split)");
             if (v == 1.0 && !split_allowed(H)) return fail(HP_EINVAL, "the grid does not allow the split layout");
@@ -1231,6 +1251,7 @@ int hp_get_option(const hp_handle* H, int key, double* v) {
         case HP_OPT_COARSEST_MAX: *v = H->coarsest_max; return HP_OK;
         case HP_OPT_LAYOUT: *v = H->lv[0].split; return HP_OK;
         case HP_OPT_KERNEL_TIMING: *v = H->timing; return HP_OK;
+        case HP_OPT_FACE_RULE: *v = H->face_rule; return HP_OK;
         default: return fail(HP_EINVAL, "unknown option %d", key);
     }
 }
