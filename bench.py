@@ -215,9 +215,56 @@ def learned_leg(p3, rho3, c23, rhs, x, W, K, dev, base, sols):
                      "max_rel_residual": max(q["rel_residual"] for q in stats),
                      "all_converged": all(q["converged"] for q in stats),
                      "speedup_vs_fp64_mgpcg": round(v / base, 3)}
+    out.update(previous_pressure_leg(s, rhs, x, W, K, base))
     s.close()
     net.close()
     out["training"] = training_leg(dev)
+    return out
+
+
+def previous_pressure_leg(s, rhs, x, W, K, base):
+    """With a previous pressure, the network's fourth input (the case a time step gives): p_prev
+    is the FP64 solution for the rhs plus 10% white noise (the perturbation the training samples
+    use), computed outside the timed region. Plain FP64 MG-PCG started from p_prev against the
+    warm start x0 = g net(b, p_prev) followed by FP64 MG-PCG; both to the same true residual."""
+    import torch
+    import paper_1112_3507_amd as hp
+    from paper_1112_3507_amd import workloads as wl
+    s.set_option(hp.OPT_MODE, hp.MODE_FP64_MGPCG)
+    log("bench: Ma=0.001 previous-pressure inputs")
+    prevs = []
+    for k in range(W + K):
+        noise = torch.from_numpy(wl.rhs_white(tuple(s.n), 5000 + k)).to(x.device)
+        bp = rhs[k] + 0.1 * (rhs[k].norm() / noise.norm()) * noise
+        pk = torch.zeros_like(x)
+        s.solve(bp, pk, tol=TOL)
+        prevs.append(pk)
+    out = {}
+    for name in ("prev_plain", "prev_warm_start"):
+        log("bench: Ma=0.001 %s" % name)
+        stats = []
+        for k in range(W + K):
+            if k == W:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if name == "prev_plain":
+                x.copy_(prevs[k])
+            else:
+                s.warm_start(rhs[k], x, p_prev=prevs[k])
+            st = s.solve(rhs[k], x, tol=TOL)
+            if k >= W:
+                stats.append(st)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        v = K / secs
+        out[name] = {"value": round(v, 3), "unit": "solves/s", "ms_per_step": round(1e3 * secs / K, 4),
+                     "iterations_mean": sum(q["iterations"] for q in stats) / K,
+                     "max_rel_residual": max(q["rel_residual"] for q in stats),
+                     "all_converged": all(q["converged"] for q in stats),
+                     "speedup_vs_fp64_mgpcg": round(v / base, 3)}
+    out["prev_warm_start"]["speedup_vs_prev_plain"] = round(out["prev_warm_start"]["value"] /
+                                                            out["prev_plain"]["value"], 3)
+    del prevs
     return out
 
 
@@ -594,6 +641,8 @@ def main():
         if lv is not None:
             var["learned_warm_start"] = lv["warm_start"]
             var["learned_fcg"] = lv["fcg"]
+            var["from_previous_pressure"] = {"plain": lv["prev_plain"],
+                                             "learned_warm_start": lv["prev_warm_start"]}
             result["learned_training"] = lv["training"]
         del rho3, c23
 
