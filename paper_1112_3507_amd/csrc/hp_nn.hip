@@ -287,7 +287,6 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
     // epilogue: this lane holds D[o = ct*16 + 4*grp + e][voxel li of row r of slice sl] (bias
     // included); a brick inside the grid needs no bounds checks
     const bool full = x0 + BX <= p.nx && y0 + BY <= p.ny && z0 + FZ <= p.nz;
-    const float lo = p.relu ? 0.f : -INFINITY;
     const int gx = x0 + li;
 #pragma unroll
     for (int sr = 0; sr < 4 * SPW; ++sr) {
@@ -299,7 +298,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
             const int o = ct * 16 + 4 * grp;
             float v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[sr][ct][e], lo);
+            for (int e = 0; e < 4; ++e) v[e] = p.relu ? fmaxf(acc[sr][ct][e], 0.f) : acc[sr][ct][e];
             if (CT == 1 && p.head) {
                 // the activation as it would be stored (bfloat16), dotted with the head weights;
                 // the four lanes of a voxel hold channels 4 grp .. 4 grp + 3

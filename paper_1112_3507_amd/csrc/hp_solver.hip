@@ -1547,11 +1547,14 @@ int hp_pressure_rhs(hp_handle* H, const hp_rhs_fields* f, double* rhs) {
     if (!f || !rhs || !f->rho_n || !f->c2_n || !f->p_n || !f->mom_n || !f->rho_np1 || !f->mom_star)
         return fail(HP_EINVAL, "null field");
     if (f->temp_n && (!f->conc_n || !f->rkc_n)) return fail(HP_EINVAL, "two components need conc_n and rkc_n");
+    const LevelData& F = H->lv[0];
+    // rhs may not overlap any input (the momenta span three cell arrays)
     const double* ins[] = {f->rho_n, f->c2_n, f->p_n, f->mom_n, f->rho_np1, f->mom_star, f->visc, f->temp_n,
                            f->conc_n, f->rkc_n};
-    for (const double* q : ins)
-        if (q == rhs) return fail(HP_EINVAL, "rhs must not alias an input");
-    const LevelData& F = H->lv[0];
+    const int spans[] = {1, 1, 1, 3, 1, 3, 1, 1, 1, 1};
+    for (int q = 0; q < 10; ++q)
+        if (ins[q] && rhs < ins[q] + spans[q] * F.N && ins[q] < rhs + F.N)
+            return fail(HP_EINVAL, "rhs must not overlap an input");
     const int bcs[3] = {H->bc.x, H->bc.y, H->bc.z};
     if (hydro_launch_rhs(F.n, bcs, F.h, H->dt, f, rhs, H->stream) != HP_OK) return check_launch();
     return check_launch();

@@ -210,3 +210,6 @@ def test_argument_errors():
         with pytest.raises(hp.HPError) as ex:   # rhs aliasing the pressure input
             sv.pressure_rhs(dev(p.rho), dev(p.c2), b, dev(s.mom_n), dev(p.rho), ms, b)
         assert ex.value.code == hp.EINVAL
+        with pytest.raises(hp.HPError) as ex:   # rhs inside the (3-array) momentum input
+            sv.pressure_rhs(dev(p.rho), dev(p.c2), dev(s.p_n), dev(s.mom_n), dev(p.rho), ms, ms[1])
+        assert ex.value.code == hp.EINVAL
