@@ -141,6 +141,10 @@ void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split,
 bool split_layout_ok(int nx, int ny, int nz, const Transfer* t);
 template <typename T>
 void launch_coarse_solve(const double* ainv, int nc, const T* b, T* x, hipStream_t s);
+// In-place inverse of the dense SPD n x n matrix a (row-major) by Gauss-Jordan steps ping-ponged
+// through work (n x n); the matrix must be put in a for even n and in work for odd n (the
+// result always ends in a); *flag is set on a pivot that is not positive.
+void launch_spd_inverse(double* a, double* work, int n, int* flag, hipStream_t s);
 
 // Deterministic dot <x, y> accumulated in FP64.
 template <typename T>

@@ -13,7 +13,6 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <thread>
 #include <utility>
 #include <vector>
 
@@ -74,8 +73,8 @@ struct hp_handle {
     double dt = 0.0;
     std::vector<LevelData> lv;
     int nc = 0;
-    double* ainv = nullptr;
-    std::vector<double> host_ainv;
+    double* ainv = nullptr;       // inverse of the coarsest operator (nc x nc)
+    double* ainv_work = nullptr;  // the Gauss-Jordan sweep's second buffer
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double* r2 = nullptr;  // second residual array: the fused residual update writes r' there
     // the split iterate of the running solve is zero and has not been written yet (a zero initial
@@ -265,64 +264,17 @@ int build_coarse_inverse(hp_handle* H) {
                         A[(size_t)a * n + b] -= w;
                     }
             }
-    // Cholesky A = L L^T (lower triangle of L stored in A)
-    for (int j = 0; j < n; ++j) {
-        double d = A[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
-        if (!(d > 0.0)) return fail(HP_EDOMAIN, "coarsest operator is not positive definite");
-        double ljj = std::sqrt(d);
-        A[(size_t)j * n + j] = ljj;
-        for (int i = j + 1; i < n; ++i) {
-            double s = A[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) s -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-            A[(size_t)i * n + j] = s / ljj;
-        }
-    }
-    // inverse: solve L L^T x = e_col for every column (independent, split over host threads);
-    // L y = e_col has y = 0 above row col; x goes to row col of X (the inverse is symmetric).
-    std::vector<double> U((size_t)n * n, 0.0);  // L^T, row-major, for contiguous back substitution
-    for (int i = 0; i < n; ++i)
-        for (int k = 0; k <= i; ++k) U[(size_t)k * n + i] = A[(size_t)i * n + k];
-    std::vector<double>& X = H->host_ainv;
-    X.assign((size_t)n * n, 0.0);
-    auto solve_columns = [&](int c0, int c1) {
-        std::vector<double> y(n);
-        for (int col = c0; col < c1; ++col) {
-            for (int i = 0; i < col; ++i) y[i] = 0.0;
-            for (int i = col; i < n; ++i) {
-                const double* Li = &A[(size_t)i * n];
-                double sum = (i == col) ? 1.0 : 0.0;
-                for (int k = col; k < i; ++k) sum -= Li[k] * y[k];
-                y[i] = sum / Li[i];
-            }
-            double* x = &X[(size_t)col * n];
-            for (int i = n - 1; i >= 0; --i) {
-                const double* Ui = &U[(size_t)i * n];
-                double sum = y[i];
-                for (int k = i + 1; k < n; ++k) sum -= Ui[k] * x[k];
-                x[i] = sum / Ui[i];
-            }
-        }
-    };
-    const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
-    if (nthreads == 1 || n < 64) {
-        solve_columns(0, n);
-    } else {
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nthreads; ++t)
-            pool.emplace_back(solve_columns, (int)((int64_t)n * t / nthreads),
-                              (int)((int64_t)n * (t + 1) / nthreads));
-        for (auto& th : pool) th.join();
-    }
-    for (int i = 0; i < n; ++i)  // exact symmetry keeps the V-cycle a symmetric operator
-        for (int j = i + 1; j < n; ++j) {
-            double v = 0.5 * (X[(size_t)i * n + j] + X[(size_t)j * n + i]);
-            X[(size_t)i * n + j] = v;
-            X[(size_t)j * n + i] = v;
-        }
-    HIPCHK(hipMemcpyAsync(H->ainv, X.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice,
-                          H->stream));
+    // inverse on the device: the operator goes where the Gauss-Jordan sweep starts (so that the
+    // inverse ends in ainv), a non-positive pivot means the operator is not positive definite
+    double* start = (n % 2 == 0) ? H->ainv : H->ainv_work;
+    HIPCHK(hipMemcpyAsync(start, A.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice, H->stream));
+    *H->host_flag = 0;
+    HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
+    launch_spd_inverse(H->ainv, H->ainv_work, n, H->flag, H->stream);
+    CHK(check_launch());
+    HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
+    if (*H->host_flag) return fail(HP_EDOMAIN, "coarsest operator is not positive definite");
     return HP_OK;
 }
 
@@ -1125,7 +1077,9 @@ int hp_setup_two_density(const hp_grid* grid, const double* rho_n, const double*
             if ((rc = dalloc(H, &L.t, L.N)) || (rc = dalloc(H, &L.t32, L.N))) return bail(rc);
         }
     }
-    if ((rc = dalloc(H, &H->ainv, (int64_t)H->nc * H->nc))) return bail(rc);
+    if ((rc = dalloc(H, &H->ainv, (int64_t)H->nc * H->nc)) ||
+        (rc = dalloc(H, &H->ainv_work, (int64_t)H->nc * H->nc)))
+        return bail(rc);
     if ((rc = dalloc(H, &H->r, N)) || (rc = dalloc(H, &H->z, N)) || (rc = dalloc(H, &H->p, N)) ||
         (rc = dalloc(H, &H->q, N)) || (rc = dalloc(H, &H->r2, N)))
         return bail(rc);
