@@ -439,3 +439,12 @@ def test_checkpoint_save_load_roundtrip(tmp_path):
     assert np.array_equal(b.get_params().cpu().numpy(), before)
     for n_ in (a, b, c):
         n_.close()
+
+
+def test_network_grid_limits():
+    """hp_nn_create rejects grids the convolutions cannot index (2^31 cells or more) and sizes
+    that are not multiples of 4, before allocating anything."""
+    for n in ((2048, 1024, 1024), (12, 8, 6), (0, 8, 8)):
+        with pytest.raises(hp.HPError) as ei:
+            hp.Net(n)
+        assert ei.value.code == hp.EINVAL, n
