@@ -22,8 +22,14 @@ enum Slot {
     S_FLAG = 6,    // breakdown flag (1.0 when p^T A p <= 0 or not finite)
     S_TMP = 7,     // scratch result of a plain dot
     S_RZ_NEW = 8,
+    S_GAMMA = 9,   // learned FCG: step of the network's estimate in the preconditioner
+    S_T1 = 10,     // learned FCG: dot products the scalar steps combine
+    S_T2 = 11,
     S_COUNT = 16
 };
+
+// scalar steps of the learned FCG (hp_fcg.hip)
+enum FcgScalar { FCG_GAMMA = 0, FCG_ALPHA = 1, FCG_BETA = 2 };
 
 // What the second reduction stage (one workgroup) does with the total.
 enum RedOp {
@@ -201,6 +207,10 @@ void launch_relayout_in(const double* src, double* dst, int nx, int ny, int nz, 
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 // scal[slot] = value (stream-ordered, graph-safe)
 void launch_set_scalar(double* scal, int slot, double value, hipStream_t s);
+// learned FCG (hp_fcg.hip): scal[S_GAMMA | S_ALPHA | S_BETA] from the slots; y = x - g y (sub)
+// or y += g x with g = scal[S_GAMMA] (both skip the g term when g = 0)
+void launch_fcg_scalar(double* scal, int what, hipStream_t s);
+void launch_fcg_gamma_update(double* y, const double* x, const double* scal, int64_t n, bool sub, hipStream_t s);
 
 // ---- steps either side of the solve (hp_hydro.hip); natural-layout FP64 cell arrays ----
 int hydro_launch_rhs(const int n[3], const int bc[3], const double h[3], double dt, const hp_rhs_fields* f,
@@ -215,9 +225,11 @@ int hydro_launch_eos(int64_t N, const double* rho, const double* mom, const doub
 
 // ---- learned stage (hp_nn.hip) ----
 int nn_grid(const hp_net* net, int* nx, int* ny, int* nz);
-// z = s * out_scale * net(r / s, log rho, -log(rho m), p_prev / s), s = RMS(r); p_prev may be null
+// z = s * out_scale * net(r / s, log rho, -log(rho m), p_prev / s), s = RMS(r); p_prev may be null.
+// rho and m in natural order; r, p_prev and z in natural order, or with split != 0 in the red-black
+// split storage of the finest level (nx even)
 int nn_apply(hp_net* net, hipStream_t stream, const double* r, const double* rho, const double* m,
-             const double* pprev, double* z);
+             const double* pprev, double* z, int split = 0);
 const char* nn_error();
 // training with a loss computed by the solver: forward pass, d = estimate - x, backward + Adam
 // from the physical-units output gradient coef * q

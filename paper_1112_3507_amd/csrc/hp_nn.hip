@@ -470,17 +470,32 @@ __global__ void k_reduce_dw(const float* __restrict__ partial, int nparts, int n
 
 // network input: [b/s, log rho, log c2, p_prev/s, 0, 0, 0, 0] in bf16; s = sqrt(scal[0])
 // (c2 may be null: then log c2 = -log(rho m) from the mass term m = 1/(rho c2))
+// Position of natural-order cell v in the red-black split storage of an nx x ny x nz level (each x
+// row holds its red cells, then its black cells; nx even): where the solver keeps its finest-level
+// vectors.
+__device__ __forceinline__ int64_t split_pos(int64_t v, int nx, int ny) {
+    const int64_t row = v / nx;
+    const int i = (int)(v - row * nx);
+    const int j = (int)(row % ny);
+    const int64_t k = row / ny;
+    const int c = (int)((i + j + k) & 1);
+    return row * nx + c * (nx >> 1) + (i >> 1);
+}
+
+// b and pprev in natural order or (split != 0) in the split storage of the nx x ny grid; rho,
+// c2 and m always in natural order
 __global__ void k_features(const double* __restrict__ b, const double* __restrict__ rho,
                            const double* __restrict__ c2, const double* __restrict__ m,
                            const double* __restrict__ pprev, const double* __restrict__ ss,
-                           bf16_t* __restrict__ out, int64_t n) {
+                           bf16_t* __restrict__ out, int64_t n, int split, int nx, int ny) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    const int64_t vb = split ? split_pos(v, nx, ny) : v;
     const double inv = 1.0 / ss[1];
     const double lc2 = c2 ? log(c2[v]) : -log(rho[v] * m[v]);
     uint4 pk;
-    pk.x = (unsigned)f2bf((float)(b[v] * inv)) | ((unsigned)f2bf((float)log(rho[v])) << 16);
-    pk.y = (unsigned)f2bf((float)lc2) | ((unsigned)f2bf((float)(pprev ? pprev[v] * inv : 0.0)) << 16);
+    pk.x = (unsigned)f2bf((float)(b[vb] * inv)) | ((unsigned)f2bf((float)log(rho[v])) << 16);
+    pk.y = (unsigned)f2bf((float)lc2) | ((unsigned)f2bf((float)(pprev ? pprev[vb] * inv : 0.0)) << 16);
     pk.z = 0u;
     pk.w = 0u;
     *(uint4*)(out + v * 8) = pk;
@@ -696,10 +711,11 @@ __global__ void k_head_bwd(const float* __restrict__ gy, const bf16_t* __restric
 }
 
 // x_out = scale * y (scale = s * out_scale), FP64 output
+// x (natural order, or split storage with split != 0) = s * out_scale * y
 __global__ void k_output(const float* __restrict__ y, const double* __restrict__ ss, double oscale,
-                         double* __restrict__ x, int64_t n) {
+                         double* __restrict__ x, int64_t n, int split, int nx, int ny) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) x[v] = (double)y[v] * ss[1] * oscale;
+    if (v < n) x[split ? split_pos(v, nx, ny) : v] = (double)y[v] * ss[1] * oscale;
 }
 
 __global__ void k_output_minus(const float* __restrict__ y, const double* __restrict__ ss, double oscale,
@@ -1235,12 +1251,12 @@ int adam(hp_net* N, float lr) {
 
 // network input from (b, rho, c2 or m, p_prev): scale, features into x0
 int features(hp_net* N, const double* b, const double* rho, const double* c2, const double* m,
-             const double* pprev) {
+             const double* pprev, int split = 0) {
     int rc = rhs_scale(N, b);
     if (rc) return rc;
-    const int64_t V = N->lv[0].nv;
-    hipLaunchKernelGGL(k_features, dim3(nblk(V)), dim3(256), 0, N->stream, b, rho, c2, m, pprev, N->ss,
-                       N->x0, V);
+    const Level& L = N->lv[0];
+    hipLaunchKernelGGL(k_features, dim3(nblk(L.nv)), dim3(256), 0, N->stream, b, rho, c2, m, pprev, N->ss,
+                       N->x0, L.nv, split, L.nx, L.ny);
     return check();
 }
 
@@ -1272,7 +1288,8 @@ int hp_nn_forward(hp_net* N, const double* b, const double* rho, const double* c
     if (rc) return rc;
     if ((rc = forward_net(N))) return rc;
     const int64_t V = N->lv[0].nv;
-    hipLaunchKernelGGL(k_output, dim3(nblk(V)), dim3(256), 0, N->stream, N->y, N->ss, N->out_scale, x, V);
+    hipLaunchKernelGGL(k_output, dim3(nblk(V)), dim3(256), 0, N->stream, N->y, N->ss, N->out_scale, x, V, 0,
+                       N->lv[0].nx, N->lv[0].ny);
     return check();
 }
 
@@ -1302,13 +1319,14 @@ int nn_grid(const hp_net* N, int* nx, int* ny, int* nz) {
 }
 // z = s * out_scale * net(r / s, log rho, -log(rho m), p_prev / s), s = RMS(r)
 int nn_apply(hp_net* N, hipStream_t stream, const double* r, const double* rho, const double* m,
-             const double* pprev, double* z) {
+             const double* pprev, double* z, int split) {
     N->stream = stream;
-    int rc = features(N, r, rho, nullptr, m, pprev);
+    int rc = features(N, r, rho, nullptr, m, pprev, split);
     if (rc) return rc;
     if ((rc = forward_net(N))) return rc;
-    const int64_t V = N->lv[0].nv;
-    hipLaunchKernelGGL(k_output, dim3(nblk(V)), dim3(256), 0, N->stream, N->y, N->ss, N->out_scale, z, V);
+    const Level& L = N->lv[0];
+    hipLaunchKernelGGL(k_output, dim3(nblk(L.nv)), dim3(256), 0, N->stream, N->y, N->ss, N->out_scale, z, L.nv,
+                       split, L.nx, L.ny);
     return check();
 }
 const char* nn_error() { return g_nn_err.c_str(); }

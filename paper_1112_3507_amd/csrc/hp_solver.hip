@@ -771,56 +771,48 @@ int fcg_learned(hp_handle* H, const double* b, double* x, double tol, double bno
     Geo<double> g = geo<double>(H, F);
     hipStream_t s = H->stream;
     hp_stats& st = H->stats;
-    auto dot = [&](const double* u, const double* v, double* out) -> int {
-        launch_dot<double>(u, v, N, red(H, OP_STORE, S_TMP), s);
-        CHK(check_launch());
-        CHK(read_scalars(H));
-        *out = H->host_scal[S_TMP];
-        return HP_OK;
+    // Every scalar stays on the device (dot products into slots, hp_fcg.hip for g, alpha, beta);
+    // the host waits once per iteration, for ||r||^2 and p^T A p.
+    auto dot = [&](const double* u, const double* v, int slot) {
+        launch_dot<double>(u, v, N, red(H, OP_STORE, slot), s);
     };
+    // z = g y + M (r - g A y), y = net(r), g = <r, y> / <y, A y> (0 if not both positive)
     auto precond = [&](const double* r, double* z) -> int {
-        int rc;
-        if (F.split) {  // the network works in natural order
-            relayout0<double>(H, r, H->w2, 0);
-            rc = nn_apply(H->net, s, H->w2, H->rho_nat, H->m_nat, nullptr, H->w3);
-            if (!rc) relayout0<double>(H, H->w3, H->w1, 1);
-        } else {
-            rc = nn_apply(H->net, s, r, F.rho, F.m, nullptr, H->w1);
-        }
+        // the network reads r and writes y in the finest level's storage order (its coefficient
+        // inputs in natural order)
+        const int rc = F.split ? nn_apply(H->net, s, r, H->rho_nat, H->m_nat, nullptr, H->w1, 1)
+                               : nn_apply(H->net, s, r, F.rho, F.m, nullptr, H->w1);
         if (rc) return fail(rc, "network: %s", nn_error());
         launch_apply<double>(g, F.rho, F.m, H->w1, nullptr, H->w2, 0, red(H, OP_NONE), s);
-        double rz1, z1az1;
-        CHK(dot(r, H->w1, &rz1));
-        CHK(dot(H->w1, H->w2, &z1az1));
-        double gam = (rz1 > 0.0 && z1az1 > 0.0 && std::isfinite(rz1) && std::isfinite(z1az1))
-                         ? rz1 / z1az1 : 0.0;
-        launch_axpby(1.0, r, -gam, H->w2, N, s);  // w2 = r - g A z1 (= r when g = 0)
-        if (gam == 0.0) launch_copy<double>(r, H->w2, N, s);
+        dot(r, H->w1, S_T1);
+        dot(H->w1, H->w2, S_T2);
+        launch_fcg_scalar(H->scal, FCG_GAMMA, s);
+        launch_fcg_gamma_update(H->w2, r, H->scal, N, true, s);    // w2 = r - g A y
         vcycle<double>(H, 0, H->w2, z);
-        if (gam != 0.0) launch_axpby(gam, H->w1, 1.0, z, N, s);
+        launch_fcg_gamma_update(z, H->w1, H->scal, N, false, s);  // z += g y
         return check_launch();
+    };
+    // q = A p with p^T A p into S_PQ
+    auto apply_pq = [&]() {
+        launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_STORE, S_PQ), s);
     };
     std::vector<double> hist;
     bool restart = true;
-    double pq = 0.0;
     while (true) {
         if (restart) {
             CHK(precond(H->r, H->z));
             launch_copy<double>(H->z, H->p, N, s);
-            launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_STORE, S_PQ), s);
-            CHK(check_launch());
-            CHK(read_scalars(H));
-            pq = H->host_scal[S_PQ];
+            apply_pq();
             restart = false;
         }
-        if (!(pq > 0.0) || !std::isfinite(pq)) return fail(HP_EBREAKDOWN, "FCG breakdown: p^T A p <= 0");
-        double pr;
-        CHK(dot(H->p, H->r, &pr));
-        launch_set_scalar(H->scal, S_ALPHA, pr / pq, s);
+        dot(H->p, H->r, S_T1);
+        launch_fcg_scalar(H->scal, FCG_ALPHA, s);          // alpha = <p, r> / p^T A p
         launch_axpy2_norm<double>(x, H->p, H->r, H->q, N, red(H, OP_STORE, S_RR), s);
         CHK(check_launch());
         CHK(read_scalars(H));
         st.iterations++;
+        const double pq = H->host_scal[S_PQ];
+        if (!(pq > 0.0) || !std::isfinite(pq)) return fail(HP_EBREAKDOWN, "FCG breakdown: p^T A p <= 0");
         double rr = H->host_scal[S_RR];
         if (!std::isfinite(rr)) return fail(HP_ENAN, "non-finite residual in iteration %d", st.iterations);
         if (std::sqrt(rr) <= tol * bnorm) {
@@ -849,14 +841,11 @@ int fcg_learned(hp_handle* H, const double* b, double* x, double tol, double bno
             return rc;
         }
         CHK(precond(H->r, H->z));
-        double zq;
-        CHK(dot(H->z, H->q, &zq));
-        launch_set_scalar(H->scal, S_BETA, -zq / pq, s);
+        dot(H->z, H->q, S_T1);
+        launch_fcg_scalar(H->scal, FCG_BETA, s);           // beta = -<z, A p_old> / p_old^T A p_old
         launch_xpby<double>(H->z, H->p, N, H->scal, s);
-        launch_apply<double>(g, F.rho, F.m, H->p, nullptr, H->q, 1, red(H, OP_STORE, S_PQ), s);
+        apply_pq();
         CHK(check_launch());
-        CHK(read_scalars(H));
-        pq = H->host_scal[S_PQ];
     }
     double rel;
     CHK(true_residual(H, b, x, H->z, bnorm, &rel));
