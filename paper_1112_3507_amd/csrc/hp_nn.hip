@@ -95,6 +95,9 @@ struct ConvArgs {
     // non-null (one output tile only): the network head is applied in the epilogue and out is
     // y[voxel] (FP32) = sum_c bf16(act[voxel][c]) head[c] + head[16]; act itself is not stored
     const float* head;
+    // non-null (one output tile, two z-slices per wave, bf16 output): the 2x2x2 mean of the
+    // stored activation is written here as well ([coarse voxel][16], grid sizes halved)
+    bf16_t* pool_out;
 };
 
 // SPW z-slices per wave: the output brick is 16 x 4 x (4 SPW) voxels.
@@ -288,6 +291,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
     // included); a brick inside the grid needs no bounds checks
     const bool full = x0 + BX <= p.nx && y0 + BY <= p.ny && z0 + FZ <= p.nz;
     const int gx = x0 + li;
+    constexpr bool POOL = (CT == 1 && SPW == 2 && !OUT_F32);
+    uint2 stored[POOL ? 4 * SPW : 1];  // the bfloat16 pairs written for each row (pooling)
+#pragma unroll
+    for (int sr = 0; sr < (POOL ? 4 * SPW : 1); ++sr) stored[sr] = uint2{0u, 0u};
 #pragma unroll
     for (int sr = 0; sr < 4 * SPW; ++sr) {
         const int gz = z0 + wave * SPW + (sr >> 2), gy = y0 + (sr & 3);
@@ -317,6 +324,43 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvArgs p) {
                 pk.x = pack_bf2(v[0], v[1]);
                 pk.y = pack_bf2(v[2], v[3]);
                 *(uint2*)((bf16_t*)p.out + vox * p.cout + o) = pk;
+                if constexpr (POOL) stored[sr] = pk;
+            }
+        }
+    }
+    if constexpr (POOL) {
+        if (p.pool_out) {
+            // 2x2x2 mean of the stored activation: the wave holds two z-slices and four y rows, and
+            // the x pair sits in lanes li, li + 1. The eight values of each channel are summed in
+            // z, y, x order (x fastest) in FP32, then halved three times and rounded.
+            const int cx = p.nx >> 1, cy = p.ny >> 1;
+            const int X = gx >> 1, Z = (z0 + wave * SPW) >> 1;
+#pragma unroll
+            for (int yp = 0; yp < 2; ++yp) {
+                float sum[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int zc = 0; zc < 2; ++zc)
+#pragma unroll
+                    for (int yc = 0; yc < 2; ++yc) {
+                        const uint2 own = stored[zc * 4 + 2 * yp + yc];
+                        const uint2 nxt = uint2{(unsigned)__shfl_down((int)own.x, 1, 64),
+                                                (unsigned)__shfl_down((int)own.y, 1, 64)};
+                        const unsigned w[2][2] = {{own.x, own.y}, {nxt.x, nxt.y}};
+#pragma unroll
+                        for (int xc = 0; xc < 2; ++xc) {
+                            sum[0] += __uint_as_float(w[xc][0] << 16);
+                            sum[1] += __uint_as_float(w[xc][0] & 0xffff0000u);
+                            sum[2] += __uint_as_float(w[xc][1] << 16);
+                            sum[3] += __uint_as_float(w[xc][1] & 0xffff0000u);
+                        }
+                    }
+                const int Y = (y0 >> 1) + yp;
+                if (!(li & 1) && gx < p.nx && 2 * Y < p.ny && 2 * Z < p.nz) {
+                    uint2 pk;
+                    pk.x = pack_bf2(sum[0] * 0.125f, sum[1] * 0.125f);
+                    pk.y = pack_bf2(sum[2] * 0.125f, sum[3] * 0.125f);
+                    *(uint2*)(p.pool_out + (((int64_t)Z * cy + Y) * cx + X) * 16 + 4 * grp) = pk;
+                }
             }
         }
     }
@@ -847,11 +891,13 @@ int check() {
     return HP_OK;
 }
 
-void conv_launch(hp_net* N, int l, const bf16_t* a, int ca, int a_up, const bf16_t* b, int cb,
+// returns whether the launch also wrote the 2x2x2 mean into `pool` (one 16-channel output tile
+// with two z-slices per wave and bf16 output; else the caller pools)
+bool conv_launch(hp_net* N, int l, const bf16_t* a, int ca, int a_up, const bf16_t* b, int cb,
                  const bf16_t* w, const float* bias, void* out, int cout, int relu, bool out_f32,
-                 const float* head = nullptr) {
+                 const float* head = nullptr, bf16_t* pool = nullptr) {
     const Level& L = N->lv[level_of_conv(l)];
-    ConvArgs p{a, ca, a_up, b, cb, w, bias, out, cout, L.nx, L.ny, L.nz, relu, head};
+    ConvArgs p{a, ca, a_up, b, cb, w, bias, out, cout, L.nx, L.ny, L.nz, relu, head, pool};
     const int ct = cout / 16;
     const int cin = ca + cb;
     // two z-slices per wave for the 16-channel outputs (more products per staged brick; four
@@ -884,6 +930,7 @@ void conv_launch(hp_net* N, int l, const bf16_t* a, int ca, int a_up, const bf16
 #undef CONV_CASE
 #undef CONV_LAUNCH
 #undef CONV_LAUNCH2
+    return pool && ct == 1 && spw == 2 && !out_f32;
 }
 
 // conv input tensors of layer l in the forward pass
@@ -919,8 +966,9 @@ int pack_weights(hp_net* N) {
 }
 
 int forward_net(hp_net* N) {
+    bool pooled1 = false;  // layer 1 wrote pool(e1) in its epilogue
     for (int l = 0; l < NCONV; ++l) {
-        if (l == 2) {
+        if (l == 2 && !pooled1) {
             const Level& L = N->lv[1];
             hipLaunchKernelGGL(k_pool, dim3(nblk(L.nv * 2)), dim3(256), 0, N->stream, N->act[1], N->p1,
                                L.nx, L.ny, L.nz, 16);
@@ -934,9 +982,10 @@ int forward_net(hp_net* N) {
         // without training the last layer's activation is only needed by the head, which then
         // runs in that convolution's epilogue
         const bool fuse_head = l == NCONV - 1 && !N->training;
-        conv_launch(N, l, in.a, in.ca, in.a_up, in.b, in.cb, N->wf[l], N->theta + N->boff[l],
-                    fuse_head ? (void*)N->y : (void*)N->act[l], COUT[l], 1, false,
-                    fuse_head ? N->theta + N->hoff : nullptr);
+        const bool done = conv_launch(N, l, in.a, in.ca, in.a_up, in.b, in.cb, N->wf[l], N->theta + N->boff[l],
+                                      fuse_head ? (void*)N->y : (void*)N->act[l], COUT[l], 1, false,
+                                      fuse_head ? N->theta + N->hoff : nullptr, l == 1 ? N->p1 : nullptr);
+        if (l == 1) pooled1 = done;
     }
     if (N->training) {
         const Level& L = N->lv[0];
