@@ -108,9 +108,30 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
                                                      const double* __restrict__ partials2, int nb2,
                                                      double* __restrict__ sc, int op, int slot) {
     const int tid = threadIdx.x;
+    // the scalar the op combines with, and the first kU partials of each list, are loaded before
+    // anything is summed (one memory round trip instead of one per partial); the sum order is
+    // that of the plain strided loop
+    constexpr int kU = 4;
+    const double rz = sc[S_RZ];
+    // (clamped indices: the loads are unconditional; partials2 may be absent, nb is at least 1)
+    const double* q2 = nb2 > 0 ? partials2 : partials;
+    const int l1 = max(nb, 1) - 1, l2 = nb2 > 0 ? nb2 - 1 : l1;
+    double v[2][kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int b = tid + u * kBlock;
+        v[0][u] = partials[min(b, l1)];
+        v[1][u] = q2[min(b, l2)];
+    }
     double acc = 0.0;
-    for (int b = tid; b < nb; b += kBlock) acc += partials[b];
-    for (int b = tid; b < nb2; b += kBlock) acc += partials2[b];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        if (tid + u * kBlock < nb) acc += v[0][u];
+    for (int b = tid + kU * kBlock; b < nb; b += kBlock) acc += partials[b];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+        if (tid + u * kBlock < nb2) acc += v[1][u];
+    for (int b = tid + kU * kBlock; b < nb2; b += kBlock) acc += partials2[b];
     double tot = block_sum(acc);
     if (tid != 0) return;
     switch (op) {
@@ -121,11 +142,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
                 sc[S_FLAG] = 1.0;
                 sc[S_ALPHA] = 0.0;
             } else {
-                sc[S_ALPHA] = sc[S_RZ] / tot;
+                sc[S_ALPHA] = rz / tot;
             }
             break;
         case OP_BETA:
-            sc[S_BETA] = tot / sc[S_RZ];
+            sc[S_BETA] = tot / rz;
             sc[S_RZ] = tot;
             break;
         case OP_RZINIT:
@@ -174,18 +195,27 @@ static inline int vec_blocks(int64_t n) {
 int64_t reduce_blocks_vec(int64_t n) { return vec_blocks(n); }
 
 // ------------------------------------------------------------------------------------------
-// Stencil core: visits the (up to six) faces of cell (i,j,k) at flat index a.
-// F(nb) is called with the neighbour's flat index once per face.
+// Stencil core: visits the six faces of cell (i,j,k) at flat index a in the order x-, x+, y-, y+,
+// z-, z+. F(nb, c) is called once per face with the neighbour's flat index and the face factor; a
+// face that does not exist (the end of a Neumann axis) gets factor 0 and the cell itself as a
+// stand-in neighbour. No call is conditional, so every neighbour load can be in flight at once
+// (with a branch per face each load waited for the one before it).
 
 template <typename T, typename F>
 __device__ __forceinline__ void for_faces(const Geo<T>& g, int i, int j, int k, int a, F&& f) {
-    const int sx = 1, sy = g.nx, sz = g.nx * g.ny;
-    if (i > 0) f(a - sx, g.cx); else if (g.px) f(a + (g.nx - 1) * sx, g.cx);
-    if (i < g.nx - 1) f(a + sx, g.cx); else if (g.px) f(a - (g.nx - 1) * sx, g.cx);
-    if (j > 0) f(a - sy, g.cy); else if (g.py) f(a + (g.ny - 1) * sy, g.cy);
-    if (j < g.ny - 1) f(a + sy, g.cy); else if (g.py) f(a - (g.ny - 1) * sy, g.cy);
-    if (k > 0) f(a - sz, g.cz); else if (g.pz) f(a + (g.nz - 1) * sz, g.cz);
-    if (k < g.nz - 1) f(a + sz, g.cz); else if (g.pz) f(a - (g.nz - 1) * sz, g.cz);
+    const int sy = g.nx, sz = g.nx * g.ny;
+    const int oxm = i > 0 ? -1 : (g.px ? g.nx - 1 : 0);
+    const int oxp = i < g.nx - 1 ? 1 : (g.px ? -(g.nx - 1) : 0);
+    const int oym = j > 0 ? -sy : (g.py ? (g.ny - 1) * sy : 0);
+    const int oyp = j < g.ny - 1 ? sy : (g.py ? -(g.ny - 1) * sy : 0);
+    const int ozm = k > 0 ? -sz : (g.pz ? (g.nz - 1) * sz : 0);
+    const int ozp = k < g.nz - 1 ? sz : (g.pz ? -(g.nz - 1) * sz : 0);
+    f(a + oxm, (i > 0 || g.px) ? g.cx : T(0));
+    f(a + oxp, (i < g.nx - 1 || g.px) ? g.cx : T(0));
+    f(a + oym, (j > 0 || g.py) ? g.cy : T(0));
+    f(a + oyp, (j < g.ny - 1 || g.py) ? g.cy : T(0));
+    f(a + ozm, (k > 0 || g.pz) ? g.cz : T(0));
+    f(a + ozp, (k < g.nz - 1 || g.pz) ? g.cz : T(0));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1505,9 +1535,10 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(Geo<T> g, const T* __restrict__
     T ra = rho[a];
     T sw = T(0), swz = T(0);
     for_faces(g, i, j, k, a, [&](int nb, T c) {
+        const T zn = z[nb];  // at a missing face the cell's own old value, which must not count
         T w = c * face_kappa<FR>(ra, rho[nb]);
         sw += w;
-        swz += w * z[nb];
+        swz += w * (c != T(0) ? zn : T(0));
     });
     z[a] = (r[a] + swz) / (m[a] + sw);
 }
@@ -1932,7 +1963,7 @@ __device__ __forceinline__ void restrict_taps(int I, int nf, int coarsened, int 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict(Transfer t, const T* __restrict__ fine,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_restrict(Transfer t, const T* __restrict__ fine,
                                                      T* __restrict__ coarse) {
     int I = blockIdx.x * blockDim.x + threadIdx.x;
     int J = blockIdx.y * blockDim.y + threadIdx.y;
@@ -1943,16 +1974,25 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Transfer t, const T* __rest
     restrict_taps(I, t.nfx, t.fx, t.perx, ix, wx);
     restrict_taps(J, t.nfy, t.fy, t.pery, iy, wy);
     restrict_taps(K, t.nfz, t.fz, t.perz, iz, wz);
+    // all 64 loads first (these levels are small: what counts is that they are in flight together)
+    T v[4][4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const T* row = fine + (int64_t)t.nfx * (iy[b] + (int64_t)t.nfy * iz[c]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[c][b][q] = row[ix[q]];
+        }
     T acc = T(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         T accy = T(0);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const T* row = fine + (int64_t)t.nfx * (iy[b] + (int64_t)t.nfy * iz[c]);
             T accx = T(0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) accx += (T)wx[q] * row[ix[q]];
+            for (int q = 0; q < 4; ++q) accx += (T)wx[q] * v[c][b][q];
             accy += (T)wy[b] * accx;
         }
         acc += (T)wz[c] * accy;
@@ -2193,12 +2233,15 @@ void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s,
 }
 
 // Coarse taps of fine index i along one axis for P.
-__device__ __forceinline__ int prolong_taps(int i, int nc, int coarsened, int periodic, int* idx,
-                                            float* w) {
+// Always two (index, weight) pairs: on an axis that is not coarsened the second has weight 0 and
+// the first index again, so the prolongation is straight-line code with independent loads.
+__device__ __forceinline__ void prolong_taps(int i, int nc, int coarsened, int periodic, int* idx,
+                                             float* w) {
     if (!coarsened) {
-        idx[0] = i;
+        idx[0] = idx[1] = i;
         w[0] = 1.0f;
-        return 1;
+        w[1] = 0.0f;
+        return;
     }
     int parent = i >> 1;
     int other = (i & 1) ? parent + 1 : parent - 1;
@@ -2207,7 +2250,6 @@ __device__ __forceinline__ int prolong_taps(int i, int nc, int coarsened, int pe
     w[0] = 0.75f;
     idx[1] = other;
     w[1] = 0.25f;
-    return 2;
 }
 
 template <typename T>
@@ -2219,21 +2261,35 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Transfer t, const T* __r
     if (i >= t.nfx || j >= t.nfy || k >= t.nfz) return;
     int ix[2], iy[2], iz[2];
     float wx[2], wy[2], wz[2];
-    int nxs = prolong_taps(i, t.ncx, t.fx, t.perx, ix, wx);
-    int nys = prolong_taps(j, t.ncy, t.fy, t.pery, iy, wy);
-    int nzs = prolong_taps(k, t.ncz, t.fz, t.perz, iz, wz);
-    T acc = T(0);
-    for (int c = 0; c < nzs; ++c) {
-        T accy = T(0);
-        for (int b = 0; b < nys; ++b) {
+    prolong_taps(i, t.ncx, t.fx, t.perx, ix, wx);
+    prolong_taps(j, t.ncy, t.fy, t.pery, iy, wy);
+    prolong_taps(k, t.ncz, t.fz, t.perz, iz, wz);
+    T* out = fine + i + (int64_t)t.nfx * (j + (int64_t)t.nfy * k);
+    const T f0 = *out;
+    T v[2][2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
             const T* row = coarse + (int64_t)t.ncx * (iy[b] + (int64_t)t.ncy * iz[c]);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) v[c][b][q] = row[ix[q]];
+        }
+    // a weight-0 tap adds an exact zero: the sums are those over the real taps alone
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        T accy = T(0);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
             T accx = T(0);
-            for (int q = 0; q < nxs; ++q) accx += (T)wx[q] * row[ix[q]];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) accx += (T)wx[q] * v[c][b][q];
             accy += (T)wy[b] * accx;
         }
         acc += (T)wz[c] * accy;
     }
-    fine[i + (int64_t)t.nfx * (j + (int64_t)t.nfy * k)] += acc;
+    *out = f0 + acc;
 }
 
 // One thread per fine cell pair (2I, 2I+1) of one fine row j, 64 pairs per wave, one fine row
@@ -2510,7 +2566,20 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(const double* __restric
     double acc = 0.0;
     if (row < nc) {
         const double* arow = ainv + (int64_t)row * nc;
-        for (int c = lane; c < nc; c += 64) acc += arow[c] * (double)b[c];
+        // the first kU columns of the lane are loaded together (clamped indices, products of
+        // columns past nc dropped): nc <= 64 kU needs one memory round trip, not nc / 64
+        constexpr int kU = 8;
+        double av[kU], bv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int c = min(lane + 64 * u, nc - 1);
+            av[u] = arow[c];
+            bv[u] = (double)b[c];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (lane + 64 * u < nc) acc += av[u] * bv[u];
+        for (int c = lane + 64 * kU; c < nc; c += 64) acc += arow[c] * (double)b[c];
     }
     acc = wave_sum(acc);
     if (row < nc && lane == 0) x[row] = (T)acc;
