@@ -181,7 +181,10 @@ void launch_jacobi_apply(const double* dinv, const double* r, double* z, int64_t
 // dst = (float)(src * scale)
 void launch_cast_scale_f32(const double* src, float* dst, double scale, int64_t n, hipStream_t s);
 // x += scale * (double)d
-void launch_axpy_from_f32(double* x, const float* d, double scale, int64_t n, hipStream_t s);
+// x += scale (d + alpha p) with d + alpha p in FP32 (alpha = scal[S_ALPHA]; the alpha p term only
+// when pending); xzero / dzero: x / d have not been written and are taken as zero
+void launch_refine_update(double* x, bool xzero, const float* d, bool dzero, const float* p, bool pending,
+                          const double* scal, double scale, int64_t n, hipStream_t s);
 template <typename T>
 void launch_fill(T* x, T v, int64_t n, hipStream_t s);
 // dst = src with 16-byte non-temporal loads and stores (16-byte aligned pointers)

@@ -2840,16 +2840,41 @@ void launch_cast_scale_f32(const double* src, float* dst, double scale, int64_t 
                        0, s, src, dst, scale, n);
 }
 
-__global__ __launch_bounds__(kBlock) void k_axpy_from_f32(double* __restrict__ x,
-                                                          const float* __restrict__ d,
-                                                          double scale, int64_t n) {
-    int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (a < n) x[a] += scale * (double)d[a];
+// The refinement step of mixed precision in one pass: x += scale d, where d is the FP32 solution of
+// the inner solve with its last update d += alpha p (alpha = scal[S_ALPHA]) applied here in FP32
+// when it is still due (PEND), exactly as the inner solve would have applied it; XZ / DZ: x / d
+// have not been written yet and are zero.
+template <bool XZ, bool DZ, bool PEND>
+__global__ __launch_bounds__(kBlock) void k_refine_update(double* __restrict__ x, const float* __restrict__ d,
+                                                          const float* __restrict__ p,
+                                                          const double* __restrict__ scal, double scale,
+                                                          int64_t n) {
+    const float alpha = (float)scal[S_ALPHA];
+    const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (a < n) {
+        float v = DZ ? 0.0f : d[a];
+        if (PEND) v = v + alpha * p[a];
+        x[a] = (XZ ? 0.0 : x[a]) + scale * (double)v;
+    }
 }
 
-void launch_axpy_from_f32(double* x, const float* d, double scale, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy_from_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, x, d, scale, n);
+void launch_refine_update(double* x, bool xzero, const float* d, bool dzero, const float* p, bool pending,
+                          const double* scal, double scale, int64_t n, hipStream_t s) {
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+#define REFINE_CASE(XZ, DZ, PEND)                                                                       \
+    if (xzero == XZ && dzero == DZ && pending == PEND) {                                                \
+        hipLaunchKernelGGL((k_refine_update<XZ, DZ, PEND>), grid, block, 0, s, x, d, p, scal, scale, n); \
+        return;                                                                                         \
+    }
+    REFINE_CASE(false, false, false)
+    REFINE_CASE(false, false, true)
+    REFINE_CASE(false, true, false)
+    REFINE_CASE(false, true, true)
+    REFINE_CASE(true, false, false)
+    REFINE_CASE(true, false, true)
+    REFINE_CASE(true, true, false)
+    REFINE_CASE(true, true, true)
+#undef REFINE_CASE
 }
 
 // Streaming copy (the measured bandwidth reference of the roofline figures): each thread moves

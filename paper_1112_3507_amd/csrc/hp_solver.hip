@@ -80,6 +80,8 @@ struct hp_handle {
     // the split iterate of the running solve is zero and has not been written yet (a zero initial
     // guess): its first update writes x = alpha p without reading it
     bool x_unset = false;
+    // likewise for the inner FP32 solution of mixed precision within one inner solve
+    bool x32_unset = false;
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     float* r32b = nullptr;  // second FP32 residual array (fused residual update)
     // split layout of the finest level: whether it is wanted, split copies of the caller's rhs and
@@ -637,18 +639,22 @@ void next_direction32(hp_handle* H, bool pre_done = false) {
     hipStream_t s = H->stream;
     RedCtl rc = red(H, OP_BETA);
     if (!vcycle<float>(H, 0, H->r32, H->z32, &rc, pre_done)) launch_dot<float>(H->r32, H->z32, F.N, rc, s);
-    launch_xpby_x<float>(H->z32, H->p32, H->x32, F.N, H->scal, s);
+    launch_xpby_x<float>(H->z32, H->p32, H->x32, F.N, H->scal, s, H->x32_unset);
+    H->x32_unset = false;
     launch_apply<float>(geo_pass(H, geo<float>(H, F), 0), F.rho32, F.m32, H->p32, nullptr, H->q32, 1,
                         red(H, OP_ALPHA), s);
 }
 
-// FP32 MG-PCG on A32 d = r32 (unit-norm r32), d = x32 starts at 0; returns inner iterations.
-int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
+// FP32 MG-PCG on A32 d = r32 (unit-norm r32), d = x32 starts at 0 (unset: its first update writes
+// it); returns inner iterations. The last update d += alpha p is left to the caller where it is
+// still due (*pending): the refinement step applies it in the same pass as x += scale d.
+int inner_pcg32(hp_handle* H, double eta, int budget, int* its, bool* pending) {
     LevelData& F = H->lv[0];
     const int64_t N = F.N;
     Geo<float> g = geo<float>(H, F);
     hipStream_t s = H->stream;
-    launch_fill<float>(H->x32, 0.0f, N, s);
+    H->x32_unset = true;
+    *pending = false;
     {
         RedCtl rc = red(H, OP_RZINIT);
         if (!vcycle<float>(H, 0, H->r32, H->z32, &rc)) launch_dot<float>(H->r32, H->z32, N, rc, s);
@@ -693,7 +699,7 @@ int inner_pcg32(hp_handle* H, double eta, int budget, int* its) {
         if (std::sqrt(rr) <= eta || *its >= budget || stalled) break;
         if (!ahead) next_direction32(H);
     }
-    if (*its > 0 && !ahead) launch_axpy_alpha<float>(H->x32, H->p32, N, H->scal, s);
+    *pending = *its > 0 && !ahead;
     return HP_OK;
 }
 
@@ -714,9 +720,13 @@ int mixed_ir(hp_handle* H, const double* b, double* x, double tol, double bnorm)
         // the inner solve need not go below what the outer tolerance still requires
         double eta = std::max(H->inner_tol, 0.5 * tol * bnorm / rnorm);
         int its = 0;
-        CHK(inner_pcg32(H, eta, H->max_iter - st.iterations, &its));
+        bool pending = false;
+        CHK(inner_pcg32(H, eta, H->max_iter - st.iterations, &its, &pending));
         st.iterations += its;
-        launch_axpy_from_f32(x, H->x32, rnorm, N, H->stream);
+        // x += rnorm d (x unset on the first refinement from a zero initial guess)
+        launch_refine_update(x, H->x_unset, H->x32, H->x32_unset, H->p32, pending, H->scal, rnorm, N,
+                             H->stream);
+        H->x_unset = false;
         launch_apply<double>(geo<double>(H, F), F.rho, F.m, x, b, H->r, 3, red(H, OP_STORE, S_RR),
                              H->stream);
         CHK(check_launch());
@@ -1296,8 +1306,9 @@ int hp_solve(hp_handle* H, const double* b, double* x, double tol) {
         st.rel_residual = std::sqrt(H->host_scal[S_RR]) / bnorm;
         rc = HP_OK;
     } else {
-        // only FP64 MG-PCG and Jacobi-PCG take an unset (zero) split iterate; the others get zeros
-        if (H->x_unset && (H->mode == HP_MODE_MIXED_IR || H->mode == HP_MODE_LEARNED)) {
+        // FP64 MG-PCG, Jacobi-PCG and mixed precision take an unset (zero) split iterate; the
+        // learned form gets zeros
+        if (H->x_unset && H->mode == HP_MODE_LEARNED) {
             launch_fill<double>(x, 0.0, N, s);
             H->x_unset = false;
         }

@@ -536,6 +536,27 @@ def test_dot_within_the_summation_bound(n):
     assert abs(got - ref) <= bound, (got, ref, bound)
 
 
+@pytest.mark.parametrize("n", [(1 << 21) - 5, 1 << 21])
+def test_dot_with_more_partials_than_one_pass_of_the_second_stage(n):
+    """Vectors of 2^21 entries give 2048 first-stage partials, more than the second stage loads in
+    its first pass (four per thread of one workgroup): the strided remainder is summed too, within
+    the summation bound of math.fsum, and reproducibly."""
+    import math
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n) * np.exp(rng.uniform(-4, 4, n))
+    y = rng.standard_normal(n)
+    ref = math.fsum((x * y).tolist())
+    bound = n * 2.0 ** -53 * float(np.sum(np.abs(x * y)))
+    p = problem((128, 128, 128), 0.001)
+    with make(p) as s:
+        xt, yt = dev(x), dev(y)
+        got = s.dot(xt, yt)
+        assert got == s.dot(xt, yt)
+    assert abs(got - ref) <= bound, (got, ref, bound)
+    # a partial sum of only the first half of the products is far outside that bound
+    assert abs(math.fsum((x[: n // 2] * y[: n // 2]).tolist()) - ref) > 100 * bound
+
+
 def test_dot_exact_cancellation():
     """x = (h, h), y = (h, -h): the exact dot product is 0; the GPU result stays within the
     summation bound of it."""
