@@ -2150,8 +2150,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict_red(Transfer t, ZTiles zt, 
     const int nri = w + 8 < NR ? 3 : 2;
     const int hl = wrapi(2 * Ic - 1, nfx) >> 1, hr = wrapi(2 * Ic + 2, nfx) >> 1;
     const bool edge_l = (lane == 0) || (Ic == 0), edge_r = (lane == 63) || (Ic == t.ncx - 1);
-    // red entries at half position Ic of this wave's rows of one fine plane and, at a wave edge,
-    // the red outer neighbour (cell 2I-1 is red where the row parity is 1, cell 2I+2 where it is 0)
+    // red entries at half position Ic of this wave's rows of one fine plane and the red outer
+    // neighbour that a wave edge needs (cell 2I-1 is red where the row parity is 1, cell 2I+2
+    // where it is 0). Every lane issues every load (valid rows and columns; what a lane does not
+    // need it ignores): with loads under a branch the compiler cannot count what is in flight, and
+    // waited for the next plane's loads before using the current ones.
     struct Raw {
         T c[3], e[3];
     };
@@ -2159,14 +2162,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict_red(Transfer t, ZTiles zt, 
         const T* base = fine + (int64_t)k * sf;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            o.c[i] = T(0);
-            o.e[i] = T(0);
-            if (i < nri) {
-                const T* rp = base + (int64_t)jr[i] * nfx;
-                const int pf = (jr[i] + k) & 1;
-                o.c[i] = rp[Ic];
-                o.e[i] = (pf ? edge_l : edge_r) ? rp[pf ? hl : hr] : T(0);
-            }
+            const T* rp = base + (int64_t)jr[i] * nfx;
+            const int pf = (jr[i] + k) & 1;
+            o.c[i] = rp[Ic];
+            o.e[i] = rp[pf ? hl : hr];
         }
     };
     // x-y weighted sum of fine plane k from the entries in cur; loads plane kn into nxt
@@ -2212,7 +2211,9 @@ __global__ __launch_bounds__(kBlock) void k_restrict_red(Transfer t, ZTiles zt, 
 template <typename T>
 void launch_restrict(const Transfer& t, const T* fine, T* coarse, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
-        ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64, 2);
+        // the red-only restriction from 256^3 and up marches chunks of eight coarse planes (1024
+        // workgroups at 256^3, resident at once; four-plane chunks take two rounds of workgroups)
+        ZTiles zt = ztiles(t.ncx, t.ncy, t.ncz, 64, (red_only && t.ncz >= 128) ? 8 : 2);
         zt.rev = t.rev;
         const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlock);
         // a split coarse level always has a split fine level above it
@@ -2427,9 +2428,11 @@ __global__ __launch_bounds__(kBlock) void k_prolong_red(Transfer t, ZTiles zt, c
     struct Raw {
         T c, e;
     };
+    // (unconditional loads, as in k_restrict_red: lanes without an edge column load their own
+    // entry again and ignore it)
     auto load_raw = [&](int K, Raw& o) {
         o.c = cv(min(I, ncx - 1), Jw, K);
-        o.e = edge >= 0 ? cv(edge, Jw, K) : T(0);
+        o.e = cv(edge >= 0 ? edge : min(I, ncx - 1), Jw, K);
     };
     T mlo, mhi, clo, chi;
     vmem(zm(k0 >> 1), mlo, mhi);
