@@ -2438,16 +2438,17 @@ __global__ __launch_bounds__(kBlock) void k_prolong_red(Transfer t, ZTiles zt, c
     vmem(zm(k0 >> 1), mlo, mhi);
     vmem(k0 >> 1, clo, chi);
     // fine planes k, k+1 of coarse plane K = k/2: the lower one takes the plane below (m), the
-    // upper one the plane above (n, from the entries loaded a pair earlier)
-    auto pstep = [&](int k, const Raw& rn, Raw& rnn, const T& z0, const T& z1, T& z0n, T& z1n) {
+    // upper one the plane above (n, from the entries loaded two pairs earlier: the loads of the
+    // pair after next are in flight while a pair is computed, a ring of three)
+    auto pstep = [&](int k, const Raw& rn, Raw& rn2, const T& z0, const T& z1, T& z0n2, T& z1n2) {
         const int K = k >> 1;
         const int sl = K & 1;
         ce[sl][w][lane + 1] = rn.c;
         if (edge >= 0) ce[sl][w][lane == 0 ? 0 : 65] = rn.e;
         __syncthreads();
-        load_raw(zp(min(K + 1, ncz - 1)), rnn);
-        z0n = *zat(min(k + 2, k1 - 1));
-        z1n = *zat(min(k + 3, k1 - 1));
+        load_raw(zp(min(K + 2, ncz - 1)), rn2);
+        z0n2 = *zat(min(k + 4, k1 - 1));
+        z1n2 = *zat(min(k + 5, k1 - 1));
         const T cy = T(0.75) * ce[sl][rJ][lc] + T(0.25) * ce[sl][rJ2][lc];
         const T cl = T(0.75) * ce[sl][rJ][ll] + T(0.25) * ce[sl][rJ2][ll];
         const T cr = T(0.75) * ce[sl][rJ][lr] + T(0.25) * ce[sl][rJ2][lr];
@@ -2466,21 +2467,37 @@ __global__ __launch_bounds__(kBlock) void k_prolong_red(Transfer t, ZTiles zt, c
         clo = nlo;
         chi = nhi;
     };
-    Raw A, B;
-    T za0, za1, zb0, zb1;
-    load_raw(zp(k0 >> 1), A);
-    za0 = *zat(k0);
-    za1 = *zat(min(k0 + 1, k1 - 1));
-    for (int k = k0; k < k1; k += 4) {
-        pstep(k, A, B, za0, za1, zb0, zb1);
-        if (k + 2 < k1) pstep(k + 2, B, A, zb0, zb1, za0, za1);
+    // a ring of four pairs; the main loop takes four pairs with no condition between them (a pair
+    // under a branch leaves the compiler unsure which loads are in flight, and it then waits for
+    // the prefetched ones too), the tail the last fewer than four
+    Raw R0, R1, R2, R3;
+    T a0, a1, b0, b1, c0, c1, d0, d1;
+    load_raw(zp(k0 >> 1), R0);
+    load_raw(zp(min((k0 >> 1) + 1, ncz - 1)), R1);
+    a0 = *zat(k0);
+    a1 = *zat(min(k0 + 1, k1 - 1));
+    b0 = *zat(min(k0 + 2, k1 - 1));
+    b1 = *zat(min(k0 + 3, k1 - 1));
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        pstep(k, R0, R2, a0, a1, c0, c1);
+        pstep(k + 2, R1, R3, b0, b1, d0, d1);
+        pstep(k + 4, R2, R0, c0, c1, a0, a1);
+        pstep(k + 6, R3, R1, d0, d1, b0, b1);
     }
+    if (k < k1) pstep(k, R0, R2, a0, a1, c0, c1);
+    if (k + 2 < k1) pstep(k + 2, R1, R3, b0, b1, d0, d1);
+    if (k + 4 < k1) pstep(k + 4, R2, R0, c0, c1, a0, a1);
 }
 
 template <typename T>
 void launch_prolong_add(const Transfer& t, const T* coarse, T* fine, hipStream_t s, bool red_only) {
     if (transfer_zm(t)) {
-        ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64, 2);
+        // the red-only prolongation holds four plane pairs in flight (86 VGPRs, five waves per
+        // SIMD): chunks of 32 fine planes at 256^3 and of 4 at 128^3 keep its workgroups (1024)
+        // resident at once
+        const int kmin = !red_only ? 2 : (t.nfz >= 256 ? 32 : (t.nfz >= 128 ? 4 : 2));
+        ZTiles zt = ztiles(t.ncx, t.nfy, t.nfz, 64, kmin);
         zt.rev = t.rev;
         zt.kz += zt.kz & 1;  // chunks start on even fine planes
         zt.tz = (t.nfz + zt.kz - 1) / zt.kz;
