@@ -145,9 +145,12 @@ __device__ __forceinline__ void load_line(const HGeo& g, const RhsArgs& A, const
 
 // One thread per (x, y) column walking kHZ planes: the x and y neighbours come from memory (the
 // x ones from the same cache lines), the z neighbours of the six stencil arrays from a ring of
-// registers (each plane is loaded once per column).
-// TC: the two-component terms (temp_n, conc_n, rkc_n given).
-template <bool TC>
+// registers (each plane is loaded once per column). Every load of a plane is issued whatever the
+// geometry (a missing neighbour, or an axis of one cell, reads the cell itself and contributes
+// nothing): with loads under branches the compiler cannot count what is in flight and waited
+// for the next plane's z loads before using this plane's values.
+// TC: the two-component terms (temp_n, conc_n, rkc_n given); VISC: the viscous term (visc given).
+template <bool TC, bool VISC>
 __global__ __launch_bounds__(256) void k_pressure_rhs(HGeo g, HTiles t, RhsArgs A) {
     int i, j, k0;
     htile(t, i, j, k0);
@@ -170,30 +173,27 @@ __global__ __launch_bounds__(256) void k_pressure_rhs(HGeo g, HTiles t, RhsArgs 
         Z.c[q] = tc ? A.conc_n[a] : 0.0;
         Z.k[q] = tc ? A.rkc_n[a] : 0.0;
     };
-    int tz;
-    if (neighbour(g, 2, k0, -1, &tz)) load_plane(tz, 0);
+    int tz = k0;
+    load_plane(neighbour(g, 2, k0, -1, &tz) ? tz : k0, 0);
     load_plane(k0, 1);
     for (int k = k0; k < k1; ++k) {
         Z.lo = nz > 1 && neighbour(g, 2, k, -1, &tz);
+        tz = k;
         Z.hi = nz > 1 && neighbour(g, 2, k, 1, &tz);
-        if (Z.hi) load_plane(tz, 2);
+        load_plane(tz, 2);
         const int64_t a = col + (int64_t)k * sxy;
         const double irn = 1.0 / Z.rn[1];
         const double m = irn / A.c2_n[a];
         double adv = 0.0, divu = 0.0, dc = 0.0;
-        if (g.n[0] > 1) {
-            Line L;
-            load_line(g, A, A.mom_star, 0, i, a, 1, tc, Z, L);
-            rhs_axis(L, A.mom_n[a] * irn, ih[0], tc, adv, divu, dc);
-        }
-        if (g.n[1] > 1) {
-            Line L;
-            load_line(g, A, A.mom_star + A.N, 1, j, a, g.n[0], tc, Z, L);
-            rhs_axis(L, A.mom_n[A.N + a] * irn, ih[1], tc, adv, divu, dc);
-        }
-        if (nz > 1) rhs_axis(Z, A.mom_n[2 * A.N + a] * irn, ih[2], tc, adv, divu, dc);
+        // (an axis of one cell has no faces: its lines contribute exact zeros)
+        Line L;
+        load_line(g, A, A.mom_star, 0, i, a, 1, tc, Z, L);
+        rhs_axis(L, A.mom_n[a] * irn, ih[0], tc, adv, divu, dc);
+        load_line(g, A, A.mom_star + A.N, 1, j, a, g.n[0], tc, Z, L);
+        rhs_axis(L, A.mom_n[A.N + a] * irn, ih[1], tc, adv, divu, dc);
+        rhs_axis(Z, A.mom_n[2 * A.N + a] * irn, ih[2], tc, adv, divu, dc);
         double b = m * (Z.p[1] - g.dt * adv) - g.dt * divu;
-        if (A.visc) b -= (2.0 * g.dt / 3.0) * (m * irn) * A.visc[a];
+        if constexpr (VISC) b -= (2.0 * g.dt / 3.0) * (m * irn) * A.visc[a];
         if (tc) b -= (3.0 * g.dt / 4.0) * m * A.r_gas * A.temp_n[a] * dc;
         A.b[a] = b;
         // the ring moves up one plane
@@ -244,19 +244,22 @@ __global__ __launch_bounds__(256) void k_pressure_update(HGeo g, HTiles t, UpdAr
         zr[q] = A.rho_np1[a];
         zm[q] = msz[a];
     };
-    int tz;
-    if (neighbour(g, 2, k0, -1, &tz)) load_plane(tz, 0);
+    // (unconditional loads, as in k_pressure_rhs: an axis of one cell has no faces and its
+    // terms are exact zeros)
+    int tz = k0;
+    load_plane(neighbour(g, 2, k0, -1, &tz) ? tz : k0, 0);
     load_plane(k0, 1);
     for (int k = k0; k < k1; ++k) {
         const bool zlo = nz > 1 && neighbour(g, 2, k, -1, &tz);
+        tz = k;
         const bool zhi = nz > 1 && neighbour(g, 2, k, 1, &tz);
-        if (zhi) load_plane(tz, 2);
+        load_plane(tz, 2);
         const int64_t a = col + (int64_t)k * sxy;
         const int c[2] = {i, j};
         const int64_t st[2] = {1, g.n[0]};
         double gp[3] = {0.0, 0.0, 0.0}, uf[3] = {0.0, 0.0, 0.0}, divn = 0.0;
+#pragma unroll
         for (int d = 0; d < 2; ++d) {
-            if (g.n[d] == 1) continue;
             int tl, th;
             const bool lo = neighbour(g, d, c[d], -1, &tl), hi = neighbour(g, d, c[d], 1, &th);
             const int64_t bl = lo ? a + (int64_t)(tl - c[d]) * st[d] : a;
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(256) void k_pressure_update(HGeo g, HTiles t, UpdAr
             const double mv[3] = {ms[bl], ms[a], ms[bh]};
             gp[d] = upd_axis(lo, hi, pv, rv, mv, g.dt, ih[d], uf[d], divn);
         }
-        if (nz > 1) gp[2] = upd_axis(zlo, zhi, zp, zr, zm, g.dt, ih[2], uf[2], divn);
+        gp[2] = upd_axis(zlo, zhi, zp, zr, zm, g.dt, ih[2], uf[2], divn);
         // step (vii): momentum; step (ix): e^{n+1} = e* - dt (P div u^{n+1} + u^{n+1} . grad P)
         const double ir = 1.0 / zr[1];
         double ug = 0.0;
@@ -398,10 +401,14 @@ int hydro_launch_rhs(const int n[3], const int bc[3], const double h[3], double 
               f->rkc_n, f->r_gas, (int64_t)n[0] * n[1] * n[2], rhs};
     const HTiles t = htiles(n);
     const dim3 grid((unsigned)t.tx * t.ty * t.tz);
-    if (f->temp_n)
-        hipLaunchKernelGGL(k_pressure_rhs<true>, grid, dim3(256), 0, s, g, t, A);
+    if (f->temp_n && f->visc)
+        hipLaunchKernelGGL((k_pressure_rhs<true, true>), grid, dim3(256), 0, s, g, t, A);
+    else if (f->temp_n)
+        hipLaunchKernelGGL((k_pressure_rhs<true, false>), grid, dim3(256), 0, s, g, t, A);
+    else if (f->visc)
+        hipLaunchKernelGGL((k_pressure_rhs<false, true>), grid, dim3(256), 0, s, g, t, A);
     else
-        hipLaunchKernelGGL(k_pressure_rhs<false>, grid, dim3(256), 0, s, g, t, A);
+        hipLaunchKernelGGL((k_pressure_rhs<false, false>), grid, dim3(256), 0, s, g, t, A);
     return hipGetLastError() == hipSuccess ? HP_OK : HP_EHIP;
 }
 
