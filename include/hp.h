@@ -366,7 +366,7 @@ int hp_stream_copy(const double* src, double* dst, long long n, void* stream);
  * concatenations, ReLU, 1x1x1 output head) in bfloat16 on the matrix cores with FP32
  * accumulation. Its input per cell is (b/s, log rho, log c2, p_prev/s) with s = RMS(b); its
  * output y gives the estimate x = s * out_scale * y of the solution of A x = b. Not part of the
- * paper's method: it stands beside the multigrid solver, which remains the judge of accuracy.
+ * paper's method: it stands beside the multigrid solver, which decides accuracy.
  *
  * Parameters: one flat FP32 device vector of hp_nn_num_params() entries; per convolution
  * W[o][t][c] (c fastest) then bias[o], in the order in->16, 16->16, 16->32, 32->32, 32->64,
