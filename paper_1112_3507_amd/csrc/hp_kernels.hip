@@ -335,17 +335,25 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, Geo<float
     int k = blockIdx.z * blockDim.z + threadIdx.z;
     if (i >= g.nx || j >= g.ny || k >= g.nz) return;
     int a = i + g.nx * (j + g.ny * k);
-    double ra = rho[a];
-    double d = m[a];
+    const double ra = rho[a], ma = m[a];
+    double d = ma;
+    double rn[6];  // the face neighbours' rho, in the order of for_faces
+    int f = 0;
     for_faces(g, i, j, k, a, [&](int nb, double c) {
-        d += c * (g.frule ? face_kappa<1>(ra, rho[nb]) : face_kappa<0>(ra, rho[nb]));
+        const double rb = rho[nb];
+        rn[f++] = rb;
+        d += c * (g.frule ? face_kappa<1>(ra, rb) : face_kappa<0>(ra, rb));
     });
     dinv[a] = 1.0 / d;
     if (dinv32) {
-        float ra32 = rho32[a];
-        float d32 = m32[a];
+        // the FP32 copies are the FP64 values rounded to nearest, so the FP32 diagonal takes
+        // them from the FP64 loads (rho32 and m32 are not read again)
+        const float ra32 = (float)ra;
+        float d32 = (float)ma;
+        f = 0;
         for_faces(g32, i, j, k, a, [&](int nb, float c) {
-            d32 += c * (g32.frule ? face_kappa<1>(ra32, rho32[nb]) : face_kappa<0>(ra32, rho32[nb]));
+            const float rb32 = (float)rn[f++];
+            d32 += c * (g32.frule ? face_kappa<1>(ra32, rb32) : face_kappa<0>(ra32, rb32));
         });
         dinv32[a] = 1.0f / d32;
     }

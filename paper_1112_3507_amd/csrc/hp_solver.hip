@@ -307,7 +307,9 @@ void relayout_l(hp_handle* H, int l, const T* src, T* dst, int to_split) {
 
 // Bring the coefficient arrays to the natural (0) or split (1) layout: the finest level and,
 // below it, every level that allows it as long as the level above is split. The relayout goes
-// through the CG scratch vectors p and p32.
+// through the CG scratch vectors p and p32; on the finest level (arrays of the same size) the
+// relaid copy then takes the array's place and the old array becomes the scratch vector (the
+// natural rho and m, kept for the network's features, keep their old arrays): no copy back.
 int set_layout(hp_handle* H, int split) {
     LevelData& F = H->lv[0];
     if (F.split == split) return HP_OK;
@@ -320,10 +322,6 @@ int set_layout(hp_handle* H, int split) {
             (rc = dalloc(H, &H->rho_nat, N)) || (rc = dalloc(H, &H->m_nat, N)))
             return rc;
     }
-    if (split) {
-        HIPCHK(hipMemcpyAsync(H->rho_nat, F.rho, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(H->m_nat, F.m, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
     for (size_t l = 0; l < H->lv.size(); ++l) {
         LevelData& L = H->lv[l];
         const int want = split && (l == 0 || (H->lv[l - 1].split && split_allowed_below(H, l)));
@@ -331,13 +329,37 @@ int set_layout(hp_handle* H, int split) {
             if (!want) break;
             continue;
         }
-        for (double* a : {L.rho, L.m, L.dinv}) {
-            relayout_l<double>(H, (int)l, a, H->p, want);
-            launch_copy<double>(H->p, a, L.N, s);
-        }
-        for (float* a : {L.rho32, L.m32, L.dinv32}) {
-            relayout_l<float>(H, (int)l, a, H->p32, want);
-            launch_copy<float>(H->p32, a, L.N, s);
+        if (l == 0) {
+            // rho and m: to split, the natural array becomes rho_nat / m_nat and the old copy
+            // there the scratch vector; back to natural, the arrays trade places with the scratch
+            double** keep[2] = {&H->rho_nat, &H->m_nat};
+            double** arr[2] = {&L.rho, &L.m};
+            for (int q = 0; q < 2; ++q) {
+                relayout_l<double>(H, 0, *arr[q], H->p, want);
+                double* relaid = H->p;
+                if (want) {
+                    H->p = *keep[q];
+                    *keep[q] = *arr[q];
+                } else {
+                    H->p = *arr[q];
+                }
+                *arr[q] = relaid;
+            }
+            relayout_l<double>(H, 0, L.dinv, H->p, want);
+            std::swap(L.dinv, H->p);
+            for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
+                relayout_l<float>(H, 0, *a, H->p32, want);
+                std::swap(*a, H->p32);
+            }
+        } else {
+            for (double* a : {L.rho, L.m, L.dinv}) {
+                relayout_l<double>(H, (int)l, a, H->p, want);
+                launch_copy<double>(H->p, a, L.N, s);
+            }
+            for (float* a : {L.rho32, L.m32, L.dinv32}) {
+                relayout_l<float>(H, (int)l, a, H->p32, want);
+                launch_copy<float>(H->p32, a, L.N, s);
+            }
         }
         L.split = want;
     }
