@@ -121,8 +121,8 @@ typedef struct {
  *            reuse them on return.
  *   dt       time step (> 0).
  * Validates sizes (n >= 1, h > 0, periodic n even or 1), rho, c2 > 0 and finite. Allocates all
- * device workspace (hp_solve allocates nothing), builds the multigrid hierarchy and factorises
- * the coarsest operator in FP64 on the host. On success *out receives the handle.
+ * device workspace (hp_solve allocates nothing), builds the multigrid hierarchy, and assembles
+ * and inverts the coarsest operator in FP64 on the device. On success *out receives the handle.
  */
 int hp_setup(const hp_grid* grid, const double* rho, const double* c2, double dt,
              const hp_bc* bc, hp_handle** out);
@@ -147,7 +147,7 @@ int hp_set_option(hp_handle* h, int key, double value);
 int hp_get_option(const hp_handle* h, int key, double* value);
 
 /*
- * Replace rho, c2 and dt (same grid): re-derives every level and the coarsest factor without
+ * Replace rho, c2 and dt (same grid): re-derives every level and the coarsest inverse without
  * reallocating. Same validation as hp_setup.
  */
 int hp_update_coefficients(hp_handle* h, const double* rho, const double* c2, double dt);

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SOURCES = ["csrc/hp_kernels.hip", "csrc/hp_solver.hip", "csrc/hp_nn.hip", "csrc/hp_noalloc.hip", "csrc/hp_hydro.hip",
-           "csrc/hp_fcg.hip"]
+           "csrc/hp_fcg.hip", "csrc/hp_coarse.hip"]
 LIB = os.path.join(PKG, "libhp.so")
 ARCH = "gfx950"
 

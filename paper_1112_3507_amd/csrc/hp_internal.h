@@ -147,9 +147,13 @@ void launch_relayout(const T* src, T* dst, int nx, int ny, int nz, int to_split,
 bool split_layout_ok(int nx, int ny, int nz, const Transfer* t);
 template <typename T>
 void launch_coarse_solve(const double* ainv, int nc, const T* b, T* x, hipStream_t s);
-// In-place inverse of the dense SPD n x n matrix a (row-major) by Gauss-Jordan steps ping-ponged
-// through work (n x n); the matrix must be put in a for even n and in work for odd n (the
-// result always ends in a); *flag is set on a pivot that is not positive.
+// Dense coarsest operator (N x N row-major, N = n[0] n[1] n[2]) from the level's rho and m: the
+// seven-point flux-form matrix with face weights cd[d] * kappa (per[d]: axis d periodic).
+void launch_coarse_assemble(const double* rho, const double* m, const int n[3], const int per[3],
+                            const double cd[3], int face_rule, double* A, hipStream_t s);
+// In-place inverse of the dense SPD n x n matrix a (row-major) by blocked Gauss-Jordan steps;
+// work holds spd_inverse_work(n) doubles; *flag is set on a pivot that is not positive and finite.
+int64_t spd_inverse_work(int n);
 void launch_spd_inverse(double* a, double* work, int n, int* flag, hipStream_t s);
 
 // Deterministic dot <x, y> accumulated in FP64.

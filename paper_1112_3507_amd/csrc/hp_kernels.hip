@@ -2613,45 +2613,6 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(const double* __restric
     if (row < nc && lane == 0) x[row] = (T)acc;
 }
 
-// Inverse of the dense SPD coarsest operator by Gauss-Jordan elimination without pivoting (the
-// pivots of an SPD matrix are positive), one launch per step, out of place (in -> out): row k is
-// divided by its pivot, every other row loses its multiple of row k, and column k takes the
-// negated multipliers (1/pivot on the diagonal); after steps 0 .. n-1 the array holds the
-// inverse. A pivot that is not positive and finite sets *flag.
-__global__ __launch_bounds__(kBlock) void k_gj_step(const double* __restrict__ in, double* __restrict__ out,
-                                                    int n, int k, int* __restrict__ flag) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= (int64_t)n * n) return;
-    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-    const double piv = in[(int64_t)k * n + k];
-    if (i == k) {
-        out[e] = (j == k) ? 1.0 / piv : in[e] / piv;
-        if (j == k && !(piv > 0.0 && piv < INFINITY)) *flag = 1;
-        return;
-    }
-    const double f = in[(int64_t)i * n + k] / piv;
-    out[e] = (j == k) ? -f : in[e] - f * in[(int64_t)k * n + j];
-}
-
-// x = (x + x^T) / 2 in place (one thread per pair i < j)
-__global__ __launch_bounds__(kBlock) void k_symmetrize(double* __restrict__ x, int n) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= (int64_t)n * n) return;
-    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-    if (i >= j) return;
-    const double v = 0.5 * (x[(int64_t)i * n + j] + x[(int64_t)j * n + i]);
-    x[(int64_t)i * n + j] = v;
-    x[(int64_t)j * n + i] = v;
-}
-
-void launch_spd_inverse(double* a, double* work, int n, int* flag, hipStream_t s) {
-    const unsigned blocks = (unsigned)(((int64_t)n * n + kBlock - 1) / kBlock);
-    double* buf[2] = {(n % 2 == 0) ? a : work, (n % 2 == 0) ? work : a};
-    for (int k = 0; k < n; ++k)
-        hipLaunchKernelGGL(k_gj_step, dim3(blocks), dim3(kBlock), 0, s, buf[k & 1], buf[(k + 1) & 1], n, k, flag);
-    hipLaunchKernelGGL(k_symmetrize, dim3(blocks), dim3(kBlock), 0, s, a, n);
-}
-
 template <typename T>
 void launch_coarse_solve(const double* ainv, int nc, const T* b, T* x, hipStream_t s) {
     int blocks = (nc + (kBlock / 64) - 1) / (kBlock / 64);

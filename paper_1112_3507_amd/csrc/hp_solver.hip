@@ -74,7 +74,7 @@ struct hp_handle {
     std::vector<LevelData> lv;
     int nc = 0;
     double* ainv = nullptr;       // inverse of the coarsest operator (nc x nc)
-    double* ainv_work = nullptr;  // the Gauss-Jordan sweep's second buffer
+    double* ainv_work = nullptr;  // workspace of the blocked Gauss-Jordan inverse
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double* r2 = nullptr;  // second residual array: the fused residual update writes r' there
     // the split iterate of the running solve is zero and has not been written yet (a zero initial
@@ -229,49 +229,20 @@ void time_end(hp_handle* H) {
     }
 }
 
-// ---- coarsest level: dense FP64 operator, Cholesky, symmetric inverse (host) ----
+// ---- coarsest level: dense FP64 operator and its inverse, both built on the device ----
 
 int build_coarse_inverse(hp_handle* H) {
     LevelData& C = H->lv.back();
     const int n = (int)C.N;
-    std::vector<double> rho(n), m(n);
-    HIPCHK(hipMemcpyAsync(rho.data(), C.rho, n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
-    HIPCHK(hipMemcpyAsync(m.data(), C.m, n * sizeof(double), hipMemcpyDeviceToHost, H->stream));
-    HIPCHK(hipStreamSynchronize(H->stream));
-    std::vector<double> A((size_t)n * n, 0.0);
-    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
     const int per[3] = {H->bc.x == HP_BC_PERIODIC, H->bc.y == HP_BC_PERIODIC,
                         H->bc.z == HP_BC_PERIODIC};
     const double dt2 = H->dt * H->dt;
-    for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                int a = i + nx * (j + ny * k);
-                A[(size_t)a * n + a] += m[a];
-                int c[3] = {i, j, k};
-                for (int d = 0; d < 3; ++d)
-                    for (int s = -1; s <= 1; s += 2) {
-                        int cc[3] = {c[0], c[1], c[2]};
-                        int t = cc[d] + s;
-                        if (t < 0 || t >= C.n[d]) {
-                            if (!per[d] || C.n[d] < 2) continue;
-                            t = (t + C.n[d]) % C.n[d];
-                        }
-                        cc[d] = t;
-                        int b = cc[0] + nx * (cc[1] + ny * cc[2]);
-                        const double kappa = H->face_rule == 1 ? 0.5 * (1.0 / rho[a] + 1.0 / rho[b])
-                                                               : 2.0 / (rho[a] + rho[b]);
-                        double w = dt2 / (C.h[d] * C.h[d]) * kappa;
-                        A[(size_t)a * n + a] += w;
-                        A[(size_t)a * n + b] -= w;
-                    }
-            }
-    // inverse on the device: the operator goes where the Gauss-Jordan sweep starts (so that the
-    // inverse ends in ainv), a non-positive pivot means the operator is not positive definite
-    double* start = (n % 2 == 0) ? H->ainv : H->ainv_work;
-    HIPCHK(hipMemcpyAsync(start, A.data(), (size_t)n * n * sizeof(double), hipMemcpyHostToDevice, H->stream));
+    double cd[3];
+    for (int d = 0; d < 3; ++d) cd[d] = dt2 / (C.h[d] * C.h[d]);
+    // a pivot that is not positive means the operator is not positive definite
     *H->host_flag = 0;
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
+    launch_coarse_assemble(C.rho, C.m, C.n, per, cd, H->face_rule, H->ainv, H->stream);
     launch_spd_inverse(H->ainv, H->ainv_work, n, H->flag, H->stream);
     CHK(check_launch());
     HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
@@ -1099,7 +1070,7 @@ int hp_setup_two_density(const hp_grid* grid, const double* rho_n, const double*
         }
     }
     if ((rc = dalloc(H, &H->ainv, (int64_t)H->nc * H->nc)) ||
-        (rc = dalloc(H, &H->ainv_work, (int64_t)H->nc * H->nc)))
+        (rc = dalloc(H, &H->ainv_work, spd_inverse_work(H->nc))))
         return bail(rc);
     if ((rc = dalloc(H, &H->r, N)) || (rc = dalloc(H, &H->z, N)) || (rc = dalloc(H, &H->p, N)) ||
         (rc = dalloc(H, &H->q, N)) || (rc = dalloc(H, &H->r2, N)))

@@ -188,6 +188,23 @@ def test_coarse_solve_and_vcycle_parity(f32, layout, grid):
         assert relerr(host(z), mg.vcycle(lv, r)) <= (1e-4 if f32 else 1e-9)
 
 
+# coarsest levels of 8 cells (less than one 32-wide elimination block), 240 (a ragged last
+# block) and 3332 (14 x 14 x 17: odd sizes stop the coarsening above the usual 512; 104 full
+# blocks and a ragged one)
+@pytest.mark.parametrize("grid,nc", [((2, 2, 2), 8), ((10, 6, 4), 240), ((28, 28, 17), 3332)])
+def test_coarse_solve_parity_across_coarsest_sizes(grid, nc):
+    p = problem(grid, 0.01)
+    Lc = _hier(p)[-1]
+    assert int(np.prod(Lc.shape)) == nc
+    rng = np.random.default_rng(5)
+    with make(p) as s:
+        assert s.get_option(hp.OPT_COARSEST_MAX) == 512
+        b = rng.standard_normal(Lc.shape)
+        x = torch.empty(Lc.shape, dtype=torch.float64, device=DEV)
+        s.coarse_solve(dev(b), x)
+        assert relerr(host(x), mg.coarse_solve(Lc, b)) <= 1e-10
+
+
 # ------------------------------------------------------------------ full solves
 
 @pytest.mark.parametrize("mach,rhs_seed", [(0.001, 2), (0.01, 3)])
