@@ -359,13 +359,6 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, Geo<float
     }
 }
 
-void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const double* rho,
-                        const double* m, const float* rho32, const float* m32, double* dinv,
-                        float* dinv32, hipStream_t s) {
-    Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
-    hipLaunchKernelGGL(k_jacobi_diag, sh.grid, sh.block, 0, s, g, g32, rho, m, rho32, m32, dinv, dinv32);
-}
-
 // ------------------------------------------------------------------------------------------
 // operator apply / residual
 
@@ -567,6 +560,82 @@ __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
         }
     }
     if (MODE == 1 || MODE == 3) block_partial(part, partials);
+}
+
+// Inverse diagonals of the large natural-order levels by a z march: the same values as
+// k_jacobi_diag (faces summed in the same order from the same operands), with each rho plane of a
+// column loaded once per chunk and the loads of plane k+1 in flight while plane k is computed
+// (one thread per cell reads the two z-neighbour planes again, from other workgroups' tiles).
+template <int FR>
+__global__ __launch_bounds__(kBlock) void k_jacobi_diag_zm(Geo<double> g, Geo<float> g32, ZTiles zt,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ m,
+                                                           double* __restrict__ dinv,
+                                                           float* __restrict__ dinv32) {
+    int bx, by, bz;
+    ztile(zt, bx, by, bz);
+    const int i = bx * 64 + (threadIdx.x & 63);
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const int k0 = bz * zt.kz;
+    const int k1 = min(k0 + zt.kz, g.nz);
+    const int sz = g.nx * g.ny;
+    if (i >= g.nx || j >= g.ny) return;
+    const FaceTab<double> ft(g, i, j);
+    const FaceTab<float> ft32(g32, i, j);
+    const int col = i + g.nx * j;
+    int a = col + k0 * sz;
+    bool hm, hp;
+    const int om = zoff(k0, -1, g.nz, g.pz, sz, hm);
+    const int op = zoff(k0, 1, g.nz, g.pz, sz, hp);
+    // rho of the cell and of its z neighbours (the cell itself where a face is absent, with
+    // factor 0, as in for_faces)
+    double rc = rho[a], rm = rho[a + om], rn = rho[a + op], mv = m[a];
+    double czm = hm ? g.cz : 0.0, czp = hp ? g.cz : 0.0;
+    float czm32 = hm ? g32.cz : 0.0f, czp32 = hp ? g32.cz : 0.0f;
+    double rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rv[q] = rho[a + ft.o[q]];
+    for (int k = k0; k < k1; ++k) {
+        // plane k+1 (clamped to the chunk) and the column above it
+        const int kn = min(k + 1, k1 - 1);
+        const int an = col + kn * sz;
+        bool hpn;
+        const int opn = zoff(kn, 1, g.nz, g.pz, sz, hpn);
+        double rvn[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rvn[q] = rho[an + ft.o[q]];
+        const double mvn = m[an];
+        const double rnn = rho[an + opn];
+        // plane k: faces x-, x+, y-, y+, z-, z+
+        double d = mv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d += ft.c[q] * face_kappa<FR>(rc, rv[q]);
+        d += czm * face_kappa<FR>(rc, rm);
+        d += czp * face_kappa<FR>(rc, rn);
+        dinv[a] = 1.0 / d;
+        if (dinv32) {
+            // the FP32 copies are the FP64 values rounded to nearest
+            const float rc32 = (float)rc;
+            float d32 = (float)mv;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d32 += ft32.c[q] * face_kappa<FR>(rc32, (float)rv[q]);
+            d32 += czm32 * face_kappa<FR>(rc32, (float)rm);
+            d32 += czp32 * face_kappa<FR>(rc32, (float)rn);
+            dinv32[a] = 1.0f / d32;
+        }
+        // advance: the z+ face of plane k is the z- face of plane k+1
+        rm = rc;
+        rc = rn;
+        rn = rnn;
+        mv = mvn;
+        czm = czp;
+        czm32 = czp32;
+        czp = hpn ? g.cz : 0.0;
+        czp32 = hpn ? g32.cz : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rv[q] = rvn[q];
+        a = an;
+    }
 }
 
 // Cell pairs (i0, i0 + 1), i0 even, loaded and stored as one 2-vector; needs nx even and
@@ -1455,6 +1524,20 @@ int launch_presmooth_update(const Geo<T>& g, const T* rho, const T* dinv, const 
 }
 
 static bool use_zm(int nx, int ny, int nz) { return nx >= 64 && ny >= 4 && nz >= 8; }
+
+void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const double* rho,
+                        const double* m, const float* rho32, const float* m32, double* dinv,
+                        float* dinv32, hipStream_t s) {
+    if (use_zm(g.nx, g.ny, g.nz)) {
+        const ZTiles zt = ztiles(g.nx, g.ny, g.nz, 64);
+        const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlock);
+        WITH_FACE_RULE(g.frule, hipLaunchKernelGGL((k_jacobi_diag_zm<FRV>), grid, block, 0, s, g, g32, zt,
+                                                   rho, m, dinv, dinv32));
+        return;
+    }
+    Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
+    hipLaunchKernelGGL(k_jacobi_diag, sh.grid, sh.block, 0, s, g, g32, rho, m, rho32, m32, dinv, dinv32);
+}
 // largest workgroup count of the reducing z-march launches of a level (one partial per group):
 // cells (x width 64), cell pairs (width 128) and the split layout (64 half positions)
 static int64_t zm_blocks(int nx, int ny, int nz) {
@@ -2446,8 +2529,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong_red(Transfer t, ZTiles zt, c
     vmem(zm(k0 >> 1), mlo, mhi);
     vmem(k0 >> 1, clo, chi);
     // fine planes k, k+1 of coarse plane K = k/2: the lower one takes the plane below (m), the
-    // upper one the plane above (n, from the entries loaded two pairs earlier: the loads of the
-    // pair after next are in flight while a pair is computed, a ring of three)
+    // upper one the plane above (n, from the entries loaded two pairs earlier: each pair issues
+    // the loads of the pair after next before it computes)
     auto pstep = [&](int k, const Raw& rn, Raw& rn2, const T& z0, const T& z1, T& z0n2, T& z1n2) {
         const int K = k >> 1;
         const int sl = K & 1;

@@ -99,9 +99,12 @@ struct hp_handle {
     double* host_part = nullptr;
     double* dev_part = nullptr;   // the device's address of host_part
     int host_nparts = 0;          // how many partials the last r -= alpha q wrote
-    int* host_flag = nullptr;     // pinned
+    int* host_flag = nullptr;     // pinned; [0] input checks, [1] coarsest pivots
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t ev_scal = nullptr;  // marks the copy of scal into host_scal
+    // the coarsest inverse runs on a stream of its own, beside the finest level's relayout
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     unsigned dir = 0;              // traversal direction of the last finest-level pass
     std::vector<void*> allocs;
     // options
@@ -231,7 +234,11 @@ void time_end(hp_handle* H) {
 
 // ---- coarsest level: dense FP64 operator and its inverse, both built on the device ----
 
-int build_coarse_inverse(hp_handle* H) {
+// Enqueue the coarsest operator's assembly and inverse on the side stream, behind the work
+// enqueued so far on the handle's stream (which wrote the coarsest rho and m). A pivot that is
+// not positive (the operator is not positive definite) sets host_flag[1] once the handle's stream
+// has waited for the side stream (join_coarse_inverse) and been synchronised.
+int start_coarse_inverse(hp_handle* H) {
     LevelData& C = H->lv.back();
     const int n = (int)C.N;
     const int per[3] = {H->bc.x == HP_BC_PERIODIC, H->bc.y == HP_BC_PERIODIC,
@@ -239,15 +246,30 @@ int build_coarse_inverse(hp_handle* H) {
     const double dt2 = H->dt * H->dt;
     double cd[3];
     for (int d = 0; d < 3; ++d) cd[d] = dt2 / (C.h[d] * C.h[d]);
-    // a pivot that is not positive means the operator is not positive definite
-    *H->host_flag = 0;
-    HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
-    launch_coarse_assemble(C.rho, C.m, C.n, per, cd, H->face_rule, H->ainv, H->stream);
-    launch_spd_inverse(H->ainv, H->ainv_work, n, H->flag, H->stream);
+    H->host_flag[1] = 0;
+    HIPCHK(hipEventRecord(H->ev_fork, H->stream));
+    HIPCHK(hipStreamWaitEvent(H->side, H->ev_fork, 0));
+    HIPCHK(hipMemsetAsync(H->flag + 1, 0, sizeof(int), H->side));
+    launch_coarse_assemble(C.rho, C.m, C.n, per, cd, H->face_rule, H->ainv, H->side);
+    launch_spd_inverse(H->ainv, H->ainv_work, n, H->flag + 1, H->side);
     CHK(check_launch());
-    HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipMemcpyAsync(H->host_flag + 1, H->flag + 1, sizeof(int), hipMemcpyDeviceToHost, H->side));
+    HIPCHK(hipEventRecord(H->ev_join, H->side));
+    return HP_OK;
+}
+
+// Work enqueued on the handle's stream after this call sees the coarsest inverse.
+int join_coarse_inverse(hp_handle* H) {
+    HIPCHK(hipStreamWaitEvent(H->stream, H->ev_join, 0));
+    return HP_OK;
+}
+
+// The coarsest inverse on its own (the caller waits for it).
+int build_coarse_inverse(hp_handle* H) {
+    CHK(start_coarse_inverse(H));
+    CHK(join_coarse_inverse(H));
     HIPCHK(hipStreamSynchronize(H->stream));
-    if (*H->host_flag) return fail(HP_EDOMAIN, "coarsest operator is not positive definite");
+    if (H->host_flag[1]) return fail(HP_EDOMAIN, "coarsest operator is not positive definite");
     return HP_OK;
 }
 
@@ -359,13 +381,14 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
     H->dt = dt;
     LevelData& F = H->lv[0];
     for (auto& L : H->lv) L.split = 0;  // every array below is recomputed in natural order
-    *H->host_flag = 0;
+    H->host_flag[0] = 0;
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
     launch_setup_coef(rho_mass, rho_face, c2, F.rho, F.m, F.rho32, F.m32, F.N, H->flag, H->stream);
     CHK(check_launch());
     HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
-    HIPCHK(hipStreamSynchronize(H->stream));
-    if (*H->host_flag) return fail(HP_EDOMAIN, "rho and c2 must be positive and finite in every cell");
+    // The input check is read once everything below has run: with an invalid cell the steps
+    // below compute non-finite values (no index or trip count depends on a value) and the call
+    // fails at the end, leaving the coefficients undefined as before.
     for (size_t l = 0; l + 1 < H->lv.size(); ++l) {
         LevelData& C = H->lv[l + 1];
         launch_coarsen_coef(transfer(H, (int)l), H->lv[l].rho, H->lv[l].m, C.rho, C.m, C.rho32,
@@ -376,8 +399,14 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
         launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
                            L.dinv32, H->stream);
     CHK(check_launch());
-    CHK(build_coarse_inverse(H));
-    return H->want_split ? set_layout(H, 1) : HP_OK;
+    // the coarsest inverse overlaps the relayout to the split storage order
+    CHK(start_coarse_inverse(H));
+    const int rc = H->want_split ? set_layout(H, 1) : HP_OK;
+    CHK(join_coarse_inverse(H));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    if (H->host_flag[0]) return fail(HP_EDOMAIN, "rho and c2 must be positive and finite in every cell");
+    if (H->host_flag[1]) return fail(HP_EDOMAIN, "coarsest operator is not positive definite");
+    return rc;
 }
 
 // ---- V-cycle ----
@@ -1085,18 +1114,22 @@ int hp_setup_two_density(const hp_grid* grid, const double* rho_n, const double*
     H->partial_cap = cap;
     if ((rc = dalloc(H, &H->partials, cap)) || (rc = dalloc(H, &H->partials2, cap)) ||
         (rc = dalloc(H, &H->scal, S_COUNT)) ||
-        (rc = dalloc(H, &H->flag, 1)))
+        (rc = dalloc(H, &H->flag, 2)))
         return bail(rc);
     if (hipHostMalloc((void**)&H->host_scal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&H->host_part, (cap + 1) * sizeof(double),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-        hipHostMalloc((void**)&H->host_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&H->host_flag, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(HP_ENOMEM, "pinned host allocation failed"));
     if (hipHostGetDevicePointer((void**)&H->dev_part, H->host_part, 0) != hipSuccess)
         return bail(fail(HP_EHIP, "hipHostGetDevicePointer failed"));
     if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess ||
-        hipEventCreateWithFlags(&H->ev_scal, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&H->ev_scal, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&H->ev_join, hipEventDisableTiming) != hipSuccess)
         return bail(fail(HP_EHIP, "hipEventCreate failed"));
+    if (hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(HP_EHIP, "hipStreamCreateWithFlags failed"));
     if (hipMemsetAsync(H->scal, 0, S_COUNT * sizeof(double), H->stream) != hipSuccess)
         return bail(fail(HP_EHIP, "hipMemsetAsync failed"));
     H->want_split = split_allowed(H) ? 1 : 0;
@@ -1117,6 +1150,12 @@ void hp_free(hp_handle* H) {
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
     if (H->ev_scal) (void)hipEventDestroy(H->ev_scal);
+    if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+    if (H->ev_join) (void)hipEventDestroy(H->ev_join);
+    if (H->side) {
+        (void)hipStreamSynchronize(H->side);
+        (void)hipStreamDestroy(H->side);
+    }
     for (hipEvent_t e : H->tev) (void)hipEventDestroy(e);
     delete H;
 }
