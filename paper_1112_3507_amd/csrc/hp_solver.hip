@@ -300,15 +300,15 @@ void relayout_l(hp_handle* H, int l, const T* src, T* dst, int to_split) {
 
 // Bring the coefficient arrays to the natural (0) or split (1) layout: the finest level and,
 // below it, every level that allows it as long as the level above is split. The relayout goes
-// through the CG scratch vectors p and p32; on the finest level (arrays of the same size) the
-// relaid copy then takes the array's place and the old array becomes the scratch vector (the
-// natural rho and m, kept for the network's features, keep their old arrays): no copy back.
+// through a scratch array of the level's size (the CG vectors p and p32 on the finest level, the
+// level's residual scratch t and t32 below it); the relaid copy then takes the array's place and
+// the old array becomes the scratch (on the finest level the natural rho and m, kept for the
+// network's features, keep their old arrays): no copy back.
 int set_layout(hp_handle* H, int split) {
     LevelData& F = H->lv[0];
     if (F.split == split) return HP_OK;
     if (split && !split_allowed(H)) return fail(HP_EINVAL, "the grid does not allow the split layout");
     const int64_t N = F.N;
-    hipStream_t s = H->stream;
     if (split && !H->bs) {
         int rc;
         if ((rc = dalloc(H, &H->bs, N)) || (rc = dalloc(H, &H->xs, N)) ||
@@ -345,13 +345,15 @@ int set_layout(hp_handle* H, int split) {
                 std::swap(*a, H->p32);
             }
         } else {
-            for (double* a : {L.rho, L.m, L.dinv}) {
-                relayout_l<double>(H, (int)l, a, H->p, want);
-                launch_copy<double>(H->p, a, L.N, s);
+            // through the level's residual scratch t / t32 (its size, contents never kept between
+            // V-cycles): the relaid copy takes the array's place, the old array becomes t
+            for (double** a : {&L.rho, &L.m, &L.dinv}) {
+                relayout_l<double>(H, (int)l, *a, L.t, want);
+                std::swap(*a, L.t);
             }
-            for (float* a : {L.rho32, L.m32, L.dinv32}) {
-                relayout_l<float>(H, (int)l, a, H->p32, want);
-                launch_copy<float>(H->p32, a, L.N, s);
+            for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
+                relayout_l<float>(H, (int)l, *a, L.t32, want);
+                std::swap(*a, L.t32);
             }
         }
         L.split = want;
@@ -395,12 +397,13 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
                             C.m32, H->stream);
         CHK(check_launch());
     }
+    // the coarsest inverse (it needs only the coarsest rho and m) overlaps the Jacobi diagonals
+    // and the relayout to the split storage order
+    CHK(start_coarse_inverse(H));
     for (auto& L : H->lv)
         launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
                            L.dinv32, H->stream);
     CHK(check_launch());
-    // the coarsest inverse overlaps the relayout to the split storage order
-    CHK(start_coarse_inverse(H));
     const int rc = H->want_split ? set_layout(H, 1) : HP_OK;
     CHK(join_coarse_inverse(H));
     HIPCHK(hipStreamSynchronize(H->stream));
