@@ -90,10 +90,11 @@ void launch_neumann_rhs(int nx, int ny, int nz, int d, int side, double coef, co
                         hipStream_t s);
 void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m_f,
                          double* rho_c, double* m_c, float* rho32_c, float* m32_c, hipStream_t s);
-// dinv = 1 / (m + sum of face weights) in FP64 and (if dinv32) FP32
+// dinv = 1 / (m + sum of face weights) in FP64 and (if dinv32) FP32, from natural-order rho and m;
+// written in natural order, or in the red-black split order with split_out
 void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const double* rho,
                         const double* m, const float* rho32, const float* m32, double* dinv,
-                        float* dinv32, hipStream_t s);
+                        float* dinv32, bool split_out, hipStream_t s);
 
 // y = A x (mode 0), y = A x with <x, y> reduced (mode 1), y = b - A x (mode 2),
 // y = b - A x with <y, y> reduced (mode 3).

@@ -321,15 +321,22 @@ void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m
                        rho32_c, m32_c);
 }
 
+// position of cell (i, j, k) in the red-black split order: colour c = (i + j + k) & 1 at half
+// position c nx/2 + i/2 of its row
+__device__ __forceinline__ int split_index(int i, int j, int k, int nx, int ny) {
+    return (j + ny * k) * nx + (((i + j + k) & 1) ? (nx >> 1) : 0) + (i >> 1);
+}
+
 // inverse diagonal 1 / (m_a + sum_f w_f) in FP64, and its FP32 counterpart computed from the
-// FP32 coefficient copies (so each precision's smoother uses its own operator's diagonal)
+// FP32 coefficient copies (so each precision's smoother uses its own operator's diagonal); the
+// inputs are in natural order, the outputs in natural or (split) in split order
 __global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, Geo<float> g32,
                                                         const double* __restrict__ rho,
                                                         const double* __restrict__ m,
                                                         const float* __restrict__ rho32,
                                                         const float* __restrict__ m32,
                                                         double* __restrict__ dinv,
-                                                        float* __restrict__ dinv32) {
+                                                        float* __restrict__ dinv32, int split) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y * blockDim.y + threadIdx.y;
     int k = blockIdx.z * blockDim.z + threadIdx.z;
@@ -344,7 +351,8 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, Geo<float
         rn[f++] = rb;
         d += c * (g.frule ? face_kappa<1>(ra, rb) : face_kappa<0>(ra, rb));
     });
-    dinv[a] = 1.0 / d;
+    const int ao = split ? split_index(i, j, k, g.nx, g.ny) : a;
+    dinv[ao] = 1.0 / d;
     if (dinv32) {
         // the FP32 copies are the FP64 values rounded to nearest, so the FP32 diagonal takes
         // them from the FP64 loads (rho32 and m32 are not read again)
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(Geo<double> g, Geo<float
             const float rb32 = (float)rn[f++];
             d32 += c * (g32.frule ? face_kappa<1>(ra32, rb32) : face_kappa<0>(ra32, rb32));
         });
-        dinv32[a] = 1.0f / d32;
+        dinv32[ao] = 1.0f / d32;
     }
 }
 
@@ -562,11 +570,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_zm(Geo<T> g, ZTiles zt,
     if (MODE == 1 || MODE == 3) block_partial(part, partials);
 }
 
-// Inverse diagonals of the large natural-order levels by a z march: the same values as
-// k_jacobi_diag (faces summed in the same order from the same operands), with each rho plane of a
-// column loaded once per chunk and the loads of plane k+1 in flight while plane k is computed
-// (one thread per cell reads the two z-neighbour planes again, from other workgroups' tiles).
-template <int FR>
+// Inverse diagonals of the large levels by a z march: the same values as k_jacobi_diag (faces
+// summed in the same order from the same operands), with each rho plane of a column loaded once
+// per chunk and the loads of plane k+1 in flight while plane k is computed (one thread per cell
+// reads the two z-neighbour planes again, from other workgroups' tiles). Natural-order inputs;
+// SPLIT writes the outputs in split order (a wave's 64 cells of a row go to two runs of 32).
+template <int FR, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_jacobi_diag_zm(Geo<double> g, Geo<float> g32, ZTiles zt,
                                                            const double* __restrict__ rho,
                                                            const double* __restrict__ m,
@@ -612,7 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag_zm(Geo<double> g, Geo<fl
         for (int q = 0; q < 4; ++q) d += ft.c[q] * face_kappa<FR>(rc, rv[q]);
         d += czm * face_kappa<FR>(rc, rm);
         d += czp * face_kappa<FR>(rc, rn);
-        dinv[a] = 1.0 / d;
+        const int ao = SPLIT ? split_index(i, j, k, g.nx, g.ny) : a;
+        dinv[ao] = 1.0 / d;
         if (dinv32) {
             // the FP32 copies are the FP64 values rounded to nearest
             const float rc32 = (float)rc;
@@ -621,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag_zm(Geo<double> g, Geo<fl
             for (int q = 0; q < 4; ++q) d32 += ft32.c[q] * face_kappa<FR>(rc32, (float)rv[q]);
             d32 += czm32 * face_kappa<FR>(rc32, (float)rm);
             d32 += czp32 * face_kappa<FR>(rc32, (float)rn);
-            dinv32[a] = 1.0f / d32;
+            dinv32[ao] = 1.0f / d32;
         }
         // advance: the z+ face of plane k is the z- face of plane k+1
         rm = rc;
@@ -1527,16 +1537,21 @@ static bool use_zm(int nx, int ny, int nz) { return nx >= 64 && ny >= 4 && nz >=
 
 void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const double* rho,
                         const double* m, const float* rho32, const float* m32, double* dinv,
-                        float* dinv32, hipStream_t s) {
+                        float* dinv32, bool split_out, hipStream_t s) {
     if (use_zm(g.nx, g.ny, g.nz)) {
         const ZTiles zt = ztiles(g.nx, g.ny, g.nz, 64);
         const dim3 grid(zt.tx * zt.ty * zt.tz), block(kBlock);
-        WITH_FACE_RULE(g.frule, hipLaunchKernelGGL((k_jacobi_diag_zm<FRV>), grid, block, 0, s, g, g32, zt,
-                                                   rho, m, dinv, dinv32));
+        if (split_out)
+            WITH_FACE_RULE(g.frule, hipLaunchKernelGGL((k_jacobi_diag_zm<FRV, true>), grid, block, 0, s, g,
+                                                       g32, zt, rho, m, dinv, dinv32));
+        else
+            WITH_FACE_RULE(g.frule, hipLaunchKernelGGL((k_jacobi_diag_zm<FRV, false>), grid, block, 0, s, g,
+                                                       g32, zt, rho, m, dinv, dinv32));
         return;
     }
     Shape3 sh = cells_shape(g.nx, g.ny, g.nz);
-    hipLaunchKernelGGL(k_jacobi_diag, sh.grid, sh.block, 0, s, g, g32, rho, m, rho32, m32, dinv, dinv32);
+    hipLaunchKernelGGL(k_jacobi_diag, sh.grid, sh.block, 0, s, g, g32, rho, m, rho32, m32, dinv, dinv32,
+                       split_out ? 1 : 0);
 }
 // largest workgroup count of the reducing z-march launches of a level (one partial per group):
 // cells (x width 64), cell pairs (width 128) and the split layout (64 half positions)

@@ -292,6 +292,15 @@ bool split_allowed_below(const hp_handle* H, size_t l) {
     return L.n[0] / 2 >= 32 && split_layout_ok(L.n[0], L.n[1], L.n[2], &t);
 }
 
+// Whether level l is in split order under the split layout: the finest level where the grid
+// allows it, and below it each level that allows it while the level above is split.
+bool split_target(const hp_handle* H, size_t l) {
+    if (!split_allowed(H)) return false;
+    for (size_t q = 1; q <= l; ++q)
+        if (!split_allowed_below(H, q)) return false;
+    return true;
+}
+
 template <typename T>
 void relayout_l(hp_handle* H, int l, const T* src, T* dst, int to_split) {
     const LevelData& L = H->lv[l];
@@ -303,8 +312,9 @@ void relayout_l(hp_handle* H, int l, const T* src, T* dst, int to_split) {
 // through a scratch array of the level's size (the CG vectors p and p32 on the finest level, the
 // level's residual scratch t and t32 below it); the relaid copy then takes the array's place and
 // the old array becomes the scratch (on the finest level the natural rho and m, kept for the
-// network's features, keep their old arrays): no copy back.
-int set_layout(hp_handle* H, int split) {
+// network's features, keep their old arrays): no copy back. dinv_split: the Jacobi diagonals of
+// the levels that become split are in split order already (everything else in natural order).
+int set_layout(hp_handle* H, int split, bool dinv_split = false) {
     LevelData& F = H->lv[0];
     if (F.split == split) return HP_OK;
     if (split && !split_allowed(H)) return fail(HP_EINVAL, "the grid does not allow the split layout");
@@ -317,7 +327,7 @@ int set_layout(hp_handle* H, int split) {
     }
     for (size_t l = 0; l < H->lv.size(); ++l) {
         LevelData& L = H->lv[l];
-        const int want = split && (l == 0 || (H->lv[l - 1].split && split_allowed_below(H, l)));
+        const int want = split && split_target(H, l);
         if (L.split == want) {
             if (!want) break;
             continue;
@@ -338,9 +348,12 @@ int set_layout(hp_handle* H, int split) {
                 }
                 *arr[q] = relaid;
             }
-            relayout_l<double>(H, 0, L.dinv, H->p, want);
-            std::swap(L.dinv, H->p);
+            if (!dinv_split) {
+                relayout_l<double>(H, 0, L.dinv, H->p, want);
+                std::swap(L.dinv, H->p);
+            }
             for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
+                if (dinv_split && a == &L.dinv32) continue;
                 relayout_l<float>(H, 0, *a, H->p32, want);
                 std::swap(*a, H->p32);
             }
@@ -348,10 +361,12 @@ int set_layout(hp_handle* H, int split) {
             // through the level's residual scratch t / t32 (its size, contents never kept between
             // V-cycles): the relaid copy takes the array's place, the old array becomes t
             for (double** a : {&L.rho, &L.m, &L.dinv}) {
+                if (dinv_split && a == &L.dinv) continue;
                 relayout_l<double>(H, (int)l, *a, L.t, want);
                 std::swap(*a, L.t);
             }
             for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
+                if (dinv_split && a == &L.dinv32) continue;
                 relayout_l<float>(H, (int)l, *a, L.t32, want);
                 std::swap(*a, L.t32);
             }
@@ -400,11 +415,15 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
     // the coarsest inverse (it needs only the coarsest rho and m) overlaps the Jacobi diagonals
     // and the relayout to the split storage order
     CHK(start_coarse_inverse(H));
-    for (auto& L : H->lv)
+    // the Jacobi diagonals of the levels that the split layout will reach are written in split
+    // order directly (set_layout then leaves them alone)
+    for (size_t l = 0; l < H->lv.size(); ++l) {
+        LevelData& L = H->lv[l];
         launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
-                           L.dinv32, H->stream);
+                           L.dinv32, H->want_split && split_target(H, l), H->stream);
+    }
     CHK(check_launch());
-    const int rc = H->want_split ? set_layout(H, 1) : HP_OK;
+    const int rc = H->want_split ? set_layout(H, 1, true) : HP_OK;
     CHK(join_coarse_inverse(H));
     HIPCHK(hipStreamSynchronize(H->stream));
     if (H->host_flag[0]) return fail(HP_EDOMAIN, "rho and c2 must be positive and finite in every cell");
@@ -1210,7 +1229,7 @@ int hp_set_option(hp_handle* H, int key, double v) {
             if (rc) return rc;
             for (auto& L : H->lv)
                 launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
-                                   L.dinv32, H->stream);
+                                   L.dinv32, false, H->stream);
             CHK(check_launch());
             CHK(build_coarse_inverse(H));
             return was_split ? set_layout(H, 1) : HP_OK;

@@ -11,7 +11,9 @@
   solve still meets the bar against the oracle.
 * Two pre- and post-smoothing sweeps: the V-cycle against the oracle's V(2,2) in both layouts
   (the pre-smoothing then takes the general residual kernel), and a full solve.
-* A solve on a non-default stream (hp_set_stream): bitwise the result on the default stream.
+* A solve on a non-default stream (hp_set_stream): bitwise the result on the default stream; the
+  same for a coefficient update followed by a solve (the update's coarsest inverse runs on the
+  library's own side stream, forked from and joined to the handle's stream).
 """
 import numpy as np
 import pytest
@@ -155,6 +157,31 @@ def test_solve_on_a_non_default_stream():
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
             s.set_stream(stream)
+            x2 = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+            st = s.solve(b, x2, tol=1e-10)
+        stream.synchronize()
+        out.append(host(x2))
+        s.set_stream(torch.cuda.current_stream())
+    assert st["converged"] and np.array_equal(out[0], out[1])
+
+
+def test_update_coefficients_on_a_non_default_stream():
+    p = wl.polytrope((256, 32, 32), 0.001, seed=1)
+    q = wl.polytrope((256, 32, 32), 0.001, seed=2)
+    b = dev(wl.rhs_white(p.n, 6))
+    rho_q, c2_q = dev(q.rho), dev(q.c2)
+    out = []
+    with hp.setup(p.n, p.h, p.bc, dev(p.rho), dev(p.c2), p.dt) as s:
+        s.update_coefficients(rho_q, c2_q, q.dt)
+        x = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
+        s.solve(b, x, tol=1e-10)
+        out.append(host(x))
+    with hp.setup(p.n, p.h, p.bc, dev(p.rho), dev(p.c2), p.dt) as s:
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            s.set_stream(stream)
+            s.update_coefficients(rho_q, c2_q, q.dt)
             x2 = torch.zeros(p.shape, dtype=torch.float64, device=DEV)
             st = s.solve(b, x2, tol=1e-10)
         stream.synchronize()
