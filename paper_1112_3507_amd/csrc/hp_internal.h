@@ -81,15 +81,20 @@ struct Transfer {
 // launch has happened yet.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();
-// m = 1 / (rho_mass c2), face density rho_face (flag bad if any input is <= 0 or not finite)
+// m = 1 / (rho_mass c2), face density rho_face (flag bad if any input is <= 0 or not finite), on
+// an nx x ny x nz grid in natural order; the FP32 copies in the red-black split order with split32
 void launch_setup_coef(const double* rho_mass, const double* rho_face, const double* c2, double* rho_out,
-                       double* m, float* rho32, float* m32, int64_t n, int* bad, hipStream_t s);
+                       double* m, float* rho32, float* m32, int nx, int ny, int nz, bool split32, int* bad,
+                       hipStream_t s);
 // b += dt^2 q / h_d on the cells next to boundary `side` of axis d, q the prescribed outward normal
 // flux per face (natural layout; coef = dt^2 / h_d)
 void launch_neumann_rhs(int nx, int ny, int nz, int d, int side, double coef, const double* q, double* b,
                         hipStream_t s);
+// coarse rho and m as the means over each coarse cell's children (natural order; the FP32 copies
+// in the red-black split order with split32)
 void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m_f,
-                         double* rho_c, double* m_c, float* rho32_c, float* m32_c, hipStream_t s);
+                         double* rho_c, double* m_c, float* rho32_c, float* m32_c, bool split32,
+                         hipStream_t s);
 // dinv = 1 / (m + sum of face weights) in FP64 and (if dinv32) FP32, from natural-order rho and m;
 // written in natural order, or in the red-black split order with split_out
 void launch_jacobi_diag(const Geo<double>& g, const Geo<float>& g32, const double* rho,

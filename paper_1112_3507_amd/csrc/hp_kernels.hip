@@ -221,17 +221,24 @@ __device__ __forceinline__ void for_faces(const Geo<T>& g, int i, int j, int k, 
 // ------------------------------------------------------------------------------------------
 // coefficient setup
 
+// position of cell (i, j, k) in the red-black split order: colour c = (i + j + k) & 1 at half
+// position c nx/2 + i/2 of its row
+__device__ __forceinline__ int split_index(int i, int j, int k, int nx, int ny) {
+    return (j + ny * k) * nx + (((i + j + k) & 1) ? (nx >> 1) : 0) + (i >> 1);
+}
+
 // m = 1 / (rho_mass c2) (the mass term with the density of time level n) and the face density
 // rho_face (time level n+1; the same array as rho_mass in the one-density form), with the
-// Lax-Milgram check that all three are positive and finite
+// Lax-Milgram check that all three are positive and finite. The FP32 copies go to natural or
+// (split32, nx even) split order.
 __global__ __launch_bounds__(kBlock) void k_setup_coef(const double* __restrict__ rho_mass,
                                                        const double* __restrict__ rho_face,
                                                        const double* __restrict__ c2,
                                                        double* __restrict__ rho_out,
                                                        double* __restrict__ m,
                                                        float* __restrict__ rho32,
-                                                       float* __restrict__ m32, int64_t n,
-                                                       int* bad) {
+                                                       float* __restrict__ m32, int64_t n, int nx,
+                                                       int ny, int split32, int* bad) {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
     double rm = rho_mass[a], rf = rho_face[a], c = c2[a];
@@ -245,15 +252,22 @@ __global__ __launch_bounds__(kBlock) void k_setup_coef(const double* __restrict_
     double mm = 1.0 / (rm * c);
     rho_out[a] = rf;
     m[a] = mm;
-    rho32[a] = (float)rf;
-    m32[a] = (float)mm;
+    int64_t a32 = a;
+    if (split32) {
+        const int64_t row = a / nx;
+        a32 = split_index((int)(a - row * nx), (int)(row % ny), (int)(row / ny), nx, ny);
+    }
+    rho32[a32] = (float)rf;
+    m32[a32] = (float)mm;
 }
 
 void launch_setup_coef(const double* rho_mass, const double* rho_face, const double* c2, double* rho_out,
-                       double* m, float* rho32, float* m32, int64_t n, int* bad, hipStream_t s) {
+                       double* m, float* rho32, float* m32, int nx, int ny, int nz, bool split32, int* bad,
+                       hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nz;
     int blocks = (int)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_setup_coef, dim3(blocks), dim3(kBlock), 0, s, rho_mass, rho_face, c2, rho_out, m,
-                       rho32, m32, n, bad);
+                       rho32, m32, n, nx, ny, split32 ? 1 : 0, bad);
 }
 
 // Inhomogeneous Neumann data on boundary `side` of axis d: b_a += coef q_f for the cell a next to
@@ -282,13 +296,14 @@ void launch_neumann_rhs(int nx, int ny, int nz, int d, int side, double coef, co
                        nx, ny, nz, d, side, coef, q, b);
 }
 
-// mean over the children of each coarse cell
+// mean over the children of each coarse cell (natural order; the FP32 copies in split order with
+// split32)
 __global__ __launch_bounds__(kBlock) void k_coarsen_coef(Transfer t, const double* __restrict__ rf,
                                                          const double* __restrict__ mf,
                                                          double* __restrict__ rc,
                                                          double* __restrict__ mc,
                                                          float* __restrict__ rc32,
-                                                         float* __restrict__ mc32) {
+                                                         float* __restrict__ mc32, int split32) {
     int I = blockIdx.x * blockDim.x + threadIdx.x;
     int J = blockIdx.y * blockDim.y + threadIdx.y;
     int K = blockIdx.z * blockDim.z + threadIdx.z;
@@ -310,21 +325,17 @@ __global__ __launch_bounds__(kBlock) void k_coarsen_coef(Transfer t, const doubl
     double inv = 1.0 / cnt;
     rc[c] = sr * inv;
     mc[c] = sm * inv;
-    rc32[c] = (float)(sr * inv);
-    mc32[c] = (float)(sm * inv);
+    const int64_t c32 = split32 ? split_index(I, J, K, t.ncx, t.ncy) : c;
+    rc32[c32] = (float)(sr * inv);
+    mc32[c32] = (float)(sm * inv);
 }
 
 void launch_coarsen_coef(const Transfer& t, const double* rho_f, const double* m_f,
-                         double* rho_c, double* m_c, float* rho32_c, float* m32_c, hipStream_t s) {
+                         double* rho_c, double* m_c, float* rho32_c, float* m32_c, bool split32,
+                         hipStream_t s) {
     Shape3 sh = cells_shape(t.ncx, t.ncy, t.ncz);
     hipLaunchKernelGGL(k_coarsen_coef, sh.grid, sh.block, 0, s, t, rho_f, m_f, rho_c, m_c,
-                       rho32_c, m32_c);
-}
-
-// position of cell (i, j, k) in the red-black split order: colour c = (i + j + k) & 1 at half
-// position c nx/2 + i/2 of its row
-__device__ __forceinline__ int split_index(int i, int j, int k, int nx, int ny) {
-    return (j + ny * k) * nx + (((i + j + k) & 1) ? (nx >> 1) : 0) + (i >> 1);
+                       rho32_c, m32_c, split32 ? 1 : 0);
 }
 
 // inverse diagonal 1 / (m_a + sum_f w_f) in FP64, and its FP32 counterpart computed from the

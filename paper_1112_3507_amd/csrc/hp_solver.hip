@@ -312,9 +312,10 @@ void relayout_l(hp_handle* H, int l, const T* src, T* dst, int to_split) {
 // through a scratch array of the level's size (the CG vectors p and p32 on the finest level, the
 // level's residual scratch t and t32 below it); the relaid copy then takes the array's place and
 // the old array becomes the scratch (on the finest level the natural rho and m, kept for the
-// network's features, keep their old arrays): no copy back. dinv_split: the Jacobi diagonals of
-// the levels that become split are in split order already (everything else in natural order).
-int set_layout(hp_handle* H, int split, bool dinv_split = false) {
+// network's features, keep their old arrays): no copy back. fresh: the levels that become split
+// hold dinv and the FP32 copies in split order already, rho and m in natural order (the state the
+// coefficient setup leaves).
+int set_layout(hp_handle* H, int split, bool fresh = false) {
     LevelData& F = H->lv[0];
     if (F.split == split) return HP_OK;
     if (split && !split_allowed(H)) return fail(HP_EINVAL, "the grid does not allow the split layout");
@@ -348,28 +349,27 @@ int set_layout(hp_handle* H, int split, bool dinv_split = false) {
                 }
                 *arr[q] = relaid;
             }
-            if (!dinv_split) {
+            if (!fresh) {
                 relayout_l<double>(H, 0, L.dinv, H->p, want);
                 std::swap(L.dinv, H->p);
-            }
-            for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
-                if (dinv_split && a == &L.dinv32) continue;
-                relayout_l<float>(H, 0, *a, H->p32, want);
-                std::swap(*a, H->p32);
+                for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
+                    relayout_l<float>(H, 0, *a, H->p32, want);
+                    std::swap(*a, H->p32);
+                }
             }
         } else {
             // through the level's residual scratch t / t32 (its size, contents never kept between
             // V-cycles): the relaid copy takes the array's place, the old array becomes t
             for (double** a : {&L.rho, &L.m, &L.dinv}) {
-                if (dinv_split && a == &L.dinv) continue;
+                if (fresh && a == &L.dinv) continue;
                 relayout_l<double>(H, (int)l, *a, L.t, want);
                 std::swap(*a, L.t);
             }
-            for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
-                if (dinv_split && a == &L.dinv32) continue;
-                relayout_l<float>(H, (int)l, *a, L.t32, want);
-                std::swap(*a, L.t32);
-            }
+            if (!fresh)
+                for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
+                    relayout_l<float>(H, (int)l, *a, L.t32, want);
+                    std::swap(*a, L.t32);
+                }
         }
         L.split = want;
     }
@@ -400,7 +400,10 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
     for (auto& L : H->lv) L.split = 0;  // every array below is recomputed in natural order
     H->host_flag[0] = 0;
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
-    launch_setup_coef(rho_mass, rho_face, c2, F.rho, F.m, F.rho32, F.m32, F.N, H->flag, H->stream);
+    // the FP32 copies and the Jacobi diagonals of the levels that the split layout will reach are
+    // written in split order directly (set_layout then leaves them alone)
+    launch_setup_coef(rho_mass, rho_face, c2, F.rho, F.m, F.rho32, F.m32, F.n[0], F.n[1], F.n[2],
+                      H->want_split && split_target(H, 0), H->flag, H->stream);
     CHK(check_launch());
     HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
     // The input check is read once everything below has run: with an invalid cell the steps
@@ -408,15 +411,13 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
     // fails at the end, leaving the coefficients undefined as before.
     for (size_t l = 0; l + 1 < H->lv.size(); ++l) {
         LevelData& C = H->lv[l + 1];
-        launch_coarsen_coef(transfer(H, (int)l), H->lv[l].rho, H->lv[l].m, C.rho, C.m, C.rho32,
-                            C.m32, H->stream);
+        launch_coarsen_coef(transfer(H, (int)l), H->lv[l].rho, H->lv[l].m, C.rho, C.m, C.rho32, C.m32,
+                            H->want_split && split_target(H, l + 1), H->stream);
         CHK(check_launch());
     }
     // the coarsest inverse (it needs only the coarsest rho and m) overlaps the Jacobi diagonals
     // and the relayout to the split storage order
     CHK(start_coarse_inverse(H));
-    // the Jacobi diagonals of the levels that the split layout will reach are written in split
-    // order directly (set_layout then leaves them alone)
     for (size_t l = 0; l < H->lv.size(); ++l) {
         LevelData& L = H->lv[l];
         launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
