@@ -66,7 +66,8 @@ void launch_coarse_assemble(const double* rho, const double* m, const int n[3], 
 // 0 .. K-1), the block row becomes A_Kj <- D A_Kj, every other block row loses its multiple
 // A_ij <- A_ij - A_iK A_Kj (old A_iK, new A_Kj), block column K takes A_iK <- -A_iK D, and the
 // diagonal block becomes D. After the last step the array holds the inverse. This is the
-// unblocked Gauss-Jordan sweep grouped by kGJ pivots: the same pivots, summed in another order.
+// unblocked Gauss-Jordan sweep grouped by kGJ pivots: the same pivots, with the products summed in
+// another order (and each pivot applied through its reciprocal).
 //
 // Two launches per step: k_gj_panel (one workgroup per block column) inverts A_KK in LDS by the
 // unblocked sweep, updates its tile of block row K and saves its rows of the old block column K
@@ -83,8 +84,8 @@ constexpr int kGJPer = kGJ * kGJ / kGJThreads;  // entries of a kGJ x kGJ tile p
 
 int64_t spd_inverse_work(int n) { return (int64_t)n * kGJ + kGJ * kGJ; }
 
-// 1/x from the hardware estimate and two Newton steps (within an ulp or so; inf and NaN pass
-// through, so a bad pivot still shows in the flag and the result)
+// 1/x from the hardware estimate and two Newton steps (within an ulp or so). A zero, infinite or
+// NaN pivot gives a result that is not finite; the pivot flag is taken from the pivot itself.
 __device__ __forceinline__ double rcp_nr(double x) {
     double r = __builtin_amdgcn_rcp(x);
     double e = __builtin_fma(-x, r, 1.0);
