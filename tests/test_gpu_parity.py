@@ -339,6 +339,36 @@ def test_update_coefficients_matches_fresh_setup():
     assert st["converged"] and relerr(host(x), xref) <= 1e-9
 
 
+# On 256 x 32 x 32 the split layout reaches levels 0, 1 and 2: an update rewrites arrays whose
+# buffers the previous layout change rotated, writes the FP32 copies and Jacobi diagonals of those
+# levels in split order directly and relays the rest; the solves must equal those of a fresh
+# handle on the same coefficients bit for bit (same kernels, same order), in FP64 and mixed
+# precision.
+@pytest.mark.parametrize("mode", [hp.MODE_FP64_MGPCG, hp.MODE_MIXED_IR])
+def test_update_on_split_levels_equals_fresh_setup(mode):
+    p1 = problem(DEEP, 0.001, seed=1)
+    p2 = problem(DEEP, 0.01, seed=2)
+    b = dev(wl.rhs_white(p2.n, 7))
+    out = []
+    with make(p1, mode) as s:
+        assert s.get_option(hp.OPT_LAYOUT) == 1
+        s.update_coefficients(dev(p2.rho), dev(p2.c2), p2.dt)
+        x = torch.zeros(p2.shape, dtype=torch.float64, device=DEV)
+        st1 = s.solve(b, x, tol=1e-10)
+        out.append(host(x))
+        # and once more, from the state the first update left
+        s.update_coefficients(dev(p2.rho), dev(p2.c2), p2.dt)
+        x = torch.zeros(p2.shape, dtype=torch.float64, device=DEV)
+        s.solve(b, x, tol=1e-10)
+        out.append(host(x))
+    with make(p2, mode) as s:
+        x = torch.zeros(p2.shape, dtype=torch.float64, device=DEV)
+        st2 = s.solve(b, x, tol=1e-10)
+        out.append(host(x))
+    assert st1["converged"] and st2["converged"] and st1["iterations"] == st2["iterations"]
+    assert np.array_equal(out[0], out[2]) and np.array_equal(out[1], out[2])
+
+
 @pytest.mark.parametrize("max_iter", [1, 2, 3])
 def test_capped_solves_from_zero_return_their_iterate(max_iter):
     """A solve from a zero guess stopped after 1-3 iterations (HP_ENOCONV) returns its last
