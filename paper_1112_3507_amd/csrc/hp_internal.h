@@ -82,10 +82,11 @@ struct Transfer {
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();
 // m = 1 / (rho_mass c2), face density rho_face (flag bad if any input is <= 0 or not finite), on
-// an nx x ny x nz grid in natural order; the FP32 copies in the red-black split order with split32
+// an nx x ny x nz grid, into rho_out and m in natural order; with split32 the FP32 copies go to
+// the red-black split order, and FP64 copies in that order into rho_split and m_split if given
 void launch_setup_coef(const double* rho_mass, const double* rho_face, const double* c2, double* rho_out,
-                       double* m, float* rho32, float* m32, int nx, int ny, int nz, bool split32, int* bad,
-                       hipStream_t s);
+                       double* m, double* rho_split, double* m_split, float* rho32, float* m32, int nx,
+                       int ny, int nz, bool split32, int* bad, hipStream_t s);
 // b += dt^2 q / h_d on the cells next to boundary `side` of axis d, q the prescribed outward normal
 // flux per face (natural layout; coef = dt^2 / h_d)
 void launch_neumann_rhs(int nx, int ny, int nz, int d, int side, double coef, const double* q, double* b,

@@ -229,13 +229,16 @@ __device__ __forceinline__ int split_index(int i, int j, int k, int nx, int ny) 
 
 // m = 1 / (rho_mass c2) (the mass term with the density of time level n) and the face density
 // rho_face (time level n+1; the same array as rho_mass in the one-density form), with the
-// Lax-Milgram check that all three are positive and finite. The FP32 copies go to natural or
-// (split32, nx even) split order.
+// Lax-Milgram check that all three are positive and finite. rho_out and m in natural order; with
+// split32 (nx even) the FP32 copies go to split order, and so do FP64 copies into rho_split and
+// m_split where those are given.
 __global__ __launch_bounds__(kBlock) void k_setup_coef(const double* __restrict__ rho_mass,
                                                        const double* __restrict__ rho_face,
                                                        const double* __restrict__ c2,
                                                        double* __restrict__ rho_out,
                                                        double* __restrict__ m,
+                                                       double* __restrict__ rho_split,
+                                                       double* __restrict__ m_split,
                                                        float* __restrict__ rho32,
                                                        float* __restrict__ m32, int64_t n, int nx,
                                                        int ny, int split32, int* bad) {
@@ -256,18 +259,22 @@ __global__ __launch_bounds__(kBlock) void k_setup_coef(const double* __restrict_
     if (split32) {
         const int64_t row = a / nx;
         a32 = split_index((int)(a - row * nx), (int)(row % ny), (int)(row / ny), nx, ny);
+        if (rho_split) {
+            rho_split[a32] = rf;
+            m_split[a32] = mm;
+        }
     }
     rho32[a32] = (float)rf;
     m32[a32] = (float)mm;
 }
 
 void launch_setup_coef(const double* rho_mass, const double* rho_face, const double* c2, double* rho_out,
-                       double* m, float* rho32, float* m32, int nx, int ny, int nz, bool split32, int* bad,
-                       hipStream_t s) {
+                       double* m, double* rho_split, double* m_split, float* rho32, float* m32, int nx,
+                       int ny, int nz, bool split32, int* bad, hipStream_t s) {
     const int64_t n = (int64_t)nx * ny * nz;
     int blocks = (int)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_setup_coef, dim3(blocks), dim3(kBlock), 0, s, rho_mass, rho_face, c2, rho_out, m,
-                       rho32, m32, n, nx, ny, split32 ? 1 : 0, bad);
+                       rho_split, m_split, rho32, m32, n, nx, ny, split32 ? 1 : 0, bad);
 }
 
 // Inhomogeneous Neumann data on boundary `side` of axis d: b_a += coef q_f for the cell a next to

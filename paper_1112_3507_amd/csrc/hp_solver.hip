@@ -307,25 +307,30 @@ void relayout_l(hp_handle* H, int l, const T* src, T* dst, int to_split) {
     launch_relayout<T>(src, dst, L.n[0], L.n[1], L.n[2], to_split, H->stream);
 }
 
+// The finest level's buffers of the split layout (rhs and iterate in split order, the natural rho
+// and m), allocated the first time that layout is wanted.
+int alloc_split_buffers(hp_handle* H) {
+    const int64_t N = H->lv[0].N;
+    int rc;
+    for (double** a : {&H->bs, &H->xs, &H->rho_nat, &H->m_nat})
+        if (!*a && (rc = dalloc(H, a, N))) return rc;
+    return HP_OK;
+}
+
 // Bring the coefficient arrays to the natural (0) or split (1) layout: the finest level and,
 // below it, every level that allows it as long as the level above is split. The relayout goes
 // through a scratch array of the level's size (the CG vectors p and p32 on the finest level, the
 // level's residual scratch t and t32 below it); the relaid copy then takes the array's place and
 // the old array becomes the scratch (on the finest level the natural rho and m, kept for the
-// network's features, keep their old arrays): no copy back. fresh: the levels that become split
-// hold dinv and the FP32 copies in split order already, rho and m in natural order (the state the
-// coefficient setup leaves).
+// network's features, keep their old arrays): no copy back. fresh: the state the coefficient
+// setup leaves, in which the levels that become split hold dinv and the FP32 copies in split order
+// already, and rho and m in natural order below the finest level; the finest level's rho and m are
+// in split order with their natural copies in rho_nat / m_nat, so it is left as it is.
 int set_layout(hp_handle* H, int split, bool fresh = false) {
     LevelData& F = H->lv[0];
     if (F.split == split) return HP_OK;
     if (split && !split_allowed(H)) return fail(HP_EINVAL, "the grid does not allow the split layout");
-    const int64_t N = F.N;
-    if (split && !H->bs) {
-        int rc;
-        if ((rc = dalloc(H, &H->bs, N)) || (rc = dalloc(H, &H->xs, N)) ||
-            (rc = dalloc(H, &H->rho_nat, N)) || (rc = dalloc(H, &H->m_nat, N)))
-            return rc;
-    }
+    if (split) CHK(alloc_split_buffers(H));
     for (size_t l = 0; l < H->lv.size(); ++l) {
         LevelData& L = H->lv[l];
         const int want = split && split_target(H, l);
@@ -333,7 +338,9 @@ int set_layout(hp_handle* H, int split, bool fresh = false) {
             if (!want) break;
             continue;
         }
-        if (l == 0) {
+        if (l == 0 && fresh) {
+            // the coefficient setup wrote everything in its final place
+        } else if (l == 0) {
             // rho and m: to split, the natural array becomes rho_nat / m_nat and the old copy
             // there the scratch vector; back to natural, the arrays trade places with the scratch
             double** keep[2] = {&H->rho_nat, &H->m_nat};
@@ -349,13 +356,11 @@ int set_layout(hp_handle* H, int split, bool fresh = false) {
                 }
                 *arr[q] = relaid;
             }
-            if (!fresh) {
-                relayout_l<double>(H, 0, L.dinv, H->p, want);
-                std::swap(L.dinv, H->p);
-                for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
-                    relayout_l<float>(H, 0, *a, H->p32, want);
-                    std::swap(*a, H->p32);
-                }
+            relayout_l<double>(H, 0, L.dinv, H->p, want);
+            std::swap(L.dinv, H->p);
+            for (float** a : {&L.rho32, &L.m32, &L.dinv32}) {
+                relayout_l<float>(H, 0, *a, H->p32, want);
+                std::swap(*a, H->p32);
             }
         } else {
             // through the level's residual scratch t / t32 (its size, contents never kept between
@@ -400,10 +405,16 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
     for (auto& L : H->lv) L.split = 0;  // every array below is recomputed in natural order
     H->host_flag[0] = 0;
     HIPCHK(hipMemsetAsync(H->flag, 0, sizeof(int), H->stream));
-    // the FP32 copies and the Jacobi diagonals of the levels that the split layout will reach are
-    // written in split order directly (set_layout then leaves them alone)
-    launch_setup_coef(rho_mass, rho_face, c2, F.rho, F.m, F.rho32, F.m32, F.n[0], F.n[1], F.n[2],
-                      H->want_split && split_target(H, 0), H->flag, H->stream);
+    // The FP32 copies and the Jacobi diagonals of the levels that the split layout will reach are
+    // written in split order directly (set_layout then leaves them alone); on a split finest level
+    // rho and m go to its arrays in split order as well and to rho_nat / m_nat in natural order
+    // (whose old contents are stale), which the coarsening and the diagonals below read.
+    const bool split0 = H->want_split && split_target(H, 0);
+    if (split0) CHK(alloc_split_buffers(H));
+    double* rho0 = split0 ? H->rho_nat : F.rho;
+    double* m0 = split0 ? H->m_nat : F.m;
+    launch_setup_coef(rho_mass, rho_face, c2, rho0, m0, split0 ? F.rho : nullptr, split0 ? F.m : nullptr,
+                      F.rho32, F.m32, F.n[0], F.n[1], F.n[2], split0, H->flag, H->stream);
     CHK(check_launch());
     HIPCHK(hipMemcpyAsync(H->host_flag, H->flag, sizeof(int), hipMemcpyDeviceToHost, H->stream));
     // The input check is read once everything below has run: with an invalid cell the steps
@@ -411,8 +422,8 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
     // fails at the end, leaving the coefficients undefined as before.
     for (size_t l = 0; l + 1 < H->lv.size(); ++l) {
         LevelData& C = H->lv[l + 1];
-        launch_coarsen_coef(transfer(H, (int)l), H->lv[l].rho, H->lv[l].m, C.rho, C.m, C.rho32, C.m32,
-                            H->want_split && split_target(H, l + 1), H->stream);
+        launch_coarsen_coef(transfer(H, (int)l), l == 0 ? rho0 : H->lv[l].rho, l == 0 ? m0 : H->lv[l].m,
+                            C.rho, C.m, C.rho32, C.m32, H->want_split && split_target(H, l + 1), H->stream);
         CHK(check_launch());
     }
     // the coarsest inverse (it needs only the coarsest rho and m) overlaps the Jacobi diagonals
@@ -420,8 +431,8 @@ int load_coefficients(hp_handle* H, const double* rho_mass, const double* rho_fa
     CHK(start_coarse_inverse(H));
     for (size_t l = 0; l < H->lv.size(); ++l) {
         LevelData& L = H->lv[l];
-        launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), L.rho, L.m, L.rho32, L.m32, L.dinv,
-                           L.dinv32, H->want_split && split_target(H, l), H->stream);
+        launch_jacobi_diag(geo<double>(H, L), geo<float>(H, L), l == 0 ? rho0 : L.rho, l == 0 ? m0 : L.m,
+                           L.rho32, L.m32, L.dinv, L.dinv32, H->want_split && split_target(H, l), H->stream);
     }
     CHK(check_launch());
     const int rc = H->want_split ? set_layout(H, 1, true) : HP_OK;
